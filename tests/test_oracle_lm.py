@@ -1,0 +1,217 @@
+"""Pins of the oracle's Levenberg-Marquardt inversion (Sect. 2, 4.2-4.4).
+
+* Table 2 transitions (golden fixture) on every row and boundary;
+* the damped solve against numpy.linalg.solve of (H + eps diag H) d = g, and
+  its SVD fallback against numpy.linalg.pinv with the same truncation;
+* chi^2 normalisation 1/(4L - F) of Eq. 1 with a reduced free set;
+* Fig. 6 semantics through the work counters;
+* the minimum reached: noiseless recovery, brute force over two free
+  parameters, and MINPACK's Levenberg-Marquardt (scipy least_squares) on the
+  same residual from the same start.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import least_squares
+
+import oracle
+import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def hmi():
+    s = wl.hmi_instrument()
+    return oracle.Instrument(s.lambda0_A, s.geff, s.fine_offset_mA, s.filter)
+
+
+def test_table2_transitions():
+    g = json.load(open(os.path.join(GOLD, "table2_eps.json")))
+    for row in g["decrease"]:
+        assert oracle.eps_decrease(row["eps_old"]) == pytest.approx(row["eps_new"], rel=1e-15), row
+    for row in g["increase"]:
+        assert oracle.eps_increase(row["eps_old"]) == pytest.approx(row["eps_new"], rel=1e-15), row
+
+
+def _random_normal_eq(rng, cond=1e6):
+    Q, _ = np.linalg.qr(rng.normal(size=(10, 10)))
+    ev = np.logspace(0, -np.log10(cond), 10)
+    D = np.diag(10.0 ** rng.uniform(-3, 5, 10))
+    H = D @ Q @ np.diag(ev) @ Q.T @ D
+    H = 0.5 * (H + H.T)
+    g = rng.normal(size=10) * np.sqrt(np.diag(H))
+    return H, g
+
+
+def test_solve_matches_damped_normal_equations():
+    rng = np.random.default_rng(0)
+    for eps in (1e-9, 1e-3, 1.0, 1e4):
+        H, g = _random_normal_eq(rng)
+        d, code = oracle.solve(H, g, eps)
+        assert code == 0
+        ref = np.linalg.solve(H + eps * np.diag(np.diag(H)), g)
+        np.testing.assert_allclose(d, ref, rtol=1e-8, atol=0)
+
+
+def test_solve_frozen_parameters():
+    rng = np.random.default_rng(1)
+    H, g = _random_normal_eq(rng)
+    H[4, :] = H[:, 4] = 0.0  # no leverage: frozen
+    mask = 0x3FF & ~(1 << 7)  # S0 held fixed by the caller
+    d, code = oracle.solve(H, g, 1e-2, mask)
+    assert d[4] == 0.0 and d[7] == 0.0
+    keep = [p for p in range(10) if p not in (4, 7)]
+    Hs = H[np.ix_(keep, keep)]
+    ref = np.linalg.solve(Hs + 1e-2 * np.diag(np.diag(Hs)), g[keep])
+    np.testing.assert_allclose(d[keep], ref, rtol=1e-8)
+
+
+def test_solve_svd_fallback():
+    """A singular equilibrated system with no damping: the Cholesky breaks
+    down and the pseudo-inverse with the 1e-12 truncation is used."""
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(10, 6))
+    H = A @ A.T  # rank 6
+    g = H @ rng.normal(size=10)  # consistent right-hand side
+    d, code = oracle.solve(H, g, 0.0)
+    assert code == 1
+    s = 1 / np.sqrt(np.diag(H))
+    C = s[:, None] * H * s[None, :]
+    w, V = np.linalg.eigh(C)
+    keep = np.abs(w) >= 1e-12 * np.abs(w).max()
+    y = V[:, keep] @ ((V[:, keep].T @ (s * g)) / w[keep])
+    np.testing.assert_allclose(d, s * y, rtol=1e-7, atol=1e-12 * np.abs(s * y).max())
+
+
+def test_project_symmetries():
+    M = np.array([-1200.0, 30.0, -20.0, 25.0, 1.0, -1.0, 0.0, -5.0, 9.0, 1.5])
+    P = oracle.project(M)
+    assert P[0] == 1200.0 and P[1] == pytest.approx(150.0) and P[2] == pytest.approx(160.0)
+    assert P[3] == 20.0 and P[4] == 5.0 and P[5] == 0.0 and P[6] == 1e-3
+    assert P[7] == -1.0 and P[8] == 5.0 and P[9] == 1.0
+    assert oracle.project([100, 400.0, 370.0, 0, 30, 0.1, 5, 0.3, 0.7, 0.5])[1] == pytest.approx(40.0)
+    assert oracle.project([100, 200.0, 0, 0, 30, 0.1, 5, 0.3, 0.7, 0.5])[1] == pytest.approx(160.0)
+    assert oracle.project([100, -30.0, 0, 0, 30, 0.1, 5, 0.3, 0.7, 0.5])[1] == pytest.approx(30.0)
+
+
+def _pixel(hmi, M, seed, sigma=1e-3):
+    S = oracle.forward(hmi, M)
+    rng = np.random.default_rng(seed)
+    return (S + rng.normal(0, sigma, S.shape)).astype(np.float32)
+
+
+def test_chi2_normalisation_and_initial_state(hmi):
+    M = wl.draw_params(1, 11)[0]
+    obs = _pixel(hmi, M, 11)
+    W = wl.weights(6, w=(0.5, 1.0, 1.0, 2.0))
+    mask = 0x3FF & ~(1 << 5) & ~(1 << 8)
+    r = oracle.lm_pixel(hmi, obs, W, M0=M, opts=oracle.Options(max_iter=0, free_mask=mask))
+    S = oracle.forward(hmi, M)
+    ref = np.sum(W.astype(np.float64) * (obs.astype(np.float64) - S) ** 2) / (24 - 8)
+    assert r["chi2"] == pytest.approx(ref, rel=1e-14)
+    assert r["iters"] == 0 and r["status"] == oracle.MAX_ITER
+    assert r["counters"]["derivs"] == 1 and r["counters"]["trials"] == 0
+
+
+def test_nonfinite_input(hmi):
+    obs = _pixel(hmi, wl.default_model(), 3)
+    obs[2, 3] = np.nan
+    r = oracle.lm_pixel(hmi, obs, wl.weights(6))
+    assert r["status"] == oracle.NONFINITE and r["iters"] == 0
+    assert np.all(np.isnan(r["params"])) and np.isnan(r["chi2"])
+
+
+def test_fig6_work_counters(hmi):
+    P = wl.draw_params(16, 12)
+    obs = (oracle.forward_batch(hmi, P) + wl.draw_noise(16, 6, 12)).astype(np.float32)
+    res = oracle.invert(hmi, obs, wl.weights(6), nthreads=2)
+    c = res["counters"]
+    assert c["trials"] == res["iters"].sum() == c["solves"]
+    # one synthesis with derivatives per pixel at the start, one per success
+    assert 16 <= c["derivs"] <= 16 + c["trials"]
+    for k in range(4):
+        r = oracle.lm_pixel(hmi, obs[k], wl.weights(6))
+        assert r["params"] == pytest.approx(res["params"][k], abs=0)
+        assert r["chi2"] == res["chi2"][k] and r["iters"] == res["iters"][k]
+
+
+def test_noiseless_recovery(hmi):
+    P = wl.draw_params(12, 13, b_range=(1000.0, 3000.0))
+    P[:, 1] = np.clip(P[:, 1], 20, 160)
+    P[:, 9] = 0.9
+    opts = oracle.Options(max_iter=200, rel_tol=1e-14)
+    for M in P:
+        obs = oracle.forward(hmi, M).astype(np.float32)
+        truth_chi = np.sum(1e6 * (obs - oracle.forward(hmi, M)) ** 2) / 14
+        M0 = M + np.array([40.0, 2.0, 2.0, 0.05, 1.0, 0.02, 0.5, 0.01, -0.01, -0.02])
+        r = oracle.lm_pixel(hmi, obs, wl.weights(6), M0=M0, opts=opts)
+        # the float32 rounding of the data is the only "noise"
+        assert r["chi2"] <= truth_chi * (1 + 1e-6) + 1e-20
+        assert r["params"][0] == pytest.approx(M[0], rel=1e-3)
+        assert r["params"][1] == pytest.approx(M[1], abs=0.05)
+        assert r["params"][3] == pytest.approx(M[3], abs=2e-4)
+
+
+def test_brute_force_two_free_parameters(hmi):
+    """Free B and v only; LM from a nearby start reaches the grid minimum."""
+    M = np.array([1400.0, 55.0, 40.0, 0.8, 32.0, 0.2, 8.0, 0.25, 0.75, 0.7])
+    obs = _pixel(hmi, M, 14)
+    W = wl.weights(6)
+    mask = (1 << 0) | (1 << 3)
+    r = oracle.lm_pixel(hmi, obs, W, M0=M + np.array([150, 0, 0, -0.2, 0, 0, 0, 0, 0, 0.0]),
+                        opts=oracle.Options(max_iter=100, rel_tol=1e-12, free_mask=mask))
+
+    def chi(B, v):
+        X = M.copy()
+        X[0], X[3] = B, v
+        return np.sum(W * (obs - oracle.forward(hmi, X)) ** 2) / 22
+
+    best = (np.inf, None, None)
+    for B in np.linspace(M[0] - 300, M[0] + 300, 31):
+        for v in np.linspace(M[3] - 0.3, M[3] + 0.3, 31):
+            c = chi(B, v)
+            if c < best[0]:
+                best = (c, B, v)
+    for _ in range(3):  # refine around the grid minimum
+        _, B0, v0 = best
+        for B in np.linspace(B0 - 20, B0 + 20, 21):
+            for v in np.linspace(v0 - 0.02, v0 + 0.02, 21):
+                c = chi(B, v)
+                if c < best[0]:
+                    best = (c, B, v)
+    assert r["chi2"] <= best[0] * (1 + 1e-9)
+    assert r["params"][0] == pytest.approx(best[1], abs=2.0)
+    assert r["params"][3] == pytest.approx(best[2], abs=2e-3)
+
+
+def test_same_minimum_as_minpack(hmi):
+    P = wl.draw_params(6, 15, b_range=(800.0, 2800.0))
+    P[:, 1] = np.clip(P[:, 1], 25, 155)
+    W = wl.weights(6)
+    sw = np.sqrt(W.astype(np.float64))
+    compared = 0
+    for k, M in enumerate(P):
+        obs = _pixel(hmi, M, 100 + k)
+        M0 = M + np.array([60.0, 3.0, 3.0, 0.05, 1.0, 0.02, 0.5, 0.01, -0.01, -0.02])
+
+        def res(x):
+            return (sw * (obs - oracle.forward(hmi, x))).ravel()
+
+        def jac(x):
+            _, J = oracle.forward(hmi, x, jac=True)
+            return -(sw[:, :, None] * J).reshape(24, 10)
+
+        ls = least_squares(res, M0, jac=jac, method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15,
+                           max_nfev=5000)
+        chi_ls = np.sum(ls.fun ** 2) / 14
+        r = oracle.lm_pixel(hmi, obs, W, M0=M0, opts=oracle.Options(max_iter=300, rel_tol=1e-13))
+        inside = np.all(oracle.project(ls.x)[[0, 3, 4, 5, 6, 7, 8, 9]] == ls.x[[0, 3, 4, 5, 6, 7, 8, 9]])
+        if not inside:
+            continue  # MINPACK is unconstrained; compare only interior minima
+        assert r["chi2"] <= chi_ls * (1 + 1e-9), (k, r["chi2"], chi_ls)
+        assert r["chi2"] == pytest.approx(chi_ls, rel=1e-6)
+        compared += 1
+    assert compared >= 3
