@@ -1,0 +1,196 @@
+/*
+ * vfisv.h -- C ABI of libvfisv.so, the MI355X (gfx950) Milne-Eddington
+ * Stokes-vector inverter.
+ *
+ * The library implements the per-pixel inversion of Borrero et al.,
+ * "VFISV: Very Fast Inversion of the Stokes Vector for the Helioseismic and
+ * Magnetic Imager" (arXiv:0901.2702): for every pixel a Levenberg-Marquardt
+ * fit (Sect. 2, Eqs. 1-6; Sect. 4.2, Table 2) of a Milne-Eddington model,
+ * synthesised with Voigt / Faraday-Voigt profiles and analytic derivatives
+ * (Sect. 3.1-3.2, Eqs. 7-9; Sect. 4.4) and observed through a linear filter
+ * (Sect. 5 and 7: profiles convolved with the HMI filters).
+ *
+ * Conventions
+ *  - Every function returns an int status (VFISV_OK = 0 or a negative
+ *    VFISV_E_* code) and never throws.  On a validation error nothing is
+ *    enqueued and no output is written; vfisv_last_error() explains.
+ *  - "dev" pointers are device memory of the context's HIP device, owned by
+ *    the caller, kept alive until the stream has been synchronised.  "host"
+ *    pointers are read during the call only.
+ *  - stream is a hipStream_t passed as void* (NULL: the null stream).  Work
+ *    is enqueued asynchronously; the caller synchronises.
+ *  - A context is not thread-safe: use one per host thread, or lock.  Two
+ *    inversions in flight on different streams of one context race on the
+ *    context's work counters (results stay correct; counters do not).
+ *
+ * Model parameters (API order and units), 10 per pixel, float32:
+ *   0 B [G], 1 inclination gamma [deg], 2 azimuth psi [deg],
+ *   3 line-of-sight velocity [km/s] (positive = redshift),
+ *   4 Doppler width [mA], 5 damping a, 6 eta0 (line-to-continuum absorption
+ *   ratio), 7 S0, 8 S1 (source function S0 + S1 tau), 9 filling factor alpha.
+ *   (Sect. 2 model vector with the macroturbulence fixed at zero, which
+ *   Sect. 4.1 shows can be dropped.)
+ *
+ * Stokes data of one pixel: [4][n_obs] float32, rows I, Q, U, V.
+ */
+#ifndef VFISV_H
+#define VFISV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VFISV_NPAR 10
+
+/* Return codes. */
+#define VFISV_OK 0
+#define VFISV_E_INVALID (-1)     /* bad argument: null pointer, bad size,   */
+                                 /* non-finite or negative weight/filter   */
+#define VFISV_E_DEVICE (-2)      /* HIP error (message in last_error)       */
+#define VFISV_E_NOMEM (-3)       /* device or host allocation failed        */
+#define VFISV_E_UNSUPPORTED (-4) /* valid request this build cannot serve   */
+
+/* Per-pixel status word: low 4 bits = exit code. */
+#define VFISV_CONVERGED 0  /* relative chi^2 decrease below rel_tol      */
+#define VFISV_MAX_ITER 1   /* max_iter trial syntheses used              */
+#define VFISV_STALLED 2    /* damping eps grew above eps_max             */
+#define VFISV_NONFINITE 3  /* non-finite input: params and chi2 are NaN  */
+
+typedef struct vfisv_ctx vfisv_ctx;
+typedef struct vfisv_instrument vfisv_instrument;
+
+/* Instrument: a Zeeman-triplet line (Table 1; Eq. 7 gives its splitting
+ * from lambda0 and g_eff) synthesised on n_fine wavelengths and observed
+ * through a linear filter (n_obs x n_fine), e.g. the six HMI filter
+ * positions of Sect. 1.  Taps smaller than tap_threshold times the largest
+ * tap of their row are dropped (0 keeps every non-zero tap); the sum of the
+ * dropped taps' magnitudes, relative to the row sum, is reported through
+ * vfisv_instrument_info. */
+typedef struct {
+  double lambda0_A;             /* line centre [A]                      */
+  double geff;                  /* effective Lande factor               */
+  int n_fine;                   /* synthesis points, 1..4096            */
+  const double *fine_offset_mA; /* host [n_fine], offsets from lambda0  */
+  int n_obs;                    /* observed samples; this build: 6      */
+  const double *filter;         /* host [n_obs][n_fine], row-major      */
+  double tap_threshold;         /* relative; 0 <= t < 1                 */
+} vfisv_instrument_desc;
+
+typedef struct {
+  int n_active_fine;       /* synthesis points carrying a non-zero tap */
+  double max_dropped_rel;  /* largest dropped tap mass / row sum       */
+  double cz_mA_per_G;      /* Eq. 7 splitting constant                 */
+} vfisv_instrument_info;
+
+/* Fit options; vfisv_options_default fills the documented defaults. */
+typedef struct {
+  int max_iter;        /* trial syntheses per pixel (default 50)            */
+  double eps0;         /* initial damping (1e-3)                            */
+  double eps_max;      /* stall threshold (1e8)                             */
+  double rel_tol;      /* relative chi^2 decrease ending the fit (1e-5)     */
+  uint32_t free_mask;  /* bit p set: parameter p free (0x3FF)               */
+  int grid_waves;      /* persistent grid size in waves; 0 = auto           */
+} vfisv_options;
+
+/* Work counters of the most recent vfisv_invert on a context. */
+typedef struct {
+  int64_t pixels;         /* pixels finished                                */
+  int64_t trials;         /* trial syntheses (sum of iters)                 */
+  int64_t accepts;        /* accepted trials                                */
+  int64_t passes;         /* synthesis passes executed (trials + initial)   */
+  int64_t svd_fallbacks;  /* solves that needed the eigen/SVD fallback      */
+  int64_t grid_waves;     /* waves launched                                 */
+} vfisv_counters;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (the device is made current on
+ * the calling thread).  Allocates the context's device work counters and
+ * the solve workspace.  Errors: VFISV_E_INVALID (out == NULL or no such
+ * device), VFISV_E_DEVICE, VFISV_E_NOMEM. */
+int vfisv_create(vfisv_ctx **out, int device);
+
+/* Free the context (synchronises its device).  NULL is accepted. */
+int vfisv_destroy(vfisv_ctx *ctx);
+
+/* Message of the last failed call on ctx (ctx == NULL: of the last failed
+ * vfisv_create on this thread).  Valid until the next call on ctx. */
+const char *vfisv_last_error(const vfisv_ctx *ctx);
+
+/* Library version string. */
+const char *vfisv_version(void);
+
+/* ---- instrument ------------------------------------------------------- */
+
+/* Copy the instrument to the device (host inputs are copied; the
+ * instrument owns its device tables).  Validates sizes, finiteness and
+ * non-negativity of the filter.  n_obs other than 6 returns
+ * VFISV_E_UNSUPPORTED in this build. */
+int vfisv_instrument_create(vfisv_ctx *ctx, const vfisv_instrument_desc *desc,
+                            vfisv_instrument **out);
+int vfisv_instrument_info_get(const vfisv_instrument *inst, vfisv_instrument_info *info);
+int vfisv_instrument_destroy(vfisv_instrument *inst);
+
+/* ---- options ---------------------------------------------------------- */
+
+void vfisv_options_default(vfisv_options *opt);
+
+/* ---- forward synthesis (Sect. 3; filtered, Sect. 5) ------------------- */
+
+/* For n pixels: the filtered Stokes vector of the model params (dev
+ * [n][10]) into stokes (dev [n][4][n_obs]) and, if jac != NULL, its
+ * Jacobian into jac (dev [n][4][n_obs][10], per API unit).  If noise !=
+ * NULL (dev [n][4][n_obs]) it is added to stokes (not to jac).  Params are
+ * used as given (no projection).  n == 0 is a no-op. */
+int vfisv_synthesize(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                     const float *params, const float *noise, float *stokes,
+                     float *jac, void *stream);
+
+/* ---- inversion (Sects. 2 and 4) --------------------------------------- */
+
+/* Invert n pixels.
+ *   stokes: dev [n][4][n_obs] observed profiles.
+ *   W:      dev weights w^2/sigma^2 of Eq. 1: [4][n_obs] shared by all
+ *           pixels, or [n][4][n_obs] when W_per_pixel != 0.  Must be
+ *           finite and >= 0 (not checked on the device; a pixel with a
+ *           non-finite weight gets status NONFINITE).
+ *   init:   dev [n][10] starting models, or NULL for the default model
+ *           (B 1500 G, gamma 90, psi 90, v 0, Doppler width 35 mA, a 0.25,
+ *           eta0 15.5, S0 0.3, S1 0.7, alpha 0.6).
+ *   params: dev [n][10] best model (float32, API units).
+ *   chi2:   dev [n] reduced chi^2 of Eq. 1 at params (float64).
+ *   iters:  dev [n] trial syntheses used.
+ *   status: dev [n] status word, or NULL.
+ * Per-pixel numerical trouble never fails the call; it is reported in
+ * status.  n == 0 enqueues nothing.  4*n_obs - (free parameters) must be
+ * > 0. */
+int vfisv_invert(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                 const float *stokes, const float *W, int W_per_pixel,
+                 const float *init, const vfisv_options *opt, float *params,
+                 double *chi2, int32_t *iters, int32_t *status, void *stream);
+
+/* Work counters of the most recent vfisv_invert (synchronises the
+ * context's device). */
+int vfisv_get_counters(vfisv_ctx *ctx, vfisv_counters *out);
+
+/* ---- damped normal-equation solve (Eqs. 3-5), for verification -------- */
+
+/* For n systems: delta = solution of (H + eps diag H) delta = g on the
+ * diagonally equilibrated system (Cholesky, eigen/SVD fallback discarding
+ * singular values below 1e-12 of the largest; parameters outside
+ * free_mask or without leverage get delta = 0).
+ *   H:     dev [n][55] float32, lower triangle packed row by row
+ *          (H[p][q], q <= p, at p*(p+1)/2 + q).
+ *   g:     dev [n][10] float32; eps: dev [n] float64.
+ *   delta: dev [n][10] float64; code: dev [n] int32 (0 Cholesky,
+ *          1 fallback, 2 nothing free), or NULL. */
+int vfisv_solve(vfisv_ctx *ctx, int64_t n, const float *H, const float *g,
+                const double *eps, uint32_t free_mask, double *delta,
+                int32_t *code, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFISV_H */

@@ -293,7 +293,7 @@ void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
 }
 
 /* ------------------------------------------------------------------ */
-/* Thread pool over pixels (chunks of 64 pixels from a shared counter). */
+/* Thread pool over pixels (one pixel at a time from a shared counter). */
 
 typedef struct {
   const orc_instrument *inst;
@@ -321,9 +321,9 @@ static void *invert_worker(void *p) {
   const int rows = 4 * jb->inst->n_obs;
   orc_counters *cnt = &jb->cnt[a->tid];
   for (;;) {
-    const int64_t start = atomic_fetch_add(&jb->next, 64);
+    const int64_t start = atomic_fetch_add(&jb->next, 1);
     if (start >= jb->n) break;
-    const int64_t end = start + 64 < jb->n ? start + 64 : jb->n;
+    const int64_t end = start + 1;
     for (int64_t i = start; i < end; ++i) {
       const float *w = jb->W_per_pixel ? jb->W + i * rows : jb->W;
       orc_lm_pixel(jb->inst, jb->opt, jb->stokes + i * rows, w,
@@ -339,9 +339,9 @@ static void *forward_worker(void *p) {
   pool_job *jb = a->job;
   const int rows = 4 * jb->inst->n_obs;
   for (;;) {
-    const int64_t start = atomic_fetch_add(&jb->next, 64);
+    const int64_t start = atomic_fetch_add(&jb->next, 1);
     if (start >= jb->n) break;
-    const int64_t end = start + 64 < jb->n ? start + 64 : jb->n;
+    const int64_t end = start + 1;
     for (int64_t i = start; i < end; ++i)
       orc_forward(jb->inst, jb->fwd_params + i * NP, jb->fwd_out + i * rows, NULL);
   }

@@ -1,0 +1,256 @@
+"""MI355X-native Milne-Eddington Stokes inverter (VFISV hot path).
+
+Thin ctypes binding of ``libvfisv.so`` (C ABI in ``include/vfisv.h``).  Torch
+is used only for device memory and streams: every step of the inversion runs
+in the library's HIP kernels.  There is no CPU fallback: if the library or a
+HIP device is missing, calls raise.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loaded first so the library binds to the process's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvfisv.so")
+NPAR = 10
+CONVERGED, MAX_ITER, STALLED, NONFINITE = 0, 1, 2, 3
+PARAM_NAMES = ("B", "gamma", "psi", "v_los", "doppler_width", "damping", "eta0", "S0", "S1",
+               "alpha")
+
+_vp = ctypes.c_void_p
+
+
+class VfisvError(RuntimeError):
+    pass
+
+
+class _InstDesc(ctypes.Structure):
+    _fields_ = [("lambda0_A", ctypes.c_double), ("geff", ctypes.c_double),
+                ("n_fine", ctypes.c_int), ("fine_offset_mA", ctypes.POINTER(ctypes.c_double)),
+                ("n_obs", ctypes.c_int), ("filter", ctypes.POINTER(ctypes.c_double)),
+                ("tap_threshold", ctypes.c_double)]
+
+
+class _InstInfo(ctypes.Structure):
+    _fields_ = [("n_active_fine", ctypes.c_int), ("max_dropped_rel", ctypes.c_double),
+                ("cz_mA_per_G", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
+                ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
+                ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int)]
+
+
+class _Counters(ctypes.Structure):
+    _fields_ = [("pixels", ctypes.c_int64), ("trials", ctypes.c_int64),
+                ("accepts", ctypes.c_int64), ("passes", ctypes.c_int64),
+                ("svd_fallbacks", ctypes.c_int64), ("grid_waves", ctypes.c_int64)]
+
+
+# Every symbol declared in include/vfisv.h.
+EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
+           "vfisv_instrument_create", "vfisv_instrument_info_get", "vfisv_instrument_destroy",
+           "vfisv_options_default", "vfisv_synthesize", "vfisv_invert", "vfisv_get_counters",
+           "vfisv_solve")
+
+_LIB = None
+
+
+def lib():
+    """Load libvfisv.so (built by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise VfisvError("libvfisv.so is not built (%s); run __graft_entry__.build()"
+                             % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.vfisv_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+        L.vfisv_destroy.argtypes = [_vp]
+        L.vfisv_last_error.argtypes = [_vp]
+        L.vfisv_last_error.restype = ctypes.c_char_p
+        L.vfisv_version.restype = ctypes.c_char_p
+        L.vfisv_instrument_create.argtypes = [_vp, ctypes.POINTER(_InstDesc), ctypes.POINTER(_vp)]
+        L.vfisv_instrument_info_get.argtypes = [_vp, ctypes.POINTER(_InstInfo)]
+        L.vfisv_instrument_destroy.argtypes = [_vp]
+        L.vfisv_options_default.argtypes = [ctypes.POINTER(_Options)]
+        L.vfisv_options_default.restype = None
+        L.vfisv_synthesize.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.vfisv_invert.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int, _vp,
+                                   ctypes.POINTER(_Options), _vp, _vp, _vp, _vp, _vp]
+        L.vfisv_get_counters.argtypes = [_vp, ctypes.POINTER(_Counters)]
+        L.vfisv_solve.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_uint32, _vp,
+                                  _vp, _vp]
+        _LIB = L
+    return _LIB
+
+
+def version():
+    return lib().vfisv_version().decode()
+
+
+def _ptr(t, dtype, device, shape_last=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.device != device:
+        raise ValueError("%s must live on %s, got %s" % (name, device, t.device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """Library context on one HIP device."""
+
+    def __init__(self, device=0):
+        if not torch.cuda.is_available():
+            raise VfisvError("no HIP device visible")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        h = _vp()
+        rc = lib().vfisv_create(ctypes.byref(h), device)
+        if rc != 0:
+            raise VfisvError("vfisv_create: %s" % lib().vfisv_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise VfisvError("%s (rc %d): %s" % (what, rc,
+                                                   lib().vfisv_last_error(self._h).decode()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vfisv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def counters(self):
+        c = _Counters()
+        self._check(lib().vfisv_get_counters(self._h, ctypes.byref(c)), "vfisv_get_counters")
+        return {k: getattr(c, k) for k, _ in _Counters._fields_}
+
+
+class Instrument:
+    """Line + synthesis grid + filter, copied to the device."""
+
+    def __init__(self, ctx, lambda0_A, geff, fine_offset_mA, filt, tap_threshold=2.0 ** -24):
+        import numpy as np
+        self.ctx = ctx
+        self._fine = np.ascontiguousarray(fine_offset_mA, dtype=np.float64)
+        self._filt = np.ascontiguousarray(filt, dtype=np.float64)
+        self.n_fine = int(self._fine.shape[0])
+        self.n_obs = int(self._filt.shape[0])
+        if self._filt.shape != (self.n_obs, self.n_fine):
+            raise ValueError("filter must be [n_obs, n_fine]")
+        d = _InstDesc(float(lambda0_A), float(geff), self.n_fine,
+                      self._fine.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_obs,
+                      self._filt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      float(tap_threshold))
+        h = _vp()
+        ctx._check(lib().vfisv_instrument_create(ctx._h, ctypes.byref(d), ctypes.byref(h)),
+                   "vfisv_instrument_create")
+        self._h = h
+        info = _InstInfo()
+        lib().vfisv_instrument_info_get(h, ctypes.byref(info))
+        self.info = {k: getattr(info, k) for k, _ in _InstInfo._fields_}
+
+    @classmethod
+    def from_spec(cls, ctx, spec, **kw):
+        return cls(ctx, spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vfisv_instrument_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Options:
+    max_iter: int = 50
+    eps0: float = 1e-3
+    eps_max: float = 1e8
+    rel_tol: float = 1e-5
+    free_mask: int = 0x3FF
+    grid_waves: int = 0
+
+    def c(self):
+        return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
+                        self.grid_waves)
+
+
+def synthesize(ctx, inst, params, noise=None, jac=False, out=None):
+    """Filtered Stokes vector [n, 4, n_obs] (and Jacobian [n, 4, n_obs, 10])
+    of the models ``params`` [n, 10] (float32, on the context's device)."""
+    dev = ctx.device
+    n = params.shape[0]
+    p = _ptr(params, torch.float32, dev, name="params")
+    stokes = out if out is not None else torch.empty((n, 4, inst.n_obs), device=dev,
+                                                     dtype=torch.float32)
+    J = torch.empty((n, 4, inst.n_obs, NPAR), device=dev, dtype=torch.float32) if jac else None
+    ctx._check(lib().vfisv_synthesize(ctx._h, inst._h, n, p,
+                                      _ptr(noise, torch.float32, dev, name="noise"),
+                                      _ptr(stokes, torch.float32, dev, name="out"),
+                                      _ptr(J, torch.float32, dev, name="jac"), _stream(dev)),
+               "vfisv_synthesize")
+    return (stokes, J) if jac else stokes
+
+
+def invert(ctx, inst, stokes, W, init=None, opts=None, out=None):
+    """Invert n pixels: stokes [n, 4, n_obs] float32; W [4, n_obs] or
+    [n, 4, n_obs] float32; init [n, 10] float32 or None.  Returns a dict of
+    device tensors params [n, 10], chi2 [n] (float64), iters [n], status [n]."""
+    dev = ctx.device
+    opts = opts or Options()
+    n = stokes.shape[0]
+    if out is None:
+        out = dict(params=torch.empty((n, NPAR), device=dev, dtype=torch.float32),
+                   chi2=torch.empty(n, device=dev, dtype=torch.float64),
+                   iters=torch.empty(n, device=dev, dtype=torch.int32),
+                   status=torch.empty(n, device=dev, dtype=torch.int32))
+    per_pixel = 1 if W.dim() == 3 else 0
+    o = opts.c()
+    ctx._check(lib().vfisv_invert(
+        ctx._h, inst._h, n, _ptr(stokes, torch.float32, dev, name="stokes"),
+        _ptr(W, torch.float32, dev, name="W"), per_pixel,
+        _ptr(init, torch.float32, dev, name="init"), ctypes.byref(o),
+        _ptr(out["params"], torch.float32, dev, name="params"),
+        _ptr(out["chi2"], torch.float64, dev, name="chi2"),
+        _ptr(out["iters"], torch.int32, dev, name="iters"),
+        _ptr(out["status"], torch.int32, dev, name="status"), _stream(dev)), "vfisv_invert")
+    return out
+
+
+def solve(ctx, H, g, eps, free_mask=0x3FF):
+    """Damped solves: H [n, 55] float32 packed lower triangle, g [n, 10]
+    float32, eps [n] float64 -> (delta [n, 10] float64, code [n] int32)."""
+    dev = ctx.device
+    n = H.shape[0]
+    delta = torch.empty((n, NPAR), device=dev, dtype=torch.float64)
+    code = torch.empty(n, device=dev, dtype=torch.int32)
+    ctx._check(lib().vfisv_solve(ctx._h, n, _ptr(H, torch.float32, dev, name="H"),
+                                 _ptr(g, torch.float32, dev, name="g"),
+                                 _ptr(eps, torch.float64, dev, name="eps"), free_mask,
+                                 _ptr(delta, torch.float64, dev, name="delta"),
+                                 _ptr(code, torch.int32, dev, name="code"), _stream(dev)),
+               "vfisv_solve")
+    return delta, code

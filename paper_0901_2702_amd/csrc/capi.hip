@@ -1,0 +1,404 @@
+// C ABI of libvfisv.so (declared in include/vfisv.h): argument checking,
+// instrument preparation, device buffers owned by the library, and kernel
+// launches.  No torch types cross this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "vfisv.h"
+
+using namespace vfisv;
+
+struct vfisv_ctx {
+  int device = 0;
+  int num_cus = 0;
+  int lm_blocks_per_cu = 1;
+  unsigned long long* d_work = nullptr;
+  double* d_ws = nullptr;
+  int64_t ws_lanes = 0;
+  float wc[NW + 1];
+  float wL = 0.f;
+  std::string err;
+};
+
+struct vfisv_instrument {
+  vfisv_ctx* ctx = nullptr;
+  Point* d_pts = nullptr;
+  Consts C;
+  vfisv_instrument_info info;
+};
+
+static thread_local std::string g_create_err;
+
+static int fail(vfisv_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+static int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, VFISV_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Weideman (1994) coefficients: with L = sqrt(N / sqrt(2)) and
+// f(t) = exp(-t^2) (L^2 + t^2), a_n is the n-th Fourier cosine coefficient of
+// f(L tan(theta / 2)) over theta in [-pi, pi], computed here by the
+// trapezoidal rule on 2M points (spectrally accurate for this smooth
+// periodic function).
+static void weideman_coefficients(int N, double* L_out, double* a /* [N + 1] */) {
+  const double L = std::sqrt(N / std::sqrt(2.0));
+  const int M = 8 * N;
+  const double pi = 3.14159265358979323846;
+  for (int n = 0; n <= N; ++n) {
+    double s = 0.0;
+    for (int k = -M + 1; k <= M; ++k) {
+      const double th = k * pi / M;
+      double F = 0.0;
+      if (k != M) {
+        const double t = L * std::tan(0.5 * th);
+        F = std::exp(-t * t) * (L * L + t * t);
+      }
+      s += F * std::cos(n * th);
+    }
+    a[n] = s / (2.0 * M);
+  }
+  *L_out = L;
+}
+
+extern "C" {
+
+const char* vfisv_version(void) { return "vfisv-gfx950 0.1.0"; }
+
+const char* vfisv_last_error(const vfisv_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int vfisv_create(vfisv_ctx** out, int device) {
+  if (!out) return fail(nullptr, VFISV_E_INVALID, "vfisv_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev)
+    return fail(nullptr, VFISV_E_INVALID, "vfisv_create: no HIP device " + std::to_string(device));
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  vfisv_ctx* c = new (std::nothrow) vfisv_ctx();
+  if (!c) return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: host allocation");
+  c->device = device;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipGetDeviceProperties");
+  }
+  c->num_cus = prop.multiProcessorCount;
+  int bpc = 0;
+  e = lm_blocks_per_cu(&bpc);
+  if (e != hipSuccess || bpc < 1) bpc = 1;
+  c->lm_blocks_per_cu = bpc;
+  // fallback workspace: 200 doubles per lane of the largest persistent grid
+  c->ws_lanes = (int64_t)c->num_cus * 8 * 64;
+  e = hipMalloc(&c->d_ws, sizeof(double) * 200 * c->ws_lanes);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: workspace allocation");
+  }
+  e = hipMalloc(&c->d_work, sizeof(unsigned long long) * WORK_SLOTS);
+  if (e != hipSuccess) {
+    hipFree(c->d_ws);
+    delete c;
+    return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: counter allocation");
+  }
+  e = launch_reset(c->d_work, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    hipFree(c->d_ws);
+    hipFree(c->d_work);
+    delete c;
+    return hip_fail(nullptr, e, "vfisv_create: counter reset");
+  }
+  double L, a[NW + 1];
+  weideman_coefficients(NW, &L, a);
+  c->wL = (float)L;
+  c->wc[0] = 0.f;
+  for (int n = 1; n <= NW; ++n) c->wc[n] = (float)(2.0 * a[n]);
+  *out = c;
+  return VFISV_OK;
+}
+
+int vfisv_destroy(vfisv_ctx* ctx) {
+  if (!ctx) return VFISV_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  hipFree(ctx->d_ws);
+  hipFree(ctx->d_work);
+  delete ctx;
+  return VFISV_OK;
+}
+
+void vfisv_options_default(vfisv_options* o) {
+  if (!o) return;
+  o->max_iter = 50;
+  o->eps0 = 1e-3;
+  o->eps_max = 1e8;
+  o->rel_tol = 1e-5;
+  o->free_mask = 0x3FFu;
+  o->grid_waves = 0;
+}
+
+int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
+                            vfisv_instrument** out) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "instrument_create: ctx is NULL");
+  if (!d || !out) return fail(ctx, VFISV_E_INVALID, "instrument_create: NULL argument");
+  *out = nullptr;
+  if (!d->fine_offset_mA || !d->filter)
+    return fail(ctx, VFISV_E_INVALID, "instrument_create: NULL table");
+  if (d->n_fine < 1 || d->n_fine > 4096)
+    return fail(ctx, VFISV_E_INVALID, "instrument_create: n_fine must be in 1..4096");
+  if (d->n_obs < 1) return fail(ctx, VFISV_E_INVALID, "instrument_create: n_obs must be >= 1");
+  if (!(d->lambda0_A > 0.0) || !std::isfinite(d->lambda0_A) || !std::isfinite(d->geff))
+    return fail(ctx, VFISV_E_INVALID, "instrument_create: bad lambda0 or geff");
+  if (!(d->tap_threshold >= 0.0 && d->tap_threshold < 1.0))
+    return fail(ctx, VFISV_E_INVALID, "instrument_create: tap_threshold must be in [0, 1)");
+  for (int k = 0; k < d->n_fine; ++k)
+    if (!std::isfinite(d->fine_offset_mA[k]))
+      return fail(ctx, VFISV_E_INVALID, "instrument_create: non-finite fine offset");
+  const int nf = d->n_fine, no = d->n_obs;
+  for (int64_t i = 0; i < (int64_t)nf * no; ++i)
+    if (!std::isfinite(d->filter[i]) || d->filter[i] < 0.0)
+      return fail(ctx, VFISV_E_INVALID, "instrument_create: filter taps must be finite and >= 0");
+  if (no != NOBS_HMI)
+    return fail(ctx, VFISV_E_UNSUPPORTED,
+                "instrument_create: this build serves n_obs == 6 (HMI-shaped) instruments");
+
+  vfisv_instrument* inst = new (std::nothrow) vfisv_instrument();
+  if (!inst) return fail(ctx, VFISV_E_NOMEM, "instrument_create: host allocation");
+  inst->ctx = ctx;
+  std::memset(&inst->C, 0, sizeof(Consts));
+  double max_drop = 0.0;
+  std::vector<double> kept((size_t)no * nf);
+  for (int i = 0; i < no; ++i) {
+    double rmax = 0.0, rsum = 0.0, drop = 0.0, ksum = 0.0;
+    for (int k = 0; k < nf; ++k) {
+      rmax = std::fmax(rmax, d->filter[(size_t)i * nf + k]);
+      rsum += d->filter[(size_t)i * nf + k];
+    }
+    for (int k = 0; k < nf; ++k) {
+      const double w = d->filter[(size_t)i * nf + k];
+      const bool keep = w > 0.0 && w >= d->tap_threshold * rmax && (float)w != 0.0f;
+      kept[(size_t)i * nf + k] = keep ? w : 0.0;
+      if (!keep) drop += w;
+      ksum += keep ? (double)(float)w : 0.0;
+    }
+    if (rsum > 0.0) max_drop = std::fmax(max_drop, drop / rsum);
+    inst->C.row_sum[i] = (float)ksum;
+  }
+  std::vector<Point> pts;
+  for (int k = 0; k < nf; ++k) {
+    Point p;
+    std::memset(&p, 0, sizeof p);
+    p.dl = (float)d->fine_offset_mA[k];
+    uint32_t mask = 0;
+    for (int i = 0; i < no; ++i) {
+      p.w[i] = (float)kept[(size_t)i * nf + k];
+      if (p.w[i] != 0.f) mask |= 1u << i;
+    }
+    std::memcpy(&p.w[6], &mask, 4);
+    if (mask) pts.push_back(p);
+  }
+  const double lam0_mA = d->lambda0_A * 1000.0;
+  inst->C.lam_over_c = (float)(lam0_mA / C_KMS);
+  const double cz = 4.66685e-10 * d->geff * d->lambda0_A * d->lambda0_A;  // Eq. 7
+  inst->C.cz = (float)cz;
+  inst->C.n_pts = (int)pts.size();
+  inst->C.n_obs = no;
+  for (int n = 0; n <= NW; ++n) inst->C.wc[n] = ctx->wc[n];
+  inst->C.wL = ctx->wL;
+  inst->C.wL2 = ctx->wL * ctx->wL;
+  inst->C.w2L = 2.f * ctx->wL;
+  inst->info.n_active_fine = (int)pts.size();
+  inst->info.max_dropped_rel = max_drop;
+  inst->info.cz_mA_per_G = cz;
+
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) {
+    delete inst;
+    return hip_fail(ctx, e, "hipSetDevice");
+  }
+  const size_t bytes = sizeof(Point) * (pts.empty() ? 1 : pts.size());
+  e = hipMalloc(&inst->d_pts, bytes);
+  if (e != hipSuccess) {
+    delete inst;
+    return fail(ctx, VFISV_E_NOMEM, "instrument_create: device allocation");
+  }
+  if (!pts.empty()) e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(),
+                                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(inst->d_pts);
+    delete inst;
+    return hip_fail(ctx, e, "instrument_create: copy");
+  }
+  *out = inst;
+  return VFISV_OK;
+}
+
+int vfisv_instrument_info_get(const vfisv_instrument* inst, vfisv_instrument_info* info) {
+  if (!inst || !info) return VFISV_E_INVALID;
+  *info = inst->info;
+  return VFISV_OK;
+}
+
+int vfisv_instrument_destroy(vfisv_instrument* inst) {
+  if (!inst) return VFISV_OK;
+  hipSetDevice(inst->ctx->device);
+  hipDeviceSynchronize();
+  hipFree(inst->d_pts);
+  delete inst;
+  return VFISV_OK;
+}
+
+static int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn) {
+  if (!inst) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument is NULL");
+  if (inst->ctx != ctx)
+    return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument of another context");
+  return VFISV_OK;
+}
+
+static int grid_for(int64_t n, int64_t cap) {
+  const int64_t waves = (n + 63) / 64;
+  return (int)(waves < cap ? (waves < 1 ? 1 : waves) : cap);
+}
+
+int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                     const float* params, const float* noise, float* stokes, float* jac,
+                     void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "synthesize: ctx is NULL");
+  int rc = check_inst(ctx, inst, "synthesize");
+  if (rc) return rc;
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "synthesize: n < 0");
+  if (n == 0) return VFISV_OK;
+  if (!params || !stokes) return fail(ctx, VFISV_E_INVALID, "synthesize: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  SynthArgs a;
+  a.C = inst->C;
+  a.pts = inst->d_pts;
+  a.params = params;
+  a.noise = noise;
+  a.stokes = stokes;
+  a.jac = jac;
+  a.n = n;
+  const int grid = grid_for(n, (int64_t)ctx->num_cus * 16);
+  e = launch_synth(a, jac != nullptr, grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
+  return VFISV_OK;
+}
+
+int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const float* stokes,
+                 const float* W, int W_per_pixel, const float* init, const vfisv_options* opt,
+                 float* params, double* chi2, int32_t* iters, int32_t* status, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert: ctx is NULL");
+  int rc = check_inst(ctx, inst, "invert");
+  if (rc) return rc;
+  vfisv_options o;
+  vfisv_options_default(&o);
+  if (opt) o = *opt;
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert: n < 0");
+  if (o.max_iter < 0) return fail(ctx, VFISV_E_INVALID, "invert: max_iter < 0");
+  if (!(o.eps0 > 0.0) || !(o.eps_max > 0.0) || !(o.rel_tol >= 0.0) ||
+      !std::isfinite(o.eps0) || !std::isfinite(o.rel_tol))
+    return fail(ctx, VFISV_E_INVALID, "invert: eps0, eps_max must be > 0 and rel_tol >= 0");
+  if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "invert: grid_waves < 0");
+  const uint32_t mask = o.free_mask & 0x3FFu;
+  int nfree = 0;
+  for (int p = 0; p < NPAR; ++p) nfree += (mask >> p) & 1u;
+  const int dof = 4 * inst->C.n_obs - nfree;
+  if (dof <= 0) return fail(ctx, VFISV_E_INVALID, "invert: 4*n_obs - free parameters must be > 0");
+  if (n == 0) return VFISV_OK;
+  if (!stokes || !W || !params || !chi2 || !iters)
+    return fail(ctx, VFISV_E_INVALID, "invert: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+
+  LMArgs a;
+  a.C = inst->C;
+  a.pts = inst->d_pts;
+  a.stokes = stokes;
+  a.W = W;
+  a.init = init;
+  a.params = params;
+  a.chi2 = chi2;
+  a.iters = iters;
+  a.status = status;
+  a.work = ctx->d_work;
+  a.ws = ctx->d_ws;
+  a.n = n;
+  a.eps0 = o.eps0;
+  a.eps_max = o.eps_max;
+  a.rel_tol = o.rel_tol;
+  a.inv_dof = 1.0 / (double)dof;
+  a.max_iter = o.max_iter;
+  a.W_pp = W_per_pixel ? 1 : 0;
+  a.free_mask = mask;
+  int64_t cap = (int64_t)ctx->num_cus * ctx->lm_blocks_per_cu;
+  if (o.grid_waves > 0) cap = o.grid_waves;
+  if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
+  const int grid = grid_for(n, cap);
+  a.ws_stride = (int64_t)grid * 64;
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_reset(ctx->d_work, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
+  e = launch_lm(a, grid, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert launch");
+  return VFISV_OK;
+}
+
+int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "get_counters: ctx is NULL");
+  if (!out) return fail(ctx, VFISV_E_INVALID, "get_counters: out is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  unsigned long long w[WORK_SLOTS];
+  if (e == hipSuccess) e = hipMemcpy(w, ctx->d_work, sizeof w, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "get_counters");
+  out->pixels = (int64_t)w[1];
+  out->trials = (int64_t)w[2];
+  out->accepts = (int64_t)w[3];
+  out->passes = (int64_t)w[4];
+  out->svd_fallbacks = (int64_t)w[5];
+  out->grid_waves = (int64_t)w[6];
+  return VFISV_OK;
+}
+
+int vfisv_solve(vfisv_ctx* ctx, int64_t n, const float* H, const float* g, const double* eps,
+                uint32_t free_mask, double* delta, int32_t* code, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "solve: ctx is NULL");
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "solve: n < 0");
+  if (n == 0) return VFISV_OK;
+  if (!H || !g || !eps || !delta) return fail(ctx, VFISV_E_INVALID, "solve: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  SolveArgs a;
+  a.H = H;
+  a.g = g;
+  a.eps = eps;
+  a.delta = delta;
+  a.code = code;
+  a.ws = ctx->d_ws;
+  a.n = n;
+  a.free_mask = free_mask & 0x3FFu;
+  const int grid = grid_for(n, ctx->ws_lanes / 64);
+  a.ws_stride = (int64_t)grid * 64;
+  e = launch_solve(a, grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
+  return VFISV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Kernel argument blocks and launch helpers shared by kernels.hip and the
+// C-ABI layer (capi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "me_device.h"
+
+namespace vfisv {
+
+// work[] slots: 0 next pixel, 1 pixels done, 2 trials, 3 accepts,
+// 4 passes, 5 eigen fallbacks, 6 waves
+constexpr int WORK_SLOTS = 8;
+
+struct LMArgs {
+  Consts C;
+  const Point* pts;
+  const float* stokes;
+  const float* W;
+  const float* init;
+  float* params;
+  double* chi2;
+  int32_t* iters;
+  int32_t* status;
+  unsigned long long* work;
+  double* ws;
+  int64_t ws_stride;
+  int64_t n;
+  double eps0, eps_max, rel_tol, inv_dof;
+  int max_iter;
+  int W_pp;
+  uint32_t free_mask;
+};
+
+struct SynthArgs {
+  Consts C;
+  const Point* pts;
+  const float* params;
+  const float* noise;
+  float* stokes;
+  float* jac;
+  int64_t n;
+};
+
+struct SolveArgs {
+  const float* H;
+  const float* g;
+  const double* eps;
+  double* delta;
+  int32_t* code;
+  double* ws;
+  int64_t ws_stride;
+  int64_t n;
+  uint32_t free_mask;
+};
+
+hipError_t launch_reset(unsigned long long* work, hipStream_t s);
+hipError_t launch_lm(const LMArgs& a, int grid, hipStream_t s);
+hipError_t launch_synth(const SynthArgs& a, bool deriv, int grid, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
+hipError_t lm_blocks_per_cu(int* out);
+
+}  // namespace vfisv

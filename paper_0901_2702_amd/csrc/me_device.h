@@ -1,0 +1,527 @@
+// Device-side Milne-Eddington synthesis, Jacobian, normal equations and
+// damped solve for the gfx950 inverter.  One pixel per lane: everything a
+// pixel needs per pass lives in that lane's registers; wave-uniform data
+// (fine-grid offsets, filter taps, Faddeeva coefficients) comes through the
+// scalar cache.
+//
+// Physics (Borrero et al. 2009, arXiv:0901.2702):
+//  * Zeeman triplet of Sect. 3.1: pi component at the (Doppler-shifted) line
+//    centre, blue/red sigma components shifted by -/+ C_Z B (Eq. 7).
+//  * Voigt H and Faraday-Voigt F (Sect. 3.2) as Re/Im of the Faddeeva
+//    function w(u + i a), with the analytic derivatives of Eqs. 8-9.
+//  * Milne-Eddington absorption matrix and Unno-Rachkovsky solution for a
+//    source function S0 + S1 tau at disk centre (the paper's cited
+//    Landolfi & Landi Degl'Innocenti 1982 solution); the magnetised
+//    fraction alpha mixes with a field-free component of the same
+//    atmosphere (Sect. 2 model vector).
+//  * Instrument filter (Sect. 5/7): a linear map from the synthesis grid to
+//    the observed samples, applied to values and derivatives alike.
+//
+// Evaluation choices that differ from the paper's CPU code:
+//  * w(z) uses Weideman's (1994) rational series with N = 16 terms, which is
+//    branch-free (every lane runs the same instructions) and accurate to
+//    ~6e-7 relative in float32, instead of Hui et al. (1977) or the Taylor
+//    table of Eqs. 12-13 (~1e-4).
+//  * Q and U are synthesised in the frame psi = 0 (eta_U = rho_U = 0) and
+//    rotated by 2 psi after filtering; the psi derivatives then follow
+//    exactly from dQ/dpsi = -2U, dU/dpsi = 2Q.
+//  * The derivatives of the Stokes outputs are taken with respect to the
+//    five absorption-matrix elements once per point and chained to the six
+//    profile/angle/strength parameters; per-pixel factors (1/Doppler width,
+//    C_Z, lambda0/c, degrees) are applied after filtering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vfisv {
+
+constexpr int NPAR = 10;
+constexpr int NW = 16;          // Weideman series length
+constexpr int NOBS_HMI = 6;     // observed samples of the HMI-shaped path
+constexpr int NACC = 29;        // per-row accumulators (see synth_pass)
+constexpr float INV_SQRT_PI = 0.56418958354775628695f;
+constexpr float TWO_OVER_SQRT_PI = 1.1283791670955125739f;
+constexpr float DEG = 0.017453292519943295769f;
+constexpr double DEG_D = 0.017453292519943295769;
+constexpr double C_KMS = 299792.458;
+
+// Wave-uniform constants of one launch (kernel argument -> SGPRs).
+struct Consts {
+  float wc[NW + 1];      // 2 * a_n, n = 1..NW (index 0 unused)
+  float wL, wL2, w2L;    // Weideman L, L^2, 2L
+  float lam_over_c;      // lambda0 [mA] / c [km/s]
+  float cz;              // Eq. 7 splitting constant [mA/G]
+  int n_pts;             // synthesis points with a non-zero tap
+  int n_obs;
+  float row_sum[8];      // sum of the kept taps of each filter row
+};
+
+// One synthesis point: offset and the taps of the (up to 6) filter rows;
+// w[6] carries the bit mask of rows with a non-zero tap.  32 bytes.
+struct __attribute__((aligned(32))) Point {
+  float dl;
+  float w[7];
+};
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Per-pixel quantities of one synthesis pass.
+struct Pix {
+  float vsi, invD, zs, a, twoa, denr, denr2, c0;
+  float hs2, hc, hI, hq, hsin2g, hsg, s2h, cgh;
+  float eta0, alpha, oma;
+};
+
+__device__ __forceinline__ void pix_setup(const float* M, const Consts& C, Pix& p) {
+  const float B = M[0], g = M[1] * DEG, v = M[3], dld = M[4], a = M[5], eta0 = M[6],
+              al = M[9];
+  p.invD = frcp(dld);
+  p.vsi = C.lam_over_c * v * p.invD;
+  p.zs = C.cz * B * p.invD;
+  p.a = a;
+  p.twoa = 2.f * a;
+  p.denr = C.wL + a;
+  p.denr2 = p.denr * p.denr;
+  p.c0 = C.wL2 - a * a;
+  float sg, cg;
+  sincosf(g, &sg, &cg);
+  const float s2 = sg * sg;
+  const float half = 0.5f * eta0;
+  p.hs2 = half * s2;
+  p.hc = half * cg;
+  p.hI = half * (1.f - 0.5f * s2);
+  p.hq = 0.5f * p.hs2;
+  p.hsin2g = half * 2.f * sg * cg;
+  p.hsg = half * sg;
+  p.s2h = 0.5f * s2;
+  p.cgh = 0.5f * cg;
+  p.eta0 = eta0;
+  p.alpha = al;
+  p.oma = 1.f - al;
+}
+
+// Weideman's series for w(z), z = u + i a, a >= 0:
+//   w = 1/(sqrt(pi) (L - iz)) + 2/(L - iz)^2 sum_{n=0}^{N-1} a_{n+1} Z^n,
+//   Z = (L + iz)/(L - iz).
+// With den = L - iz = (L + a) - iu:  Z = ((L^2 - a^2 - u^2) + i 2Lu)/|den|^2.
+__device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C, float& H,
+                                         float& F) {
+  const float D = fmaf(u, u, p.denr2);
+  const float rD = frcp(D);
+  const float Zr = fmaf(-u, u, p.c0) * rD;
+  const float Zi = C.w2L * u * rD;
+  float pr = fmaf(C.wc[NW], Zr, C.wc[NW - 1]);
+  float pi = C.wc[NW] * Zi;
+#pragma unroll
+  for (int n = NW - 2; n >= 1; --n) {
+    const float nr = fmaf(pr, Zr, fmaf(-pi, Zi, C.wc[n]));
+    const float ni = fmaf(pr, Zi, pi * Zr);
+    pr = nr;
+    pi = ni;
+  }
+  const float idr = p.denr * rD, idi = u * rD;  // 1/den
+  const float qr = fmaf(pr, idr, fmaf(-pi, idi, INV_SQRT_PI));
+  const float qi = fmaf(pr, idi, pi * idr);
+  H = fmaf(idr, qr, -idi * qi);
+  F = fmaf(idr, qi, idi * qr);
+}
+
+// Contributions of one synthesis point to the per-row accumulators
+// (all normalised by S1; magnetic Q, U in the psi = 0 frame):
+//   c[0] I_mix = alpha I_m + (1 - alpha) I_0,  c[1] I_m - I_0,
+//   c[2] Q0, c[3] U0, c[4] V,
+//   c[5 + 4q + X], q in {B, gamma, v, Doppler width, a, eta0},
+//   X in {I_mix, Q0, U0, V}: derivatives up to per-pixel factors
+//   (B: C_Z/DlD, gamma: 1 per radian, v: -(lambda0/c)/DlD, DlD: -1/DlD).
+template <bool DERIV>
+__device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Consts& C,
+                                              float* c) {
+  const float up = fmaf(dl, p.invD, -p.vsi);
+  const float ub = up + p.zs, ur = up - p.zs;
+  float Hp, Fp, Hb, Fb, Hr, Fr;
+  faddeeva(up, p, C, Hp, Fp);
+  faddeeva(ub, p, C, Hb, Fb);
+  faddeeva(ur, p, C, Hr, Fr);
+
+  const float sH = 0.5f * (Hb + Hr), dHl = Hp - sH, dHv = Hr - Hb;
+  const float sF = 0.5f * (Fb + Fr), dFl = Fp - sF, dFv = Fr - Fb;
+  // absorption-matrix elements, psi = 0 frame
+  const float eI = fmaf(p.eta0, sH, fmaf(p.hs2, dHl, 1.f));
+  const float eQ = p.hs2 * dHl, eV = p.hc * dHv;
+  const float rQ = p.hs2 * dFl, rV = p.hc * dFv;
+  // Unno-Rachkovsky
+  const float eI2 = eI * eI;
+  const float Pi = fmaf(eQ, rQ, eV * rV);
+  const float R2 = fmaf(rQ, rQ, rV * rV);
+  const float T = fmaf(-eV, eV, fmaf(-eQ, eQ, eI2)) + R2;
+  const float Del = fmaf(eI2, T, -Pi * Pi);
+  const float rDel = frcp(Del);
+  const float NI = eI * (eI2 + R2);
+  const float NQ = fmaf(eI2, eQ, rQ * Pi);
+  const float NU = eI * fmaf(eQ, rV, -eV * rQ);
+  const float NV = fmaf(eI2, eV, rV * Pi);
+  const float Im = NI * rDel, Qh = -NQ * rDel, Uh = -NU * rDel, Vh = -NV * rDel;
+  const float I0 = frcp(fmaf(p.eta0, Hp, 1.f));
+  c[0] = fmaf(p.alpha, Im, p.oma * I0);
+  c[1] = Im - I0;
+  c[2] = Qh;
+  c[3] = Uh;
+  c[4] = Vh;
+  if (!DERIV) return;
+
+  // Eqs. 8-9
+  const float m2sp = -TWO_OVER_SQRT_PI;
+  const float alp = fmaf(p.twoa, Hp, fmaf(2.f * up, Fp, m2sp)), bep = fmaf(p.twoa, Fp, -2.f * up * Hp);
+  const float alb = fmaf(p.twoa, Hb, fmaf(2.f * ub, Fb, m2sp)), beb = fmaf(p.twoa, Fb, -2.f * ub * Hb);
+  const float alr = fmaf(p.twoa, Hr, fmaf(2.f * ur, Fr, m2sp)), ber = fmaf(p.twoa, Fr, -2.f * ur * Hr);
+
+  // d Delta / d(eta_I, eta_Q, eta_V, rho_Q, rho_V)
+  const float dDI = 2.f * eI * (T + eI2);
+  const float dDQ = -2.f * NQ, dDV = -2.f * NV;
+  const float dDq = 2.f * fmaf(eI2, rQ, -Pi * eQ);
+  const float dDw = 2.f * fmaf(eI2, rV, -Pi * eV);
+
+  // element tangents for gamma (per radian) and eta0
+  const float gI = p.hsin2g * dHl, gV = -p.hsg * dHv, gq = p.hsin2g * dFl, gw = -p.hsg * dFv;
+  const float nI = fmaf(p.s2h, dHl, sH), nQ = p.s2h * dHl, nV = p.cgh * dHv, nq = p.s2h * dFl,
+              nw = p.cgh * dFv;
+
+  // G[X][e] = d(output X)/d(element e), X = N_X/Delta with sign
+  float G[4][5];
+  {
+    const float a0 = fmaf(3.f, eI2, R2), a3 = 2.f * eI * rQ, a4 = 2.f * eI * rV;
+    G[0][0] = fmaf(-Im, dDI, a0) * rDel;
+    G[0][1] = -Im * dDQ * rDel;
+    G[0][2] = -Im * dDV * rDel;
+    G[0][3] = fmaf(-Im, dDq, a3) * rDel;
+    G[0][4] = fmaf(-Im, dDw, a4) * rDel;
+  }
+  {
+    G[1][0] = -fmaf(Qh, dDI, 2.f * eI * eQ) * rDel;
+    G[1][1] = -fmaf(Qh, dDQ, fmaf(rQ, rQ, eI2)) * rDel;
+    G[1][2] = -fmaf(Qh, dDV, rQ * rV) * rDel;
+    G[1][3] = -fmaf(Qh, dDq, fmaf(rQ, eQ, Pi)) * rDel;
+    G[1][4] = -fmaf(Qh, dDw, rQ * eV) * rDel;
+  }
+  {
+    G[2][0] = -fmaf(Uh, dDI, fmaf(eQ, rV, -eV * rQ)) * rDel;
+    G[2][1] = -fmaf(Uh, dDQ, eI * rV) * rDel;
+    G[2][2] = -fmaf(Uh, dDV, -eI * rQ) * rDel;
+    G[2][3] = -fmaf(Uh, dDq, -eI * eV) * rDel;
+    G[2][4] = -fmaf(Uh, dDw, eI * eQ) * rDel;
+  }
+  {
+    G[3][0] = -fmaf(Vh, dDI, 2.f * eI * eV) * rDel;
+    G[3][1] = -fmaf(Vh, dDQ, rV * rQ) * rDel;
+    G[3][2] = -fmaf(Vh, dDV, fmaf(rV, rV, eI2)) * rDel;
+    G[3][3] = -fmaf(Vh, dDq, rV * eQ) * rDel;
+    G[3][4] = -fmaf(Vh, dDw, fmaf(rV, eV, Pi)) * rDel;
+  }
+  // field-free component: dI0/dHp = -eta0 I0^2, dI0/deta0 = -Hp I0^2
+  const float k0 = -p.eta0 * I0 * I0 * p.oma;
+  const float d0v = k0 * bep, d0D = k0 * bep * up, d0a = k0 * alp;
+  const float d0e = -Hp * I0 * I0 * p.oma;
+
+#pragma unroll
+  for (int X = 0; X < 4; ++X) {
+    const float sc = (X == 0) ? p.alpha : 1.f;  // I_mix carries alpha
+    const float GI = G[X][0] * sc, GQ = G[X][1] * sc, GV = G[X][2] * sc, Gq = G[X][3] * sc,
+                Gw = G[X][4] * sc;
+    // sensitivities to the six profile values
+    const float GIQ = GI + GQ;
+    const float SHp = p.hs2 * GIQ;
+    const float x1 = fmaf(p.hI, GI, -p.hq * GQ), x2 = p.hc * GV;
+    const float SHb = x1 - x2, SHr = x1 + x2;
+    const float SFp = p.hs2 * Gq;
+    const float y1 = -p.hq * Gq, y2 = p.hc * Gw;
+    const float SFb = y1 - y2, SFr = y1 + y2;
+    // u-tangent weights t_c = SH_c beta_c - SF_c alpha_c
+    const float tp = fmaf(SHp, bep, -SFp * alp);
+    const float tb = fmaf(SHb, beb, -SFb * alb);
+    const float tr = fmaf(SHr, ber, -SFr * alr);
+    float dB = tb - tr;
+    float dv = tp + tb + tr;
+    float dD = fmaf(up, tp, fmaf(ub, tb, ur * tr));
+    float da = fmaf(SHp, alp, fmaf(SFp, bep, fmaf(SHb, alb, fmaf(SFb, beb, fmaf(SHr, alr, SFr * ber)))));
+    const float dg = fmaf(GIQ, gI, fmaf(GV, gV, fmaf(Gq, gq, Gw * gw)));
+    float de = fmaf(GI, nI, fmaf(GQ, nQ, fmaf(GV, nV, fmaf(Gq, nq, Gw * nw))));
+    if (X == 0) {
+      dv += d0v;
+      dD += d0D;
+      da += d0a;
+      de += d0e;
+    }
+    c[5 + 0 + X] = dB;
+    c[5 + 4 + X] = dg;
+    c[5 + 8 + X] = dv;
+    c[5 + 12 + X] = dD;
+    c[5 + 16 + X] = da;
+    c[5 + 20 + X] = de;
+  }
+}
+
+// Accumulate the filtered contributions of every synthesis point.
+template <int NOBS, bool DERIV>
+__device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, const Pix& p,
+                                                 const Consts& C, float (&acc)[NOBS][NACC]) {
+  constexpr int NC = DERIV ? NACC : 5;
+#pragma unroll
+  for (int i = 0; i < NOBS; ++i)
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) acc[i][m] = 0.f;
+  for (int k = 0; k < C.n_pts; ++k) {
+    const Point P = pts[k];  // wave-uniform: scalar loads
+    float c[NACC];
+    point_contrib<DERIV>(P.dl, p, C, c);
+    const uint32_t mask = __float_as_uint(P.w[6]);
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      if (mask & (1u << i)) {
+        const float w = P.w[i];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
+      }
+    }
+  }
+}
+
+// Per-pixel factors that turn accumulated sums into Stokes values and
+// Jacobian rows (API units).
+struct RowFactors {
+  float S0, S1, alpha, S1a, c2p, s2p;
+  float fB, fg, fv, fD;  // per-parameter factors for B, gamma, v, DlD
+};
+
+__device__ __forceinline__ void row_factors(const float* M, const Pix& p, const Consts& C,
+                                            RowFactors& f) {
+  f.S0 = M[7];
+  f.S1 = M[8];
+  f.alpha = M[9];
+  f.S1a = f.S1 * f.alpha;
+  sincosf(2.f * M[2] * DEG, &f.s2p, &f.c2p);
+  f.fB = C.cz * p.invD;
+  f.fg = DEG;
+  f.fv = -C.lam_over_c * p.invD;
+  f.fD = -p.invD;
+}
+
+// Stokes values (I, Q, U, V) of observed sample i and, with DERIV, the four
+// Jacobian rows J[s][0..9].
+template <bool DERIV>
+__device__ __forceinline__ void assemble_sample(const float* acc, float row_sum,
+                                                const RowFactors& f, float S[4],
+                                                float J[4][NPAR]) {
+  const float Q0 = f.S1a * acc[2], U0 = f.S1a * acc[3];
+  S[0] = fmaf(f.S0, row_sum, f.S1 * acc[0]);
+  S[1] = fmaf(f.c2p, Q0, -f.s2p * U0);
+  S[2] = fmaf(f.s2p, Q0, f.c2p * U0);
+  S[3] = f.S1a * acc[4];
+  if (!DERIV) return;
+  const float qf[6] = {f.fB, f.fg, f.fv, f.fD, 1.f, 1.f};
+  const int qidx[6] = {0, 1, 3, 4, 5, 6};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const float dI = acc[5 + 4 * q + 0] * f.S1 * qf[q];
+    const float dQ0 = acc[5 + 4 * q + 1] * f.S1a * qf[q];
+    const float dU0 = acc[5 + 4 * q + 2] * f.S1a * qf[q];
+    const float dV = acc[5 + 4 * q + 3] * f.S1a * qf[q];
+    J[0][qidx[q]] = dI;
+    J[1][qidx[q]] = fmaf(f.c2p, dQ0, -f.s2p * dU0);
+    J[2][qidx[q]] = fmaf(f.s2p, dQ0, f.c2p * dU0);
+    J[3][qidx[q]] = dV;
+  }
+  // azimuth: dQ/dpsi = -2U, dU/dpsi = 2Q (per radian)
+  J[0][2] = 0.f;
+  J[1][2] = -2.f * DEG * S[2];
+  J[2][2] = 2.f * DEG * S[1];
+  J[3][2] = 0.f;
+  // S0, S1, alpha
+  J[0][7] = row_sum;
+  J[1][7] = 0.f;
+  J[2][7] = 0.f;
+  J[3][7] = 0.f;
+  const float aQ0 = f.alpha * acc[2], aU0 = f.alpha * acc[3];
+  J[0][8] = acc[0];
+  J[1][8] = fmaf(f.c2p, aQ0, -f.s2p * aU0);
+  J[2][8] = fmaf(f.s2p, aQ0, f.c2p * aU0);
+  J[3][8] = f.alpha * acc[4];
+  const float sQ0 = f.S1 * acc[2], sU0 = f.S1 * acc[3];
+  J[0][9] = f.S1 * acc[1];
+  J[1][9] = fmaf(f.c2p, sQ0, -f.s2p * sU0);
+  J[2][9] = fmaf(f.s2p, sQ0, f.c2p * sU0);
+  J[3][9] = f.S1 * acc[4];
+}
+
+__host__ __device__ constexpr int pk(int p, int q) { return p * (p + 1) / 2 + q; }
+
+// ---------------------------------------------------------------------
+// Damped solve in float64 (Eqs. 3-5 with the diagonal scaled by 1 + eps):
+// equilibrate C = D^-1/2 H D^-1/2, Cholesky of C + eps I; frozen or
+// leverage-free parameters are decoupled (unit row, zero right-hand side).
+// Returns 0 on success, 1 if the factorisation broke down (the caller then
+// runs the eigen fallback), 2 if nothing is free.
+__device__ __forceinline__ int solve_cholesky(const float* H, const float* g, double eps,
+                                              uint32_t free_mask, double* delta, double* sc,
+                                              double* b) {
+  double maxd = 0.0;
+#pragma unroll
+  for (int p = 0; p < NPAR; ++p)
+    if ((free_mask >> p) & 1u) maxd = fmax(maxd, (double)H[pk(p, p)]);
+  int nact = 0;
+#pragma unroll
+  for (int p = 0; p < NPAR; ++p) {
+    const double d = (double)H[pk(p, p)];
+    const bool act = ((free_mask >> p) & 1u) && maxd > 0.0 && d > 1e-30 * maxd;
+    sc[p] = act ? 1.0 / sqrt(d) : 0.0;
+    nact += act ? 1 : 0;
+    delta[p] = 0.0;
+  }
+  if (nact == 0) return 2;
+  double L[55];
+#pragma unroll
+  for (int p = 0; p < NPAR; ++p) {
+#pragma unroll
+    for (int q = 0; q < p; ++q) L[pk(p, q)] = sc[p] * (double)H[pk(p, q)] * sc[q];
+    L[pk(p, p)] = (sc[p] != 0.0) ? 1.0 + eps : 1.0;
+    b[p] = sc[p] * (double)g[p];
+  }
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NPAR; ++j) {
+    double d = L[pk(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = fma(-L[pk(j, k)], L[pk(j, k)], d);
+    ok = ok && (d > 0.0) && (d < 1.0e300);
+    const double ljj = sqrt(fmax(d, 1e-300));
+    const double rl = 1.0 / ljj;
+    L[pk(j, j)] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < NPAR; ++i) {
+      double s = L[pk(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s = fma(-L[pk(i, k)], L[pk(j, k)], s);
+      L[pk(i, j)] = s * rl;
+    }
+  }
+  if (!ok) return 1;
+  double y[NPAR];
+#pragma unroll
+  for (int i = 0; i < NPAR; ++i) {
+    double s = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = fma(-L[pk(i, k)], y[k], s);
+    y[i] = s / L[pk(i, i)];
+  }
+#pragma unroll
+  for (int i = NPAR - 1; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < NPAR; ++k) s = fma(-L[pk(k, i)], y[k], s);
+    y[i] = s / L[pk(i, i)];
+  }
+#pragma unroll
+  for (int p = 0; p < NPAR; ++p) delta[p] = sc[p] * y[p];
+  return 0;
+}
+
+// Eigen (= SVD, the matrix being symmetric) fallback: cyclic Jacobi on
+// C + eps I held in a lane-strided float64 workspace (A at ws[e*stride],
+// eigenvectors at ws[(100 + e)*stride]); components with |lambda| below
+// 1e-12 of the largest are discarded.
+__device__ __noinline__ void solve_eigen_fallback(const float* H, double eps, const double* sc,
+                                                  const double* b, double* ws, int64_t stride,
+                                                  double* delta) {
+  auto A = [&](int i, int j) -> double& { return ws[(int64_t)(i * NPAR + j) * stride]; };
+  auto V = [&](int i, int j) -> double& { return ws[(int64_t)(100 + i * NPAR + j) * stride]; };
+  for (int i = 0; i < NPAR; ++i)
+    for (int j = 0; j < NPAR; ++j) {
+      const int hi = i > j ? pk(i, j) : pk(j, i);
+      double v = sc[i] * (double)H[hi] * sc[j];
+      if (i == j) v = (sc[i] != 0.0) ? 1.0 + eps : 1.0;
+      A(i, j) = v;
+      V(i, j) = (i == j) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int i = 0; i < NPAR; ++i)
+      for (int j = 0; j < NPAR; ++j) {
+        const double v = A(i, j);
+        if (i == j) dia += v * v;
+        else off += v * v;
+      }
+    if (!(off > 1e-32 * dia)) break;
+    for (int p = 0; p < NPAR - 1; ++p)
+      for (int q = p + 1; q < NPAR; ++q) {
+        const double apq = A(p, q);
+        if (apq == 0.0) continue;
+        const double th = (A(q, q) - A(p, p)) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
+        for (int k = 0; k < NPAR; ++k) {
+          const double akp = A(k, p), akq = A(k, q);
+          A(k, p) = c * akp - s * akq;
+          A(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < NPAR; ++k) {
+          const double apk = A(p, k), aqk = A(q, k);
+          A(p, k) = c * apk - s * aqk;
+          A(q, k) = s * apk + c * aqk;
+        }
+        for (int k = 0; k < NPAR; ++k) {
+          const double vkp = V(k, p), vkq = V(k, q);
+          V(k, p) = c * vkp - s * vkq;
+          V(k, q) = s * vkp + c * vkq;
+        }
+      }
+  }
+  double lmax = 0.0;
+  for (int j = 0; j < NPAR; ++j) lmax = fmax(lmax, fabs(A(j, j)));
+  double y[NPAR];
+  for (int i = 0; i < NPAR; ++i) y[i] = 0.0;
+  for (int j = 0; j < NPAR; ++j) {
+    const double lam = A(j, j);
+    if (!(fabs(lam) >= 1e-12 * lmax) || lam == 0.0) continue;
+    double pr = 0.0;
+    for (int i = 0; i < NPAR; ++i) pr = fma(V(i, j), b[i], pr);
+    pr /= lam;
+    for (int i = 0; i < NPAR; ++i) y[i] = fma(V(i, j), pr, y[i]);
+  }
+  for (int p = 0; p < NPAR; ++p) delta[p] = sc[p] * y[p];
+}
+
+// Table 2 (rows read top-down).
+__device__ __forceinline__ double eps_down(double e) {
+  return e > 1e4 ? e * 0.01 : (e >= 1e-4 ? e * 0.1 : e * 0.5);
+}
+__device__ __forceinline__ double eps_up(double e) {
+  return e < 1e-4 ? e * 100.0 : (e > 1e4 ? e * 10.0 : e * 2.0);
+}
+
+__device__ __forceinline__ double clampd(double x, double lo, double hi) {
+  return fmin(fmax(x, lo), hi);
+}
+
+// Box projection after the step: (-B, gamma) == (B, 180 - gamma); gamma is
+// even in itself and 360-periodic; psi is 180-periodic; then clip.
+__device__ __forceinline__ void project(double* M) {
+  if (M[0] < 0.0) {
+    M[0] = -M[0];
+    M[1] = 180.0 - M[1];
+  }
+  double g = M[1] - 360.0 * floor(M[1] * (1.0 / 360.0));
+  if (g > 180.0) g = 360.0 - g;
+  M[1] = clampd(g, 0.0, 180.0);
+  double ps = M[2] - 180.0 * floor(M[2] * (1.0 / 180.0));
+  M[2] = clampd(ps, 0.0, 180.0);
+  M[0] = clampd(M[0], 0.0, 5000.0);
+  M[3] = clampd(M[3], -20.0, 20.0);
+  M[4] = clampd(M[4], 5.0, 150.0);
+  M[5] = clampd(M[5], 0.0, 5.0);
+  M[6] = clampd(M[6], 1e-3, 1e3);
+  M[7] = clampd(M[7], -1.0, 3.0);
+  M[8] = clampd(M[8], 0.0, 5.0);
+  M[9] = clampd(M[9], 0.0, 1.0);
+}
+
+}  // namespace vfisv
