@@ -80,6 +80,7 @@ typedef struct {
 
 typedef struct {
   int n_active_fine;       /* synthesis points carrying a non-zero tap */
+  int n_taps;              /* non-zero taps kept over all rows         */
   double max_dropped_rel;  /* largest dropped tap mass / row sum       */
   double cz_mA_per_G;      /* Eq. 7 splitting constant                 */
 } vfisv_instrument_info;

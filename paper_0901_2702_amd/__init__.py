@@ -33,7 +33,8 @@ class _InstDesc(ctypes.Structure):
 
 
 class _InstInfo(ctypes.Structure):
-    _fields_ = [("n_active_fine", ctypes.c_int), ("max_dropped_rel", ctypes.c_double),
+    _fields_ = [("n_active_fine", ctypes.c_int), ("n_taps", ctypes.c_int),
+                ("max_dropped_rel", ctypes.c_double),
                 ("cz_mA_per_G", ctypes.c_double)]
 
 

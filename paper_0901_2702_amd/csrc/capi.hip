@@ -201,6 +201,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     inst->C.row_sum[i] = (float)ksum;
   }
   std::vector<Point> pts;
+  int n_taps = 0;
   for (int k = 0; k < nf; ++k) {
     Point p;
     std::memset(&p, 0, sizeof p);
@@ -208,7 +209,10 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     uint32_t mask = 0;
     for (int i = 0; i < no; ++i) {
       p.w[i] = (float)kept[(size_t)i * nf + k];
-      if (p.w[i] != 0.f) mask |= 1u << i;
+      if (p.w[i] != 0.f) {
+        mask |= 1u << i;
+        ++n_taps;
+      }
     }
     std::memcpy(&p.w[6], &mask, 4);
     if (mask) pts.push_back(p);
@@ -224,6 +228,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   inst->C.wL2 = ctx->wL * ctx->wL;
   inst->C.w2L = 2.f * ctx->wL;
   inst->info.n_active_fine = (int)pts.size();
+  inst->info.n_taps = n_taps;
   inst->info.max_dropped_rel = max_drop;
   inst->info.cz_mA_per_G = cz;
 

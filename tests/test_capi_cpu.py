@@ -1,0 +1,69 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/vfisv.h, and its host-side argument handling works."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_0901_2702_amd as vf
+    if not os.path.exists(vf.LIB_PATH):
+        from paper_0901_2702_amd import _build
+        _build.build()
+    return vf, vf.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vfisv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vfisv_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("vfisv_create", "vfisv_destroy", "vfisv_instrument_create",
+                     "vfisv_synthesize", "vfisv_invert", "vfisv_solve"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported():
+    vf, L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(vf.EXPORTS)
+
+
+def test_options_default_and_version():
+    vf, L = _lib()
+    o = vf._Options()
+    L.vfisv_options_default(ctypes.byref(o))
+    assert (o.max_iter, o.eps0, o.eps_max, o.rel_tol, o.free_mask, o.grid_waves) == \
+        (50, 1e-3, 1e8, 1e-5, 0x3FF, 0)
+    assert vf.version().startswith("vfisv-gfx950")
+
+
+def test_null_arguments_are_rejected():
+    vf, L = _lib()
+    assert L.vfisv_create(None, 0) == -1
+    assert b"NULL" in L.vfisv_last_error(None)
+    assert L.vfisv_destroy(None) == 0
+    assert L.vfisv_invert(None, None, 0, None, None, 0, None, None, None, None, None, None,
+                          None) == -1
+    assert L.vfisv_synthesize(None, None, 0, None, None, None, None, None) == -1
+    assert L.vfisv_solve(None, 0, None, None, None, 0, None, None, None) == -1
+    assert L.vfisv_instrument_info_get(None, None) == -1
+
+
+def test_no_cpu_fallback():
+    """Without a HIP device the binding refuses to run rather than compute on
+    the CPU."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    vf, _ = _lib()
+    with pytest.raises(vf.VfisvError):
+        vf.Context(0)
