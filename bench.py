@@ -1,15 +1,23 @@
-"""Benchmark: inverted pixels/s of the Milne-Eddington LM inversion on one MI355X.
+"""Benchmark: inverted pixels/s of the Milne-Eddington inversion on one MI355X,
+learned-start LM against plain LM at matched chi^2.
 
-One step = one vfisv_invert over the whole batch (every pixel fitted from its
-starting model to its exit), inputs resident in HBM.  Prints one JSON line.
+One step = one full inversion of the held-out batch (every pixel fitted from
+its starting model to its exit), inputs resident in HBM.  Prints one JSON
+line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Workload: 512 x 512 HMI-shaped pixels (Fe I 6173.3356 A, 6 Gaussian filters,
-101-point synthesis grid), parameters drawn from the cfg0 priors (seed 1001),
-N(0, 1e-3) noise, W = 1e6, plain Levenberg-Marquardt from the default model,
-max 50 iterations.  Observations are synthesised on the device by the
-library's own forward model from the seeded parameters and noise.
+Workload (the learned-initialiser configuration): HMI-shaped pixels (Fe I
+6173.3356 A, 6 Gaussian filters, 101-point synthesis grid), parameters from
+the cfg0 priors, N(0, 1e-3) noise, W = 1e6.
+* training set: 10M pixels (seed 1003), control set 250k (seed 1103);
+* held-out set: 1M pixels (seed 2003) -- the timed batch.
+Learned path: network start, <= 15 LM trials, plain-LM fallback (<= 50 trials
+from the default model) for pixels with reduced chi^2 above the 0.99
+quantile.  Plain path: LM from the default model, <= 50 trials.
+Observations are synthesised on the device by the library's forward model
+from host-drawn (seeded numpy) parameters and noise; the network is trained
+before the timed region (its time is reported separately).
 """
 import argparse
 import json
@@ -20,12 +28,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks used for the roofline fraction.
+# Published MI355X peak used for the roofline fraction.
 PEAK_FP32_TFLOPS = 157.3
 
 # Algorithmic float32 work per unit, counted from the formula sequence of the
-# synthesis ("Work per unit"): per synthesis point, per filter tap,
-# per observed sample / Stokes row, plus the float64 solve.
+# synthesis: per synthesis point, per filter tap, per observed sample, plus
+# the float64 solve.
 FLOP_POINT_VALUES = 431      # 3 Faddeeva (124 each), absorption matrix, UR, mixing
 FLOP_POINT_JAC_EXTRA = 379   # Eqs. 8-9, element and parameter tangents
 FLOP_TAP_VALUES = 8          # 4 normalised Stokes values per tap
@@ -45,9 +53,13 @@ def work_model(n_pts, n_taps, n_obs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=512 * 512)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--train-samples", type=int, default=10_000_000)
+    ap.add_argument("--control-samples", type=int, default=250_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     args = ap.parse_args()
@@ -62,78 +74,139 @@ def main():
 
     import paper_0901_2702_amd as vf
     import workloads as wl
+    from paper_0901_2702_amd import learned
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
 
     spec = wl.hmi_instrument()
-    n = args.n
-    seed = wl.CONFIGS["cfg1"]["seed"]
-    P = wl.draw_params(n, seed)
-    noise = wl.draw_noise(n, spec.n_obs, seed)
-    W = wl.weights(spec.n_obs)
-
     ctx = vf.Context(0)
     dev = ctx.device
     inst = vf.Instrument.from_spec(ctx, spec)
     stream = torch.cuda.current_stream(dev)
-    P_d = torch.tensor(P.astype(np.float32), device=dev)
-    obs = vf.synthesize(ctx, inst, P_d, noise=torch.tensor(noise.astype(np.float32), device=dev))
-    W_d = torch.tensor(W, device=dev)
-    out = dict(params=torch.empty((n, 10), device=dev, dtype=torch.float32),
-               chi2=torch.empty(n, device=dev, dtype=torch.float64),
-               iters=torch.empty(n, device=dev, dtype=torch.int32),
-               status=torch.empty(n, device=dev, dtype=torch.int32))
+    n_obs = spec.n_obs
+
+    # ---- training (untimed) -----------------------------------------------
+    t0 = time.perf_counter()
+    S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
+                                           wl.CONFIGS["cfg3_train"]["seed"], wl.draw_params,
+                                           wl.draw_noise)
+    S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
+                                           wl.CONFIGS["cfg3_control"]["seed"], wl.draw_params,
+                                           wl.draw_noise)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log("training data %.1f s" % t_data)
+    net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
+                               batch=4096, lr=2e-3, log=log)
+    del S_tr
+    torch.cuda.empty_cache()
+
+    # ---- held-out batch -----------------------------------------------------
+    n = args.n
+    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    P = wl.draw_params(n, seed)
+    noise = wl.draw_noise(n, n_obs, seed)
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                        noise=torch.tensor(noise.astype(np.float32), device=dev))
+    obs2 = obs.view(n, 4 * n_obs)
+    W = torch.tensor(wl.weights(n_obs), device=dev)
+
+    def alloc():
+        return dict(params=torch.empty((n, 10), device=dev, dtype=torch.float32),
+                    chi2=torch.empty(n, device=dev, dtype=torch.float64),
+                    iters=torch.empty(n, device=dev, dtype=torch.int32),
+                    status=torch.empty(n, device=dev, dtype=torch.int32))
+
+    out_l, out_p = alloc(), alloc()
     opts = vf.Options()
 
-    for _ in range(args.warmup):
-        vf.invert(ctx, inst, obs, W_d, opts=opts, out=out)
-    torch.cuda.synchronize()
+    def learned_step():
+        learned.invert_learned(ctx, inst, net, obs2, W, opts=opts,
+                               learned_max_iter=args.learned_max_iter, out=out_l)
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        vf.invert(ctx, inst, obs, W_d, opts=opts, out=out)
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    kern_ms = float(np.mean(ev_ms))
-    ms_per_step = wall * 1e3 / args.steps
-    value = n / (ms_per_step * 1e-3)
+    def plain_step():
+        vf.invert(ctx, inst, obs, W, opts=opts, out=out_p)
 
-    c = ctx.counters()
-    st = out["status"].cpu().numpy()
-    it = out["iters"].cpu().numpy()
-    chi = out["chi2"].cpu().numpy()
-    f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"],
-                                         spec.n_obs)
-    alg_flops = (c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac)
-    exec_flops = c["passes"] * f_jac + c["trials"] * f_solve
-    achieved = alg_flops / (kern_ms * 1e-3) / 1e12
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return wall * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    ms_l, ev_l = timed(learned_step, args.steps)
+    c_l = ctx.counters()
+    ms_p, ev_p = timed(plain_step, max(3, args.steps // 2))
+    c_p = ctx.counters()
+
+    lc, pc = out_l["chi2"].cpu().numpy(), out_p["chi2"].cpu().numpy()
+    li, pi = out_l["iters"].cpu().numpy(), out_p["iters"].cpu().numpy()
+    ls, ps = out_l["status"].cpu().numpy(), out_p["status"].cpu().numpy()
+    fb = (ls & vf.FALLBACK_USED) != 0
+
+    f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
+
+    def alg(c):
+        return c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
+
+    achieved = alg(c_p) / (ev_p * 1e-3) / 1e12
+    executed = (c_p["passes"] * f_jac + c_p["trials"] * f_solve) / (ev_p * 1e-3) / 1e12
+
+    def q(a, p):
+        return float(np.quantile(a, p))
 
     result = {
         "metric": "inverted pixels/s on 1 MI355X, learned-init LM vs plain LM at matched chi^2",
-        "value": round(value, 1),
+        "value": round(n / (ms_l * 1e-3), 1),
         "unit": "pixels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(ms_l, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64 (LM), bf16/f32 (network)",
         "data": "synthetic",
         "config": {
-            "workload": "512x512 HMI-shaped pixels (cfg0 priors, seed 1001, noise 1e-3), "
-                        "plain LM from the default model, max 50 iterations",
-            "init": "default model (plain LM); learned init not yet in this build",
+            "workload": "1M held-out HMI-shaped pixels (cfg0 priors, seed 2003, noise 1e-3); "
+                        "learned start + <= %d LM trials + plain-LM fallback"
+                        % args.learned_max_iter,
             "pixels": n,
-            "n_obs": spec.n_obs,
-            "synthesis_points": inst.info["n_active_fine"],
-            "filter_taps": inst.info["n_taps"],
-            "grid_waves": c["grid_waves"],
+            "n_obs": n_obs,
+            "network": "%d -> 256 -> 256 -> 256 -> 10, GELU, bf16 MFMA" % (4 * n_obs),
+            "train_pixels": args.train_samples,
+            "control_pixels": args.control_samples,
+        },
+        "plain_lm": {
+            "value": round(n / (ms_p * 1e-3), 1), "unit": "pixels/s", "ms_per_step": round(ms_p, 4),
+            "mean_iters": float(pi.mean()), "status_counts": np.bincount(ps, minlength=4).tolist(),
+        },
+        "speedup_vs_plain": round(ms_p / ms_l, 3),
+        "matched_chi2": {
+            "median_learned": q(lc, 0.5), "median_plain": q(pc, 0.5),
+            "p90_learned": q(lc, 0.9), "p90_plain": q(pc, 0.9),
+            "p99_learned": q(lc, 0.99), "p99_plain": q(pc, 0.99),
+            "frac_learned_worse_1pct": float(np.mean(lc > 1.01 * pc)),
+            "frac_learned_better_1pct": float(np.mean(lc < 0.99 * pc)),
+            "frac_chi2_below_2": [float(np.mean(lc < 2.0)), float(np.mean(pc < 2.0))],
+            "fallback_rate": float(fb.mean()),
+            "mean_iters_learned": float(li.mean()),
+        },
+        "training": {
+            "seconds": round(tinfo["seconds"], 2), "data_seconds": round(t_data, 2),
+            "epochs_run": len(tinfo["history"]), "best_epoch": tinfo["best_epoch"],
+            "control_mse": round(tinfo["best_control_mse"], 5), "steps": tinfo["steps"],
         },
         "roofline": {
             "bound": "alu",
@@ -142,17 +215,13 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": None,
-            "kernel": "lm_kernel",
-            "kernel_ms": round(kern_ms, 4),
-            "executed_tflops": round(exec_flops / (kern_ms * 1e-3) / 1e12, 3),
-        },
-        "work": {
-            "trials": c["trials"], "accepts": c["accepts"], "passes": c["passes"],
-            "svd_fallbacks": c["svd_fallbacks"], "mean_iters": float(it.mean()),
-            "status_counts": np.bincount(st, minlength=4).tolist(),
-            "chi2_median": float(np.median(chi)),
+            "kernel": "lm_kernel (plain-LM leg: one launch per step)",
+            "kernel_ms": round(ev_p, 4),
+            "executed_tflops": round(executed, 3),
             "flop_per_trial": f_trial, "flop_per_jacobian_pass": f_jac,
             "flop64_per_solve": f_solve,
+            "work_plain": {k: c_p[k] for k in ("trials", "accepts", "passes", "pixels")},
+            "work_learned": {k: c_l[k] for k in ("trials", "accepts", "passes", "pixels")},
         },
     }
 
@@ -162,13 +231,14 @@ def main():
         oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
         obs_cpu = (oracle.forward_batch(oi, P[:m]) + noise[:m]).astype(np.float32)
         t1 = time.perf_counter()
-        ref = oracle.invert(oi, obs_cpu, W)
+        ref = oracle.invert(oi, obs_cpu, wl.weights(n_obs))
         dt = time.perf_counter() - t1
         result["cpu_baseline"] = {
             "value": round(m / dt, 2), "unit": "pixels/s", "cores": ref["threads"],
             "kind": "oracle",
-            "sample": "first %d of the %d pixels (same parameters and noise, observations "
-                      "synthesised by the FP64 oracle), plain LM, max 50 iterations" % (m, n),
+            "sample": "first %d of the %d held-out pixels (same parameters and noise, "
+                      "observations synthesised by the FP64 oracle), plain LM from the default "
+                      "model, max 50 iterations" % (m, n),
             "seconds": round(dt, 3),
         }
     print(json.dumps(result), flush=True)

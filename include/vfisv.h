@@ -191,6 +191,81 @@ int vfisv_solve(vfisv_ctx *ctx, int64_t n, const float *H, const float *g,
                 const double *eps, uint32_t free_mask, double *delta,
                 int32_t *code, void *stream);
 
+/* ---- learned initialiser (Sect. 5: network-proposed starting model) --- */
+
+/* A multilayer perceptron n_in -> 256 -> 256 -> 256 -> 10 (exact-erf GELU,
+ * bfloat16 weights and activations on the matrix cores, float32
+ * accumulation, float32 master weights and Adam state).  Inputs are the
+ * pixel's Stokes samples [4][n_obs] flattened, standardised by
+ * (x - in_mean) / in_std.  Outputs are ten codes: the field vector
+ * (B cos g, B sin g cos 2psi, B sin g sin 2psi) / 3000, then v, Doppler
+ * width, a, eta0, S0, S1, alpha standardised by out_mean/out_std [7].  The
+ * library owns weights, optimiser state and work buffers. */
+typedef struct vfisv_mlp vfisv_mlp;
+
+/* New network with He-initialised weights (seeded).  Host arrays are
+ * copied.  Errors: VFISV_E_INVALID (n_in outside 1..4096, non-finite or
+ * non-positive std), VFISV_E_NOMEM. */
+int vfisv_mlp_create(vfisv_ctx *ctx, int n_in, const float *in_mean, const float *in_std,
+                     const float *out_mean, const float *out_std, uint64_t seed,
+                     vfisv_mlp **out);
+int vfisv_mlp_destroy(vfisv_mlp *mlp);
+
+/* Number of float32 parameters (packed W1 [K0][256], b1, W2, b2, W3, b3,
+ * W4 [256][32], b4 [32], K0 = n_in rounded up to 32; -1 if mlp is NULL). */
+int64_t vfisv_mlp_num_params(const vfisv_mlp *mlp);
+
+/* Copy the float32 parameters to / from host memory (synchronising).
+ * set_params also clears the Adam state. n must equal num_params. */
+int vfisv_mlp_get_params(vfisv_mlp *mlp, float *host, int64_t n);
+int vfisv_mlp_set_params(vfisv_mlp *mlp, const float *host, int64_t n);
+
+/* Inference for n pixels: stokes dev [n][4*n_obs] -> codes dev [n][10]
+ * and/or params dev [n][10] (decoded, projected into the parameter box).
+ * At least one output must be given.  Internal buffers grow on first use
+ * (a synchronising allocation). */
+int vfisv_mlp_forward(vfisv_ctx *ctx, vfisv_mlp *mlp, int64_t n, const float *stokes,
+                      float *codes, float *params, void *stream);
+
+/* Gradient of the mean squared error over all n x 10 codes (no update):
+ * targets dev [n][10]; grad dev [num_params]; loss dev [1] (sum of squared
+ * errors) or NULL.  n must be a positive multiple of 32. */
+int vfisv_mlp_gradient(vfisv_ctx *ctx, vfisv_mlp *mlp, int64_t n, const float *stokes,
+                       const float *targets, float *grad, double *loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch of rows
+ * `rows` (dev int32 [batch], indices into stokes [.][4*n_obs] and targets
+ * [.][10]); batch a positive multiple of 32.  The summed squared error
+ * accumulates until vfisv_mlp_take_loss. */
+int vfisv_mlp_train_step(vfisv_ctx *ctx, vfisv_mlp *mlp, const float *stokes,
+                         const float *targets, const int32_t *rows, int batch, float lr,
+                         void *stream);
+
+/* Summed squared error of the training steps since the last call
+ * (synchronising; resets the sum). */
+int vfisv_mlp_take_loss(vfisv_mlp *mlp, double *sum_sq);
+
+/* Versioned binary file (magic, version, sizes, normalisation, parameters,
+ * FNV-1a checksum).  load rejects other versions and bad checksums. */
+int vfisv_mlp_save(vfisv_mlp *mlp, const char *path);
+int vfisv_mlp_load(vfisv_ctx *ctx, const char *path, vfisv_mlp **out);
+
+/* Learned-start inversion: the network proposes each pixel's starting
+ * model, LM runs at most learned_max_iter trials from it, and every pixel
+ * whose reduced chi^2 then exceeds chi2_accept (<= 0: the 0.99 quantile of
+ * chi^2_dof / dof) is re-fitted by plain LM from the default model with
+ * opt->max_iter trials; the better fit is kept, iters counts the trials of
+ * both runs and status gets bit 16 (VFISV_FALLBACK_USED).  Buffers as in
+ * vfisv_invert (W shared or per pixel); the network must take 4*n_obs
+ * inputs.  Library scratch (about 100 bytes per pixel) grows on first use
+ * (a synchronising allocation). */
+#define VFISV_FALLBACK_USED 16
+int vfisv_invert_learned(vfisv_ctx *ctx, const vfisv_instrument *inst, vfisv_mlp *mlp,
+                         int64_t n, const float *stokes, const float *W, int W_per_pixel,
+                         const vfisv_options *opt, int learned_max_iter, double chi2_accept,
+                         float *params, double *chi2, int32_t *iters, int32_t *status,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

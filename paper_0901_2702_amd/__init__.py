@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvfisv.so")
 NPAR = 10
 CONVERGED, MAX_ITER, STALLED, NONFINITE = 0, 1, 2, 3
+FALLBACK_USED = 16
 PARAM_NAMES = ("B", "gamma", "psi", "v_los", "doppler_width", "damping", "eta0", "S0", "S1",
                "alpha")
 
@@ -54,7 +55,10 @@ class _Counters(ctypes.Structure):
 EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_instrument_create", "vfisv_instrument_info_get", "vfisv_instrument_destroy",
            "vfisv_options_default", "vfisv_synthesize", "vfisv_invert", "vfisv_get_counters",
-           "vfisv_solve")
+           "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params",
+           "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
+           "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
+           "vfisv_mlp_load", "vfisv_invert_learned")
 
 _LIB = None
 

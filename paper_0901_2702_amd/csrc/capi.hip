@@ -10,41 +10,101 @@
 #include <string>
 #include <vector>
 
+#include "capi_internal.h"
 #include "kernels.h"
 #include "vfisv.h"
 
 using namespace vfisv;
 
-struct vfisv_ctx {
-  int device = 0;
-  int num_cus = 0;
-  int lm_blocks_per_cu = 1;
-  unsigned long long* d_work = nullptr;
-  double* d_ws = nullptr;
-  int64_t ws_lanes = 0;
-  float wc[NW + 1];
-  float wL = 0.f;
-  std::string err;
-};
-
-struct vfisv_instrument {
-  vfisv_ctx* ctx = nullptr;
-  Point* d_pts = nullptr;
-  Consts C;
-  vfisv_instrument_info info;
-};
-
 static thread_local std::string g_create_err;
 
-static int fail(vfisv_ctx* ctx, int code, const std::string& msg) {
+namespace vfisv_capi {
+
+int fail(vfisv_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
   else g_create_err = msg;
   return code;
 }
 
-static int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what) {
+int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, VFISV_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn) {
+  if (!inst) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument is NULL");
+  if (inst->ctx != ctx)
+    return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument of another context");
+  return VFISV_OK;
+}
+
+int grid_for(int64_t n, int64_t cap) {
+  const int64_t waves = (n + 63) / 64;
+  return (int)(waves < cap ? (waves < 1 ? 1 : waves) : cap);
+}
+
+int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_options* opt,
+                  vfisv_options* out, double* inv_dof) {
+  vfisv_options o;
+  vfisv_options_default(&o);
+  if (opt) o = *opt;
+  if (o.max_iter < 0) return fail(ctx, VFISV_E_INVALID, "options: max_iter < 0");
+  if (!(o.eps0 > 0.0) || !(o.eps_max > 0.0) || !(o.rel_tol >= 0.0) || !std::isfinite(o.eps0) ||
+      !std::isfinite(o.rel_tol))
+    return fail(ctx, VFISV_E_INVALID, "options: eps0, eps_max must be > 0 and rel_tol >= 0");
+  if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "options: grid_waves < 0");
+  o.free_mask &= 0x3FFu;
+  int nfree = 0;
+  for (int p = 0; p < NPAR; ++p) nfree += (o.free_mask >> p) & 1u;
+  const int dof = 4 * inst->C.n_obs - nfree;
+  if (dof <= 0)
+    return fail(ctx, VFISV_E_INVALID, "options: 4*n_obs - free parameters must be > 0");
+  *out = o;
+  *inv_dof = 1.0 / (double)dof;
+  return VFISV_OK;
+}
+
+int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+               const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
+               const float* W, int W_pp, const float* init, const vfisv_options& o,
+               double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
+               hipStream_t s, bool reset_all) {
+  LMArgs a;
+  a.C = inst->C;
+  a.pts = inst->d_pts;
+  a.stokes = stokes;
+  a.W = W;
+  a.init = init;
+  a.params = params;
+  a.chi2 = chi2;
+  a.iters = iters;
+  a.status = status;
+  a.work = ctx->d_work;
+  a.ws = ctx->d_ws;
+  a.n = n;
+  a.n_dev = n_dev;
+  a.idx = idx;
+  a.eps0 = o.eps0;
+  a.eps_max = o.eps_max;
+  a.rel_tol = o.rel_tol;
+  a.inv_dof = inv_dof;
+  a.max_iter = o.max_iter;
+  a.W_pp = W_pp ? 1 : 0;
+  a.free_mask = o.free_mask & 0x3FFu;
+  int64_t cap = (int64_t)ctx->num_cus * ctx->lm_blocks_per_cu;
+  if (o.grid_waves > 0) cap = o.grid_waves;
+  if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
+  const int grid = grid_for(n, cap);
+  a.ws_stride = (int64_t)grid * 64;
+  hipError_t e = launch_reset(ctx->d_work, reset_all, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
+  e = launch_lm(a, grid, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert launch");
+  return VFISV_OK;
+}
+
+}  // namespace vfisv_capi
+
+using namespace vfisv_capi;
 
 // Weideman (1994) coefficients: with L = sqrt(N / sqrt(2)) and
 // f(t) = exp(-t^2) (L^2 + t^2), a_n is the n-th Fourier cosine coefficient of
@@ -73,7 +133,7 @@ static void weideman_coefficients(int N, double* L_out, double* a /* [N + 1] */)
 
 extern "C" {
 
-const char* vfisv_version(void) { return "vfisv-gfx950 0.1.0"; }
+const char* vfisv_version(void) { return "vfisv-gfx950 0.2.0"; }
 
 const char* vfisv_last_error(const vfisv_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_err.c_str();
@@ -116,7 +176,7 @@ int vfisv_create(vfisv_ctx** out, int device) {
     delete c;
     return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: counter allocation");
   }
-  e = launch_reset(c->d_work, nullptr);
+  e = launch_reset(c->d_work, true, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     hipFree(c->d_ws);
@@ -139,6 +199,7 @@ int vfisv_destroy(vfisv_ctx* ctx) {
   hipDeviceSynchronize();
   hipFree(ctx->d_ws);
   hipFree(ctx->d_work);
+  if (ctx->d_learn) hipFree(ctx->d_learn);
   delete ctx;
   return VFISV_OK;
 }
@@ -243,8 +304,8 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     delete inst;
     return fail(ctx, VFISV_E_NOMEM, "instrument_create: device allocation");
   }
-  if (!pts.empty()) e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(),
-                                  hipMemcpyHostToDevice);
+  if (!pts.empty())
+    e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(inst->d_pts);
     delete inst;
@@ -267,18 +328,6 @@ int vfisv_instrument_destroy(vfisv_instrument* inst) {
   hipFree(inst->d_pts);
   delete inst;
   return VFISV_OK;
-}
-
-static int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn) {
-  if (!inst) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument is NULL");
-  if (inst->ctx != ctx)
-    return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": instrument of another context");
-  return VFISV_OK;
-}
-
-static int grid_for(int64_t n, int64_t cap) {
-  const int64_t waves = (n + 63) / 64;
-  return (int)(waves < cap ? (waves < 1 ? 1 : waves) : cap);
 }
 
 int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
@@ -313,56 +362,18 @@ int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const 
   int rc = check_inst(ctx, inst, "invert");
   if (rc) return rc;
   vfisv_options o;
-  vfisv_options_default(&o);
-  if (opt) o = *opt;
+  double inv_dof;
+  rc = check_options(ctx, inst, opt, &o, &inv_dof);
+  if (rc) return rc;
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert: n < 0");
-  if (o.max_iter < 0) return fail(ctx, VFISV_E_INVALID, "invert: max_iter < 0");
-  if (!(o.eps0 > 0.0) || !(o.eps_max > 0.0) || !(o.rel_tol >= 0.0) ||
-      !std::isfinite(o.eps0) || !std::isfinite(o.rel_tol))
-    return fail(ctx, VFISV_E_INVALID, "invert: eps0, eps_max must be > 0 and rel_tol >= 0");
-  if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "invert: grid_waves < 0");
-  const uint32_t mask = o.free_mask & 0x3FFu;
-  int nfree = 0;
-  for (int p = 0; p < NPAR; ++p) nfree += (mask >> p) & 1u;
-  const int dof = 4 * inst->C.n_obs - nfree;
-  if (dof <= 0) return fail(ctx, VFISV_E_INVALID, "invert: 4*n_obs - free parameters must be > 0");
   if (n == 0) return VFISV_OK;
+  if (n > INT32_MAX) return fail(ctx, VFISV_E_INVALID, "invert: n must be < 2^31");
   if (!stokes || !W || !params || !chi2 || !iters)
     return fail(ctx, VFISV_E_INVALID, "invert: NULL buffer");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-
-  LMArgs a;
-  a.C = inst->C;
-  a.pts = inst->d_pts;
-  a.stokes = stokes;
-  a.W = W;
-  a.init = init;
-  a.params = params;
-  a.chi2 = chi2;
-  a.iters = iters;
-  a.status = status;
-  a.work = ctx->d_work;
-  a.ws = ctx->d_ws;
-  a.n = n;
-  a.eps0 = o.eps0;
-  a.eps_max = o.eps_max;
-  a.rel_tol = o.rel_tol;
-  a.inv_dof = 1.0 / (double)dof;
-  a.max_iter = o.max_iter;
-  a.W_pp = W_per_pixel ? 1 : 0;
-  a.free_mask = mask;
-  int64_t cap = (int64_t)ctx->num_cus * ctx->lm_blocks_per_cu;
-  if (o.grid_waves > 0) cap = o.grid_waves;
-  if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
-  const int grid = grid_for(n, cap);
-  a.ws_stride = (int64_t)grid * 64;
-  hipStream_t s = (hipStream_t)stream;
-  e = launch_reset(ctx->d_work, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
-  e = launch_lm(a, grid, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "invert launch");
-  return VFISV_OK;
+  return enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, o, inv_dof,
+                    params, chi2, iters, status, (hipStream_t)stream, true);
 }
 
 int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {

@@ -1,0 +1,52 @@
+// Library-internal definitions shared by the C-ABI translation units
+// (capi.hip, mlp_capi.hip).  Not part of the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "kernels.h"
+#include "vfisv.h"
+
+struct vfisv_ctx {
+  int device = 0;
+  int num_cus = 0;
+  int lm_blocks_per_cu = 1;
+  unsigned long long* d_work = nullptr;  // WORK_SLOTS counters
+  double* d_ws = nullptr;                // eigen-fallback workspace
+  int64_t ws_lanes = 0;
+  float wc[vfisv::NW + 1];
+  float wL = 0.f;
+  // learned-start scratch (grown on demand)
+  void* d_learn = nullptr;
+  size_t learn_bytes = 0;
+  std::string err;
+};
+
+struct vfisv_instrument {
+  vfisv_ctx* ctx = nullptr;
+  vfisv::Point* d_pts = nullptr;
+  vfisv::Consts C;
+  vfisv_instrument_info info;
+};
+
+namespace vfisv_capi {
+
+int fail(vfisv_ctx* ctx, int code, const std::string& msg);
+int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what);
+int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn);
+int grid_for(int64_t n, int64_t cap);
+int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_options* opt,
+                  vfisv_options* out, double* inv_dof);
+
+// Enqueue the persistent LM kernel.  With idx != NULL the pixels are
+// idx[0 .. count), count read from n_dev on the device (n bounds the grid);
+// reset_all clears every work counter, otherwise only the queue head.
+int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+               const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
+               const float* W, int W_pp, const float* init, const vfisv_options& o,
+               double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
+               hipStream_t s, bool reset_all);
+
+}  // namespace vfisv_capi

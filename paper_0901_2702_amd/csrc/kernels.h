@@ -26,7 +26,9 @@ struct LMArgs {
   unsigned long long* work;
   double* ws;
   int64_t ws_stride;
-  int64_t n;
+  int64_t n;                         // pixels, unless n_dev is given
+  const unsigned long long* n_dev;   // device-side pixel count, or NULL
+  const int32_t* idx;                // pixel ids to invert, or NULL (0..n-1)
   double eps0, eps_max, rel_tol, inv_dof;
   int max_iter;
   int W_pp;
@@ -55,7 +57,7 @@ struct SolveArgs {
   uint32_t free_mask;
 };
 
-hipError_t launch_reset(unsigned long long* work, hipStream_t s);
+hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s);
 hipError_t launch_lm(const LMArgs& a, int grid, hipStream_t s);
 hipError_t launch_synth(const SynthArgs& a, bool deriv, int grid, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);

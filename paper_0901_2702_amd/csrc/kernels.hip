@@ -20,8 +20,8 @@
 
 namespace vfisv {
 
-__global__ void reset_work_kernel(unsigned long long* work) {
-  if (threadIdx.x < WORK_SLOTS) work[threadIdx.x] = 0ull;
+__global__ void reset_work_kernel(unsigned long long* work, int all) {
+  if (threadIdx.x < (all ? WORK_SLOTS : 1)) work[threadIdx.x] = 0ull;
 }
 
 __device__ __forceinline__ unsigned long long bcast_lane0(unsigned long long v) {
@@ -46,6 +46,7 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   const int lane = threadIdx.x;
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
 
+  const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
   bool live = false, fresh = false, exhausted = false;
   int64_t pix = 0;
   float Mb[NPAR], Mc[NPAR];
@@ -65,8 +66,8 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
         if (need) {
           const int rank = __popcll(nm & ((1ull << lane) - 1ull));
           const unsigned long long idx = base + (unsigned long long)rank;
-          if (idx < (unsigned long long)A.n) {
-            pix = (int64_t)idx;
+          if (idx < n_total) {
+            pix = A.idx ? (int64_t)A.idx[idx] : (int64_t)idx;
             const float* obs = A.stokes + pix * ROWS;
             const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
             bool finite = true;
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(64) void solve_kernel(const SolveArgs A) {
 
 // ---- launch helpers (host) --------------------------------------------------
 
-hipError_t launch_reset(unsigned long long* work, hipStream_t s) {
-  reset_work_kernel<<<1, 64, 0, s>>>(work);
+hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
+  reset_work_kernel<<<1, 64, 0, s>>>(work, all ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -1,0 +1,465 @@
+// Learned initialiser on gfx950: a multilayer perceptron (K0 -> 256 -> 256 ->
+// 256 -> 32 (10 used), exact-erf GELU) evaluated and trained with bfloat16 MFMA
+// (v_mfma_f32_16x16x32_bf16, float32 accumulation) and Adam on float32
+// master weights.
+//
+// The paper initialises B, gamma and v_los with small back-propagation
+// networks trained on synthetic filtered noisy profiles, with early stopping
+// on a control set (Sect. 5).  Here one network proposes all ten starting
+// parameters, trained on profiles synthesised by the library's own forward
+// model.
+//
+// Every GEMM is C = A . Bt^T with A [M][Kd] and Bt [N][Kd] both contiguous
+// along Kd, so each lane fetches its 8-element MFMA fragments with one
+// 16-byte load:  forward  X [B][K] . Wt [N][K]^T;  input gradient
+// dZ [B][N] . W [K][N]^T;  weight gradient dZ^T [N][B] . X^T [K][B]^T, split
+// along the batch into MLP_SPLITK partial sums that the Adam kernel adds.
+#include <hip/hip_runtime.h>
+
+#include "me_device.h"
+#include "mlp.h"
+
+namespace vfisv {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+// ---- GEMM ------------------------------------------------------------------
+// One wave computes a 64 x (16 NB) tile of C over the Kd range
+// [z * k_chunk, min((z + 1) * k_chunk, Kd)).  Kd and k_chunk are multiples
+// of 32.  MFMA 16x16x32 lane layout: lane l feeds A row (l & 15) and B
+// column (l & 15) with k = 8 (l >> 4) .. +7, and receives C rows
+// 4 (l >> 4) .. +3 of column (l & 15).
+template <int NB, class Epi>
+__global__ __launch_bounds__(64) void gemm_abt(const bf16* __restrict__ A, int64_t lda,
+                                               const bf16* __restrict__ Bt, int64_t ldb,
+                                               int64_t M, int N, int64_t Kd, int64_t k_chunk,
+                                               Epi epi) {
+  const int l = threadIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * 16 * NB;
+  const int64_t kbeg = (int64_t)blockIdx.z * k_chunk;
+  const int64_t kend = kbeg + k_chunk < Kd ? kbeg + k_chunk : Kd;
+  const int lr = l & 15, lk = (l >> 4) * 8;
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 zero;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) zero[i] = (bf16)0.f;
+  for (int64_t k = kbeg; k < kend; k += 32) {
+    bf16x8 a[4], b[NB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int64_t row = m0 + rb * 16 + lr;
+      a[rb] = row < M ? *(const bf16x8*)(A + row * lda + k + lk) : zero;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int col = n0 + cb * 16 + lr;
+      b[cb] = col < N ? *(const bf16x8*)(Bt + (int64_t)col * ldb + k + lk) : zero;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = m0 + rb * 16 + (l >> 4) * 4 + j;
+        const int col = n0 + cb * 16 + lr;
+        if (row < M && col < N) epi(row, col, acc[rb][cb][j], blockIdx.z);
+      }
+}
+
+struct EpiHidden {  // z = acc + b; y = gelu(z)
+  const float* bias;
+  bf16* Y;
+  bf16* Yt;
+  float* Z;
+  int64_t ld, ldt;
+  __device__ void operator()(int64_t row, int col, float acc, int) const {
+    const float z = acc + bias[col];
+    if (Z) Z[row * ld + col] = z;
+    const bf16 y = (bf16)gelu(z);
+    Y[row * ld + col] = y;
+    if (Yt) Yt[(int64_t)col * ldt + row] = y;
+  }
+};
+
+struct EpiOut {  // linear output layer
+  const float* bias;
+  float* Y4;
+  __device__ void operator()(int64_t row, int col, float acc, int) const {
+    Y4[row * MLP_OUT + col] = acc + bias[col];
+  }
+};
+
+struct EpiBwdX {  // dz_prev = (dZ . W^T) * gelu'(z_prev)
+  const float* Zp;
+  bf16* dZ;
+  bf16* dZt;
+  int64_t ld, ldt;
+  __device__ void operator()(int64_t row, int col, float acc, int) const {
+    const bf16 d = (bf16)(acc * gelu_grad(Zp[row * ld + col]));
+    dZ[row * ld + col] = d;
+    dZt[(int64_t)col * ldt + row] = d;
+  }
+};
+
+struct EpiDW {  // partial weight gradient, [split][out][in]
+  float* part;
+  int64_t split_stride;
+  int ldo;
+  __device__ void operator()(int64_t row, int col, float acc, int z) const {
+    part[(int64_t)z * split_stride + row * ldo + col] = acc;
+  }
+};
+
+template <int NB, class Epi>
+static hipError_t gemm(const bf16* A, int64_t lda, const bf16* Bt, int64_t ldb, int64_t M, int N,
+                       int64_t Kd, int splits, const Epi& e, hipStream_t s) {
+  const int64_t chunk = ((Kd + splits - 1) / splits + 31) / 32 * 32;
+  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 16 * NB - 1) / (16 * NB)), (unsigned)splits);
+  gemm_abt<NB, Epi><<<grid, 64, 0, s>>>(A, lda, Bt, ldb, M, N, Kd, chunk, e);
+  return hipGetLastError();
+}
+
+// ---- element-wise kernels --------------------------------------------------
+
+__global__ void encode_kernel(const float* __restrict__ stokes, const int32_t* __restrict__ rows,
+                              int64_t M, int n_in, int K0, const float* __restrict__ mean,
+                              const float* __restrict__ istd, bf16* X0, bf16* X0t, int64_t cap) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * K0) return;
+  const int64_t m = t / K0;
+  const int k = (int)(t - m * K0);
+  const int64_t src = rows ? (int64_t)rows[m] : m;
+  const float x = k < n_in ? (stokes[src * n_in + k] - mean[k]) * istd[k] : 0.f;
+  const bf16 xb = (bf16)x;
+  X0[m * K0 + k] = xb;
+  if (X0t) X0t[(int64_t)k * cap + m] = xb;
+}
+
+__global__ void loss_grad_kernel(const float* __restrict__ Y4, const float* __restrict__ T,
+                                 const int32_t* __restrict__ rows, int64_t M, int64_t cap,
+                                 bf16* dZ, bf16* dZt, double* loss) {
+  __shared__ float red[256];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float d2 = 0.f;
+  if (t < M * MLP_OUT) {
+    const int64_t m = t / MLP_OUT;
+    const int c = (int)(t - m * MLP_OUT);
+    float d = 0.f;
+    if (c < MLP_NCODE) {
+      const int64_t src = rows ? (int64_t)rows[m] : m;
+      d = Y4[m * MLP_OUT + c] - T[src * MLP_NCODE + c];
+    }
+    d2 = d * d;
+    const bf16 g = (bf16)(2.f * d / (float)(M * MLP_NCODE));
+    dZ[m * MLP_OUT + c] = g;
+    dZt[(int64_t)c * cap + m] = g;
+  }
+  red[threadIdx.x] = d2;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, (double)red[0]);
+}
+
+// db[n] = sum over the batch of dZ^T[n][:]
+__global__ void bias_grad_kernel(const bf16* __restrict__ dZt, int64_t M, int64_t cap,
+                                 float* grad_b) {
+  __shared__ float red[64];
+  const int n = blockIdx.x;
+  float s = 0.f;
+  for (int64_t m = threadIdx.x; m < M; m += 64) s += (float)dZt[(int64_t)n * cap + m];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_b[n] = red[0];
+}
+
+struct AdamArgs {
+  float* master;
+  float* m;
+  float* v;
+  float* grad;
+  const float* part[4];
+  bf16* Wt[4];
+  bf16* Wk[4];
+  int64_t oW[4], ob[4];
+  int in_dim[4], out_dim[4];
+  int64_t split_stride[4];
+  int64_t total;
+  float lr, beta1, beta2, eps, bc1, bc2;
+  int update;  // 0: only assemble the gradient
+};
+
+__global__ void adam_kernel(const AdamArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.total) return;
+  int l = 0;
+  while (l < 3 && i >= a.oW[l + 1]) ++l;
+  float g;
+  const bool is_w = i < a.ob[l];
+  int k = 0, n = 0;
+  if (is_w) {
+    const int64_t e = i - a.oW[l];
+    k = (int)(e / a.out_dim[l]);
+    n = (int)(e - (int64_t)k * a.out_dim[l]);
+    g = 0.f;
+    for (int s = 0; s < MLP_SPLITK; ++s)
+      g += a.part[l][(int64_t)s * a.split_stride[l] + (int64_t)n * a.in_dim[l] + k];
+    a.grad[i] = g;
+  } else {
+    g = a.grad[i];  // written by bias_grad_kernel
+  }
+  if (!a.update) return;
+  const float m = a.beta1 * a.m[i] + (1.f - a.beta1) * g;
+  const float v = a.beta2 * a.v[i] + (1.f - a.beta2) * g * g;
+  a.m[i] = m;
+  a.v[i] = v;
+  const float w = a.master[i] - a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+  a.master[i] = w;
+  if (is_w) {
+    a.Wt[l][(int64_t)n * a.in_dim[l] + k] = (bf16)w;
+    a.Wk[l][(int64_t)k * a.out_dim[l] + n] = (bf16)w;
+  }
+}
+
+struct RefreshArgs {
+  const float* master;
+  bf16* Wt[4];
+  bf16* Wk[4];
+  int64_t oW[4];
+  int in_dim[4], out_dim[4];
+};
+
+__global__ void refresh_kernel(const RefreshArgs a, int l) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.in_dim[l] * a.out_dim[l]) return;
+  const int k = (int)(e / a.out_dim[l]);
+  const int n = (int)(e - (int64_t)k * a.out_dim[l]);
+  const bf16 w = (bf16)a.master[a.oW[l] + e];
+  a.Wt[l][(int64_t)n * a.in_dim[l] + k] = w;
+  a.Wk[l][e] = w;
+}
+
+// Network outputs -> model parameters (the field vector is encoded as
+// (B cos g, B sin g cos 2psi, B sin g sin 2psi) / 3000), then the box.
+__global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
+                              const float* __restrict__ out_mean,
+                              const float* __restrict__ out_std, float* codes, float* params) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float y[MLP_NCODE];
+#pragma unroll
+  for (int c = 0; c < MLP_NCODE; ++c) y[c] = Y4[m * MLP_OUT + c];
+  if (codes) {
+#pragma unroll
+    for (int c = 0; c < MLP_NCODE; ++c) codes[m * MLP_NCODE + c] = y[c];
+  }
+  if (!params) return;
+  double P[NPAR];
+  const double bt = sqrt((double)y[1] * y[1] + (double)y[2] * y[2]);
+  P[0] = 3000.0 * sqrt((double)y[0] * y[0] + bt * bt);
+  P[1] = atan2(bt, (double)y[0]) * (180.0 / 3.14159265358979323846);
+  P[2] = 0.5 * atan2((double)y[2], (double)y[1]) * (180.0 / 3.14159265358979323846);
+#pragma unroll
+  for (int c = 3; c < MLP_NCODE; ++c) P[c] = (double)y[c] * out_std[c - 3] + out_mean[c - 3];
+  project(P);
+#pragma unroll
+  for (int c = 0; c < NPAR; ++c) params[m * NPAR + c] = (float)P[c];
+}
+
+__global__ void fallback_select_kernel(const double* __restrict__ chi2, int64_t n, double tau,
+                                       int32_t* list, unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double c = chi2[i];
+  if (!(c <= tau) && !isnan(c)) {  // not acceptable (non-finite input stays as is)
+    const unsigned long long slot = atomicAdd(count, 1ull);
+    list[slot] = (int32_t)i;
+  }
+}
+
+__global__ void fallback_merge_kernel(const int32_t* __restrict__ list,
+                                      const unsigned long long* __restrict__ count,
+                                      const float* __restrict__ p_fb,
+                                      const double* __restrict__ c_fb,
+                                      const int32_t* __restrict__ i_fb,
+                                      const int32_t* __restrict__ s_fb, float* params,
+                                      double* chi2, int32_t* iters, int32_t* status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((unsigned long long)t >= *count) return;
+  const int64_t i = list[t];
+  const bool better = c_fb[i] < chi2[i];
+  if (better) {
+#pragma unroll
+    for (int q = 0; q < NPAR; ++q) params[i * NPAR + q] = p_fb[i * NPAR + q];
+    chi2[i] = c_fb[i];
+  }
+  iters[i] += i_fb[i];
+  if (status) status[i] = (better ? s_fb[i] : status[i]) | 16;
+}
+
+// ---- host-side sequences ---------------------------------------------------
+
+static unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t mlp_forward(const MlpDev& net, MlpWork& w, int64_t M, const float* stokes,
+                       const int32_t* rows, bool train, hipStream_t s) {
+  const MlpLayout& L = net.L;
+  encode_kernel<<<blocks_for(M * L.K0, 256), 256, 0, s>>>(
+      stokes, rows, M, L.n_in, L.K0, net.in_mean, net.in_istd, w.X0, train ? w.X0t : nullptr,
+      w.cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bf16* X = w.X0;
+  int64_t ldx = L.K0;
+  for (int l = 0; l < 3; ++l) {
+    EpiHidden ep{net.master + L.ob[l], w.Y[l], train ? w.Yt[l] : nullptr,
+                 train ? w.Z[l] : nullptr, MLP_H, w.cap};
+    e = gemm<4>(X, ldx, net.Wt[l], L.in_dim[l], M, MLP_H, L.in_dim[l], 1, ep, s);
+    if (e != hipSuccess) return e;
+    X = w.Y[l];
+    ldx = MLP_H;
+  }
+  EpiOut eo{net.master + L.ob[3], w.Y4};
+  return gemm<2>(X, ldx, net.Wt[3], MLP_H, M, MLP_OUT, MLP_H, 1, eo, s);
+}
+
+hipError_t mlp_decode(const MlpDev& net, const float* Y4, int64_t M, float* codes, float* params,
+                      hipStream_t s) {
+  decode_kernel<<<blocks_for(M, 256), 256, 0, s>>>(Y4, M, net.out_mean, net.out_std, codes,
+                                                   params);
+  return hipGetLastError();
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+hipError_t zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  zero_u64_kernel<<<blocks_for(n, 64), 64, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* targets,
+                        const int32_t* rows, hipStream_t s) {
+  const MlpLayout& L = net.L;
+  loss_grad_kernel<<<blocks_for(M * MLP_OUT, 256), 256, 0, s>>>(
+      w.Y4, targets, rows, M, w.cap, w.dZ[3], w.dZt[3], w.loss);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int l = 3; l >= 0; --l) {
+    const int out = L.out_dim[l], in = L.in_dim[l];
+    const int64_t stride = (int64_t)out * in;
+    int64_t off = 0;
+    for (int q = 0; q < l; ++q) off += (int64_t)L.in_dim[q] * L.out_dim[q] * MLP_SPLITK;
+    // weight gradient: dWt[out][in] = dZ^T[out][B] . X^T[in][B]^T
+    const bf16* Xt = l == 0 ? w.X0t : w.Yt[l - 1];
+    EpiDW ed{w.dW + off, stride, in};
+    e = gemm<4>(w.dZt[l], w.cap, Xt, w.cap, out, in, M, MLP_SPLITK, ed, s);
+    if (e != hipSuccess) return e;
+    bias_grad_kernel<<<out, 64, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (l > 0) {  // input gradient through W and the previous GELU
+      EpiBwdX eb{w.Z[l - 1], w.dZ[l - 1], w.dZt[l - 1], MLP_H, w.cap};
+      e = gemm<4>(w.dZ[l], out, net.Wk[l], out, M, in, out, 1, eb, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t mlp_adam(const MlpDev& net, const MlpWork& w, float lr, float beta1, float beta2,
+                    float eps, int step, hipStream_t s) {
+  const MlpLayout& L = net.L;
+  AdamArgs a;
+  a.master = net.master;
+  a.m = net.adam_m;
+  a.v = net.adam_v;
+  a.grad = w.grad;
+  int64_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    a.part[l] = w.dW + off;
+    off += (int64_t)L.in_dim[l] * L.out_dim[l] * MLP_SPLITK;
+    a.Wt[l] = net.Wt[l];
+    a.Wk[l] = net.Wk[l];
+    a.oW[l] = L.oW[l];
+    a.ob[l] = L.ob[l];
+    a.in_dim[l] = L.in_dim[l];
+    a.out_dim[l] = L.out_dim[l];
+    a.split_stride[l] = (int64_t)L.in_dim[l] * L.out_dim[l];
+  }
+  a.total = L.total;
+  a.lr = lr;
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  a.update = step > 0 ? 1 : 0;
+  a.bc1 = step > 0 ? 1.f - powf(beta1, (float)step) : 1.f;
+  a.bc2 = step > 0 ? 1.f - powf(beta2, (float)step) : 1.f;
+  adam_kernel<<<blocks_for(L.total, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t s) {
+  RefreshArgs r;
+  r.master = net.master;
+  for (int l = 0; l < 4; ++l) {
+    r.Wt[l] = net.Wt[l];
+    r.Wk[l] = net.Wk[l];
+    r.oW[l] = net.L.oW[l];
+    r.in_dim[l] = net.L.in_dim[l];
+    r.out_dim[l] = net.L.out_dim[l];
+  }
+  for (int l = 0; l < 4; ++l) {
+    const int64_t n = (int64_t)net.L.in_dim[l] * net.L.out_dim[l];
+    refresh_kernel<<<blocks_for(n, 256), 256, 0, s>>>(r, l);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t fallback_select(const double* chi2, int64_t n, double tau, int32_t* list,
+                           unsigned long long* count, hipStream_t s) {
+  fallback_select_kernel<<<blocks_for(n, 256), 256, 0, s>>>(chi2, n, tau, list, count);
+  return hipGetLastError();
+}
+
+hipError_t fallback_merge(const int32_t* list, const unsigned long long* count, int64_t n,
+                          const float* p_fb, const double* c_fb, const int32_t* i_fb,
+                          const int32_t* s_fb, float* params, double* chi2, int32_t* iters,
+                          int32_t* status, hipStream_t s) {
+  fallback_merge_kernel<<<blocks_for(n, 256), 256, 0, s>>>(list, count, p_fb, c_fb, i_fb, s_fb,
+                                                           params, chi2, iters, status);
+  return hipGetLastError();
+}
+
+}  // namespace vfisv

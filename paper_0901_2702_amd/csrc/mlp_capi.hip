@@ -1,0 +1,502 @@
+// C ABI of the learned initialiser (network objects, inference, training
+// steps, save/load) and of the learned-start inversion with plain-LM
+// fallback.  Declared in include/vfisv.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "capi_internal.h"
+#include "mlp.h"
+#include "vfisv.h"
+
+using namespace vfisv;
+using namespace vfisv_capi;
+
+struct vfisv_mlp {
+  vfisv_ctx* ctx = nullptr;
+  MlpDev dev;
+  MlpWork train;
+  MlpWork infer;
+  int step = 0;
+  std::vector<float> in_mean, in_std, out_mean, out_std;  // host copies
+};
+
+namespace {
+
+constexpr int64_t INFER_CHUNK = 262144;
+constexpr uint32_t FILE_VERSION = 1;
+const char FILE_MAGIC[8] = {'V', 'F', 'I', 'S', 'V', 'M', 'L', 'P'};
+
+template <class T>
+hipError_t dalloc(T** p, int64_t count) {
+  return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+void free_work(MlpWork& w) {
+  hipFree(w.X0);
+  hipFree(w.X0t);
+  for (int l = 0; l < 3; ++l) {
+    hipFree(w.Y[l]);
+    hipFree(w.Yt[l]);
+    hipFree(w.Z[l]);
+  }
+  hipFree(w.Y4);
+  for (int l = 0; l < 4; ++l) {
+    hipFree(w.dZ[l]);
+    hipFree(w.dZt[l]);
+  }
+  hipFree(w.dW);
+  hipFree(w.grad);
+  hipFree(w.loss);
+  std::memset(&w, 0, sizeof w);
+}
+
+hipError_t alloc_work(MlpWork& w, const MlpLayout& L, int64_t cap, bool training) {
+  free_work(w);
+  w.cap = cap;
+  hipError_t e = dalloc(&w.X0, cap * L.K0);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = dalloc(&w.Y[l], cap * MLP_H);
+  if (e == hipSuccess) e = dalloc(&w.Y4, cap * MLP_OUT);
+  if (e == hipSuccess) e = dalloc(&w.loss, 1);
+  if (training) {
+    if (e == hipSuccess) e = dalloc(&w.X0t, cap * L.K0);
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) e = dalloc(&w.Yt[l], cap * MLP_H);
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) e = dalloc(&w.Z[l], cap * MLP_H);
+    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+      const int64_t width = l == 3 ? MLP_OUT : MLP_H;
+      e = dalloc(&w.dZ[l], cap * width);
+      if (e == hipSuccess) e = dalloc(&w.dZt[l], cap * width);
+    }
+    int64_t part = 0;
+    for (int l = 0; l < 4; ++l) part += (int64_t)L.in_dim[l] * L.out_dim[l] * MLP_SPLITK;
+    if (e == hipSuccess) e = dalloc(&w.dW, part);
+    if (e == hipSuccess) e = dalloc(&w.grad, L.total);
+  }
+  if (e != hipSuccess) free_work(w);
+  return e;
+}
+
+void free_dev(MlpDev& d) {
+  hipFree(d.master);
+  hipFree(d.adam_m);
+  hipFree(d.adam_v);
+  for (int l = 0; l < 4; ++l) {
+    hipFree(d.Wt[l]);
+    hipFree(d.Wk[l]);
+  }
+  hipFree(d.in_mean);
+  hipFree(d.in_istd);
+  hipFree(d.out_mean);
+  hipFree(d.out_std);
+}
+
+int build(vfisv_ctx* ctx, int n_in, const float* in_mean, const float* in_std,
+          const float* out_mean, const float* out_std, const float* params, uint64_t seed,
+          vfisv_mlp** out) {
+  if (n_in < 1 || n_in > 4096) return fail(ctx, VFISV_E_INVALID, "mlp: n_in must be 1..4096");
+  if (!in_mean || !in_std || !out_mean || !out_std)
+    return fail(ctx, VFISV_E_INVALID, "mlp: NULL normalisation");
+  for (int k = 0; k < n_in; ++k)
+    if (!std::isfinite(in_mean[k]) || !(in_std[k] > 0.f) || !std::isfinite(in_std[k]))
+      return fail(ctx, VFISV_E_INVALID, "mlp: input mean/std must be finite, std > 0");
+  for (int k = 0; k < 7; ++k)
+    if (!std::isfinite(out_mean[k]) || !(out_std[k] > 0.f) || !std::isfinite(out_std[k]))
+      return fail(ctx, VFISV_E_INVALID, "mlp: output mean/std must be finite, std > 0");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  vfisv_mlp* m = new (std::nothrow) vfisv_mlp();
+  if (!m) return fail(ctx, VFISV_E_NOMEM, "mlp: host allocation");
+  m->ctx = ctx;
+  std::memset(&m->dev, 0, sizeof m->dev);
+  std::memset(&m->train, 0, sizeof m->train);
+  std::memset(&m->infer, 0, sizeof m->infer);
+  MlpDev& d = m->dev;
+  d.L = mlp_layout(n_in);
+  const MlpLayout& L = d.L;
+  m->in_mean.assign(in_mean, in_mean + n_in);
+  m->in_std.assign(in_std, in_std + n_in);
+  m->out_mean.assign(out_mean, out_mean + 7);
+  m->out_std.assign(out_std, out_std + 7);
+
+  std::vector<float> host(L.total, 0.f);
+  if (params) {
+    std::memcpy(host.data(), params, sizeof(float) * L.total);
+  } else {  // He initialisation; padding rows/columns stay zero
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < 4; ++l) {
+      const int fan_in = l == 0 ? n_in : L.in_dim[l];
+      const int outs = l == 3 ? MLP_NCODE : L.out_dim[l];
+      std::normal_distribution<double> nd(0.0, std::sqrt((l == 3 ? 1.0 : 2.0) / fan_in));
+      for (int k = 0; k < fan_in; ++k)
+        for (int n = 0; n < outs; ++n) host[L.oW[l] + (int64_t)k * L.out_dim[l] + n] = (float)nd(rng);
+    }
+  }
+  std::vector<float> mean(L.K0, 0.f), istd(L.K0, 0.f);
+  for (int k = 0; k < n_in; ++k) {
+    mean[k] = in_mean[k];
+    istd[k] = 1.f / in_std[k];
+  }
+  e = dalloc(&d.master, L.total);
+  if (e == hipSuccess) e = dalloc(&d.adam_m, L.total);
+  if (e == hipSuccess) e = dalloc(&d.adam_v, L.total);
+  for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+    e = dalloc(&d.Wt[l], (int64_t)L.in_dim[l] * L.out_dim[l]);
+    if (e == hipSuccess) e = dalloc(&d.Wk[l], (int64_t)L.in_dim[l] * L.out_dim[l]);
+  }
+  if (e == hipSuccess) e = dalloc(&d.in_mean, L.K0);
+  if (e == hipSuccess) e = dalloc(&d.in_istd, L.K0);
+  if (e == hipSuccess) e = dalloc(&d.out_mean, 7);
+  if (e == hipSuccess) e = dalloc(&d.out_std, 7);
+  if (e != hipSuccess) {
+    free_dev(d);
+    delete m;
+    return fail(ctx, VFISV_E_NOMEM, "mlp: device allocation");
+  }
+  e = hipMemcpy(d.master, host.data(), sizeof(float) * L.total, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(d.adam_m, 0, sizeof(float) * L.total);
+  if (e == hipSuccess) e = hipMemset(d.adam_v, 0, sizeof(float) * L.total);
+  if (e == hipSuccess) e = hipMemcpy(d.in_mean, mean.data(), 4 * L.K0, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.in_istd, istd.data(), 4 * L.K0, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.out_mean, out_mean, 4 * 7, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.out_std, out_std, 4 * 7, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = mlp_refresh_bf16(d, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_dev(d);
+    delete m;
+    return hip_fail(ctx, e, "mlp: upload");
+  }
+  *out = m;
+  return VFISV_OK;
+}
+
+int ensure_train(vfisv_mlp* m, int64_t rows) {
+  if (m->train.cap >= rows) return VFISV_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = alloc_work(m->train, m->dev.L, rows, true);
+  if (e == hipSuccess) e = hipMemset(m->train.loss, 0, sizeof(double));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(m->ctx, VFISV_E_NOMEM, "mlp: training buffers");
+  return VFISV_OK;
+}
+
+int ensure_infer(vfisv_mlp* m, int64_t rows) {
+  if (m->infer.cap >= rows) return VFISV_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = alloc_work(m->infer, m->dev.L, rows, false);
+  if (e != hipSuccess) return fail(m->ctx, VFISV_E_NOMEM, "mlp: inference buffers");
+  return VFISV_OK;
+}
+
+int check_mlp(vfisv_ctx* ctx, const vfisv_mlp* m, const char* fn) {
+  if (!m) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": mlp is NULL");
+  if (m->ctx != ctx) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": mlp of another context");
+  return VFISV_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// 0.99 quantile of chi^2_k / k by the Wilson-Hilferty cube approximation.
+double chi2_red_q99(int k) {
+  const double z = 2.3263478740408408, a = 2.0 / (9.0 * k);
+  const double c = 1.0 - a + z * std::sqrt(a);
+  return c * c * c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vfisv_mlp_create(vfisv_ctx* ctx, int n_in, const float* in_mean, const float* in_std,
+                     const float* out_mean, const float* out_std, uint64_t seed,
+                     vfisv_mlp** out) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_create: ctx is NULL");
+  if (!out) return fail(ctx, VFISV_E_INVALID, "mlp_create: out is NULL");
+  *out = nullptr;
+  return build(ctx, n_in, in_mean, in_std, out_mean, out_std, nullptr, seed, out);
+}
+
+int vfisv_mlp_destroy(vfisv_mlp* m) {
+  if (!m) return VFISV_OK;
+  hipSetDevice(m->ctx->device);
+  hipDeviceSynchronize();
+  free_work(m->train);
+  free_work(m->infer);
+  free_dev(m->dev);
+  delete m;
+  return VFISV_OK;
+}
+
+int64_t vfisv_mlp_num_params(const vfisv_mlp* m) { return m ? m->dev.L.total : -1; }
+
+int vfisv_mlp_get_params(vfisv_mlp* m, float* host, int64_t n) {
+  if (!m || !host) return VFISV_E_INVALID;
+  if (n != m->dev.L.total) return fail(m->ctx, VFISV_E_INVALID, "mlp_get_params: size mismatch");
+  hipError_t e = hipSetDevice(m->ctx->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(host, m->dev.master, 4 * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(m->ctx, e, "mlp_get_params");
+  return VFISV_OK;
+}
+
+int vfisv_mlp_set_params(vfisv_mlp* m, const float* host, int64_t n) {
+  if (!m || !host) return VFISV_E_INVALID;
+  if (n != m->dev.L.total) return fail(m->ctx, VFISV_E_INVALID, "mlp_set_params: size mismatch");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(host[i])) return fail(m->ctx, VFISV_E_INVALID, "mlp_set_params: non-finite");
+  hipError_t e = hipSetDevice(m->ctx->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(m->dev.master, host, 4 * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->dev.adam_m, 0, 4 * n);
+  if (e == hipSuccess) e = hipMemset(m->dev.adam_v, 0, 4 * n);
+  if (e == hipSuccess) e = mlp_refresh_bf16(m->dev, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(m->ctx, e, "mlp_set_params");
+  m->step = 0;
+  return VFISV_OK;
+}
+
+int vfisv_mlp_forward(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stokes, float* codes,
+                      float* params, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_forward: ctx is NULL");
+  int rc = check_mlp(ctx, m, "mlp_forward");
+  if (rc) return rc;
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "mlp_forward: n < 0");
+  if (n == 0) return VFISV_OK;
+  if (!stokes || (!codes && !params)) return fail(ctx, VFISV_E_INVALID, "mlp_forward: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  rc = ensure_infer(m, n < INFER_CHUNK ? n : INFER_CHUNK);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int n_in = m->dev.L.n_in;
+  for (int64_t off = 0; off < n; off += m->infer.cap) {
+    const int64_t rows = n - off < m->infer.cap ? n - off : m->infer.cap;
+    e = mlp_forward(m->dev, m->infer, rows, stokes + off * n_in, nullptr, false, s);
+    if (e == hipSuccess)
+      e = mlp_decode(m->dev, m->infer.Y4, rows, codes ? codes + off * MLP_NCODE : nullptr,
+                     params ? params + off * NPAR : nullptr, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_forward");
+  }
+  return VFISV_OK;
+}
+
+int vfisv_mlp_gradient(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stokes,
+                       const float* targets, float* grad, double* loss, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_gradient: ctx is NULL");
+  int rc = check_mlp(ctx, m, "mlp_gradient");
+  if (rc) return rc;
+  if (n <= 0 || n % 32 != 0 || n > (1 << 22))
+    return fail(ctx, VFISV_E_INVALID, "mlp_gradient: n must be a positive multiple of 32");
+  if (!stokes || !targets || !grad) return fail(ctx, VFISV_E_INVALID, "mlp_gradient: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  rc = ensure_train(m, n);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  MlpWork& w = m->train;
+  e = zero_u64((unsigned long long*)w.loss, 1, s);
+  if (e == hipSuccess) e = mlp_forward(m->dev, w, n, stokes, nullptr, true, s);
+  if (e == hipSuccess) e = mlp_backward(m->dev, w, n, targets, nullptr, s);
+  if (e == hipSuccess) e = mlp_adam(m->dev, w, 0.f, 0.f, 0.f, 0.f, 0, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grad, w.grad, 4 * m->dev.L.total, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, w.loss, 8, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_gradient");
+  return VFISV_OK;
+}
+
+int vfisv_mlp_train_step(vfisv_ctx* ctx, vfisv_mlp* m, const float* stokes, const float* targets,
+                         const int32_t* rows, int batch, float lr, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_train_step: ctx is NULL");
+  int rc = check_mlp(ctx, m, "mlp_train_step");
+  if (rc) return rc;
+  if (batch <= 0 || batch % 32 != 0 || batch > (1 << 20))
+    return fail(ctx, VFISV_E_INVALID, "mlp_train_step: batch must be a positive multiple of 32");
+  if (!stokes || !targets || !rows) return fail(ctx, VFISV_E_INVALID, "mlp_train_step: NULL buffer");
+  if (!(lr > 0.f) || !std::isfinite(lr)) return fail(ctx, VFISV_E_INVALID, "mlp_train_step: lr");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  rc = ensure_train(m, batch);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  MlpWork& w = m->train;
+  e = mlp_forward(m->dev, w, batch, stokes, rows, true, s);
+  if (e == hipSuccess) e = mlp_backward(m->dev, w, batch, targets, rows, s);
+  if (e == hipSuccess) e = mlp_adam(m->dev, w, lr, 0.9f, 0.999f, 1e-8f, m->step + 1, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train_step");
+  m->step += 1;
+  return VFISV_OK;
+}
+
+int vfisv_mlp_take_loss(vfisv_mlp* m, double* sum_sq) {
+  if (!m || !sum_sq) return VFISV_E_INVALID;
+  *sum_sq = 0.0;
+  if (m->train.cap == 0) return VFISV_OK;
+  hipError_t e = hipSetDevice(m->ctx->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(sum_sq, m->train.loss, 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = zero_u64((unsigned long long*)m->train.loss, 1, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(m->ctx, e, "mlp_take_loss");
+  return VFISV_OK;
+}
+
+int vfisv_mlp_save(vfisv_mlp* m, const char* path) {
+  if (!m || !path) return VFISV_E_INVALID;
+  const MlpLayout& L = m->dev.L;
+  std::vector<float> params(L.total);
+  int rc = vfisv_mlp_get_params(m, params.data(), L.total);
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(m->ctx, VFISV_E_INVALID, std::string("mlp_save: cannot open ") + path);
+  const uint32_t n_in = (uint32_t)L.n_in;
+  const uint64_t total = (uint64_t)L.total;
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &n_in, 4);
+  h = fnv1a(h, &total, 8);
+  h = fnv1a(h, m->in_mean.data(), 4 * n_in);
+  h = fnv1a(h, m->in_std.data(), 4 * n_in);
+  h = fnv1a(h, m->out_mean.data(), 28);
+  h = fnv1a(h, m->out_std.data(), 28);
+  h = fnv1a(h, params.data(), 4 * total);
+  bool ok = std::fwrite(FILE_MAGIC, 1, 8, f) == 8 && std::fwrite(&FILE_VERSION, 4, 1, f) == 1 &&
+            std::fwrite(&n_in, 4, 1, f) == 1 && std::fwrite(&total, 8, 1, f) == 1 &&
+            std::fwrite(m->in_mean.data(), 4, n_in, f) == n_in &&
+            std::fwrite(m->in_std.data(), 4, n_in, f) == n_in &&
+            std::fwrite(m->out_mean.data(), 4, 7, f) == 7 &&
+            std::fwrite(m->out_std.data(), 4, 7, f) == 7 &&
+            std::fwrite(params.data(), 4, total, f) == total && std::fwrite(&h, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(m->ctx, VFISV_E_INVALID, "mlp_save: write failed");
+  return VFISV_OK;
+}
+
+int vfisv_mlp_load(vfisv_ctx* ctx, const char* path, vfisv_mlp** out) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_load: ctx is NULL");
+  if (!path || !out) return fail(ctx, VFISV_E_INVALID, "mlp_load: NULL argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(ctx, VFISV_E_INVALID, std::string("mlp_load: cannot open ") + path);
+  char magic[8];
+  uint32_t ver = 0, n_in = 0;
+  uint64_t total = 0, h_file = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, FILE_MAGIC, 8) == 0 &&
+            std::fread(&ver, 4, 1, f) == 1 && ver == FILE_VERSION &&
+            std::fread(&n_in, 4, 1, f) == 1 && n_in >= 1 && n_in <= 4096 &&
+            std::fread(&total, 8, 1, f) == 1 && (int64_t)total == mlp_layout((int)n_in).total;
+  std::vector<float> im, is, om(7), os(7), params;
+  if (ok) {
+    im.resize(n_in);
+    is.resize(n_in);
+    params.resize(total);
+    ok = std::fread(im.data(), 4, n_in, f) == n_in && std::fread(is.data(), 4, n_in, f) == n_in &&
+         std::fread(om.data(), 4, 7, f) == 7 && std::fread(os.data(), 4, 7, f) == 7 &&
+         std::fread(params.data(), 4, total, f) == total && std::fread(&h_file, 8, 1, f) == 1;
+  }
+  std::fclose(f);
+  if (!ok) return fail(ctx, VFISV_E_INVALID, "mlp_load: not a network file of this version");
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &n_in, 4);
+  h = fnv1a(h, &total, 8);
+  h = fnv1a(h, im.data(), 4 * n_in);
+  h = fnv1a(h, is.data(), 4 * n_in);
+  h = fnv1a(h, om.data(), 28);
+  h = fnv1a(h, os.data(), 28);
+  h = fnv1a(h, params.data(), 4 * total);
+  if (h != h_file) return fail(ctx, VFISV_E_INVALID, "mlp_load: checksum mismatch");
+  return build(ctx, (int)n_in, im.data(), is.data(), om.data(), os.data(), params.data(), 0, out);
+}
+
+int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m, int64_t n,
+                         const float* stokes, const float* W, int W_per_pixel,
+                         const vfisv_options* opt, int learned_max_iter, double chi2_accept,
+                         float* params, double* chi2, int32_t* iters, int32_t* status,
+                         void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert_learned: ctx is NULL");
+  int rc = check_inst(ctx, inst, "invert_learned");
+  if (rc) return rc;
+  rc = check_mlp(ctx, m, "invert_learned");
+  if (rc) return rc;
+  if (m->dev.L.n_in != 4 * inst->C.n_obs)
+    return fail(ctx, VFISV_E_INVALID, "invert_learned: network inputs != 4 * n_obs");
+  vfisv_options o;
+  double inv_dof;
+  rc = check_options(ctx, inst, opt, &o, &inv_dof);
+  if (rc) return rc;
+  if (learned_max_iter < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: learned_max_iter < 0");
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: n < 0");
+  if (n == 0) return VFISV_OK;
+  if (n > INT32_MAX) return fail(ctx, VFISV_E_INVALID, "invert_learned: n must be < 2^31");
+  if (!stokes || !W || !params || !chi2 || !iters)
+    return fail(ctx, VFISV_E_INVALID, "invert_learned: NULL buffer");
+  const double tau = chi2_accept > 0.0 ? chi2_accept : chi2_red_q99((int)std::lround(1.0 / inv_dof));
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+
+  // scratch: init [n][10] f32 | list [n] i32 | count u64 | p_fb [n][10] f32 |
+  //          c_fb [n] f64 | i_fb [n] i32 | s_fb [n] i32
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t o_init = 0;
+  const size_t o_list = o_init + al(sizeof(float) * NPAR * n);
+  const size_t o_cnt = o_list + al(sizeof(int32_t) * n);
+  const size_t o_pfb = o_cnt + 256;
+  const size_t o_cfb = o_pfb + al(sizeof(float) * NPAR * n);
+  const size_t o_ifb = o_cfb + al(sizeof(double) * n);
+  const size_t o_sfb = o_ifb + al(sizeof(int32_t) * n);
+  const size_t bytes = o_sfb + al(sizeof(int32_t) * n);
+  if (ctx->learn_bytes < bytes) {
+    e = hipDeviceSynchronize();
+    if (ctx->d_learn) hipFree(ctx->d_learn);
+    ctx->d_learn = nullptr;
+    ctx->learn_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_learn, bytes);
+    if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "invert_learned: scratch allocation");
+    ctx->learn_bytes = bytes;
+  }
+  char* base = (char*)ctx->d_learn;
+  float* init = (float*)(base + o_init);
+  int32_t* list = (int32_t*)(base + o_list);
+  unsigned long long* count = (unsigned long long*)(base + o_cnt);
+  float* p_fb = (float*)(base + o_pfb);
+  double* c_fb = (double*)(base + o_cfb);
+  int32_t* i_fb = (int32_t*)(base + o_ifb);
+  int32_t* s_fb = (int32_t*)(base + o_sfb);
+  hipStream_t s = (hipStream_t)stream;
+
+  // 1. network proposal of the starting model
+  rc = vfisv_mlp_forward(ctx, m, n, stokes, nullptr, init, stream);
+  if (rc) return rc;
+  // 2. short LM from the proposal
+  vfisv_options ol = o;
+  ol.max_iter = learned_max_iter;
+  rc = enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, ol, inv_dof,
+                  params, chi2, iters, status, s, true);
+  if (rc) return rc;
+  // 3. pixels whose fit is not acceptable go to plain LM from the default model
+  e = zero_u64(count, 1, s);
+  if (e == hipSuccess) e = fallback_select(chi2, n, tau, list, count, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: fallback selection");
+  rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, nullptr, o, inv_dof, p_fb,
+                  c_fb, i_fb, s_fb, s, false);
+  if (rc) return rc;
+  // 4. keep the better of the two fits; flag the pixel
+  e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, params, chi2, iters, status, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: merge");
+  return VFISV_OK;
+}
+
+}  // extern "C"

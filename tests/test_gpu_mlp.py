@@ -1,0 +1,161 @@
+"""GPU parity of the learned initialiser (bfloat16 MFMA network) against the
+FP64 numpy oracle with bfloat16 emulation, and its training / inversion
+behaviour."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as omlp
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+vf = pytest.importorskip("paper_0901_2702_amd")
+from paper_0901_2702_amd import learned  # noqa: E402
+
+H = 256
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    return vf.Context(0)
+
+
+def _unpack(flat, n_in):
+    K0 = (n_in + 31) // 32 * 32
+    shapes = [(K0, H), (H,), (H, H), (H,), (H, H), (H,), (H, 32), (32,)]
+    out, off = [], 0
+    for sh in shapes:
+        k = int(np.prod(sh))
+        out.append(flat[off:off + k].reshape(sh).astype(np.float64))
+        off += k
+    assert off == flat.size
+    P = {"W1": out[0][:n_in], "b1": out[1], "W2": out[2], "b2": out[3], "W3": out[4],
+         "b3": out[5], "W4": out[6][:, :10], "b4": out[7][:10]}
+    return P
+
+
+def _random_net(ctx, n_in, seed):
+    rng = np.random.default_rng(seed)
+    in_mean = rng.normal(size=n_in) * 0.1
+    in_std = rng.uniform(0.5, 2.0, n_in)
+    net = learned.Mlp(ctx, n_in, in_mean, in_std, np.zeros(7), np.ones(7), seed=seed)
+    flat = net.get_params()
+    flat = flat + (rng.normal(size=flat.size) * 0.02).astype(np.float32)
+    # keep padding rows/columns zero
+    P = _unpack(flat, n_in)
+    K0 = (n_in + 31) // 32 * 32
+    W1 = np.zeros((K0, H)); W1[:n_in] = P["W1"]
+    W4 = np.zeros((H, 32)); W4[:, :10] = P["W4"]
+    b4 = np.zeros(32); b4[:10] = P["b4"]
+    flat = np.concatenate([W1.ravel(), P["b1"], P["W2"].ravel(), P["b2"], P["W3"].ravel(),
+                           P["b3"], W4.ravel(), b4]).astype(np.float32)
+    net.set_params(flat)
+    return net, flat, in_mean, in_std
+
+
+def test_forward_matches_oracle(ctx):
+    n_in = 24
+    net, flat, mean, std = _random_net(ctx, n_in, 1)
+    x = (np.random.default_rng(2).normal(size=(1000, n_in)) * std + mean).astype(np.float32)
+    codes, params = net.forward(torch.tensor(x, device=ctx.device))
+    codes = codes.cpu().numpy()
+    P = _unpack(flat, n_in)
+    xs = ((x - mean.astype(np.float32)) * (1.0 / std.astype(np.float32))).astype(np.float32)
+    ref, _ = omlp.forward(P, xs, emulate_bf16=True)
+    scale = np.abs(ref).max()
+    err = np.abs(codes - ref)
+    print("[gpu] forward max err %.3g mean err %.3g scale %.3g" % (err.max(), err.mean(), scale))
+    assert err.max() < 2e-2 * scale and err.mean() < 1e-3 * scale
+    # decoded starting models are inside the box and follow the decoding
+    p = params.cpu().numpy()
+    dec = omlp.decode_outputs(codes.astype(np.float64), np.zeros(7), np.ones(7))
+    dec = np.array([oracle.project(m) for m in dec])
+    np.testing.assert_allclose(p[:, [0, 1, 3]], dec[:, [0, 1, 3]], rtol=1e-4, atol=1e-3)
+
+
+def test_gradient_matches_oracle(ctx):
+    n_in = 24
+    net, flat, mean, std = _random_net(ctx, n_in, 3)
+    rng = np.random.default_rng(4)
+    x = (rng.normal(size=(512, n_in)) * std + mean).astype(np.float32)
+    t = rng.normal(size=(512, 10)).astype(np.float32)
+    g, loss = net.gradient(torch.tensor(x, device=ctx.device), torch.tensor(t, device=ctx.device))
+    G = _unpack(g.cpu().numpy(), n_in)
+    P = _unpack(flat, n_in)
+    xs = ((x - mean.astype(np.float32)) * (1.0 / std.astype(np.float32))).astype(np.float32)
+    y, cache = omlp.forward(P, xs, emulate_bf16=True)
+    R = omlp.backward(P, cache, t.astype(np.float64), emulate_bf16=True)
+    assert loss.item() == pytest.approx(np.sum((y - t) ** 2), rel=1e-2)
+    for k in R:
+        rel = np.linalg.norm(G[k] - R[k]) / np.linalg.norm(R[k])
+        print("[gpu] grad %s rel err %.3g" % (k, rel))
+        assert rel < 3e-2, k
+    # the padding of the first and last layers receives no gradient
+    gf = g.cpu().numpy()
+    assert np.all(gf[n_in * H:32 * H] == 0.0)
+
+
+def test_save_load_round_trip(ctx):
+    net, flat, mean, std = _random_net(ctx, 24, 5)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        net.save(path)
+        net2 = learned.Mlp.load(ctx, path)
+        np.testing.assert_array_equal(net2.get_params(), net.get_params())
+        x = torch.randn(300, 24, device=ctx.device)
+        np.testing.assert_array_equal(net.forward(x)[0].cpu().numpy(),
+                                      net2.forward(x)[0].cpu().numpy())
+        with open(path, "r+b") as f:
+            f.seek(100)
+            b = f.read(1)
+            f.seek(100)
+            f.write(bytes([b[0] ^ 0xFF]))
+        with pytest.raises(vf.VfisvError):
+            learned.Mlp.load(ctx, path)
+
+
+@pytest.fixture(scope="module")
+def small_trained(ctx):
+    spec = wl.hmi_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    print("[gpu] synthesising a small training set", flush=True)
+    S, P = learned.make_training_set(ctx, inst, 262144, 11, wl.draw_params, wl.draw_noise)
+    Sc, Pc = learned.make_training_set(ctx, inst, 16384, 12, wl.draw_params, wl.draw_noise)
+    net, info = learned.train(ctx, inst, S, P, Sc, Pc, epochs=6, batch=2048, lr=2e-3,
+                              log=lambda m: print("[gpu] " + m, flush=True))
+    return spec, inst, net, info
+
+
+def test_training_lowers_the_control_error(small_trained):
+    spec, inst, net, info = small_trained
+    h = info["history"]
+    # standardised codes: predicting the mean gives a control error of ~1
+    assert h[-1][2] < 0.8 * h[0][2]
+    assert info["best_control_mse"] < 0.25
+
+
+def test_learned_start_needs_fewer_iterations(ctx, small_trained):
+    spec, inst, net, info = small_trained
+    n = 8192
+    P = wl.draw_params(n, 13)
+    noise = wl.draw_noise(n, 6, 13)
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=ctx.device),
+                        noise=torch.tensor(noise.astype(np.float32), device=ctx.device))
+    W = torch.tensor(wl.weights(6), device=ctx.device)
+    plain = vf.invert(ctx, inst, obs, W)
+    lrn = learned.invert_learned(ctx, inst, net, obs.view(n, 24), W)
+    pc, lc = plain["chi2"].cpu().numpy(), lrn["chi2"].cpu().numpy()
+    pi, li = plain["iters"].cpu().numpy(), lrn["iters"].cpu().numpy()
+    fb = (lrn["status"].cpu().numpy() & vf.FALLBACK_USED) != 0
+    print("[gpu] plain: median chi2 %.4f, mean iters %.2f; learned: median chi2 %.4f, mean "
+          "iters %.2f, fallback %.3f" % (np.median(pc), pi.mean(), np.median(lc), li.mean(),
+                                         fb.mean()))
+    assert li.mean() < 0.8 * pi.mean()
+    assert np.median(lc) <= np.median(pc) * 1.01
+    assert np.mean(lc > 1.01 * pc) < 0.2

@@ -103,7 +103,7 @@ def draw_params(n, seed, prior="cfg0", b_range=None):
 
 def draw_noise(n, n_obs, seed, sigma=1e-3):
     """[n, 4, n_obs] float64 Gaussian noise (stream separate from params)."""
-    rng = np.random.default_rng([seed, 7])
+    rng = np.random.default_rng([*np.atleast_1d(seed).tolist(), 7])
     return rng.normal(0.0, sigma, size=(n, 4, n_obs))
 
 
