@@ -62,6 +62,10 @@ def main():
     ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--plain-only", action="store_true",
+                    help="time only plain LM on the held-out batch (no training); for profiling")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the inversion is per-pixel independent and "
@@ -85,6 +89,17 @@ def main():
     inst = vf.Instrument.from_spec(ctx, spec)
     stream = torch.cuda.current_stream(dev)
     n_obs = spec.n_obs
+
+    if args.copy_ref_mb > 0:
+        src = torch.ones(args.copy_ref_mb << 18, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("reference copy of %d MiB done" % args.copy_ref_mb)
+        del src, dst
+
+    if args.plain_only:
+        return plain_only(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -242,6 +257,35 @@ def main():
             "seconds": round(dt, 3),
         }
     print(json.dumps(result), flush=True)
+
+
+def plain_only(args, ctx, inst, spec, log):
+    """Plain LM on the held-out batch only: the launch profiled by rocprofv3."""
+    import numpy as np
+    import torch
+
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    dev = ctx.device
+    n = args.n
+    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    P = wl.draw_params(n, seed)
+    noise = wl.draw_noise(n, spec.n_obs, seed)
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                        noise=torch.tensor(noise.astype(np.float32), device=dev))
+    W = torch.tensor(wl.weights(spec.n_obs), device=dev)
+    out = vf.invert(ctx, inst, obs, W)
+    for _ in range(args.warmup):
+        vf.invert(ctx, inst, obs, W, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        vf.invert(ctx, inst, obs, W, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    c = ctx.counters()
+    print(json.dumps({"mode": "plain-only", "pixels": n, "ms_per_step": round(ms, 4),
+                      "pixels_per_s": round(n / (ms * 1e-3), 1), "work": c}), flush=True)
 
 
 if __name__ == "__main__":

@@ -163,9 +163,9 @@ int vfisv_create(vfisv_ctx** out, int device) {
   e = lm_blocks_per_cu(&bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
   c->lm_blocks_per_cu = bpc;
-  // fallback workspace: 200 doubles per lane of the largest persistent grid
+  // fallback workspace: WS_DOUBLES per lane of the largest persistent grid
   c->ws_lanes = (int64_t)c->num_cus * 8 * 64;
-  e = hipMalloc(&c->d_ws, sizeof(double) * 200 * c->ws_lanes);
+  e = hipMalloc(&c->d_ws, sizeof(double) * WS_DOUBLES * c->ws_lanes);
   if (e != hipSuccess) {
     delete c;
     return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: workspace allocation");

@@ -209,7 +209,11 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       const int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
       if (code == 1) {
         ++n_fb;
-        solve_eigen_fallback(H, eps, sc, b, A.ws + glane, A.ws_stride, delta);
+        double* ws = A.ws + glane;
+        solve_eigen_fallback(&sHG[lane], 64, &sHG[55 * 64 + lane], 64, eps, A.free_mask, ws,
+                             A.ws_stride);
+#pragma unroll
+        for (int q = 0; q < NPAR; ++q) delta[q] = ws[(int64_t)(200 + q) * A.ws_stride];
       }
       double Mt[NPAR];
 #pragma unroll
@@ -279,8 +283,10 @@ __global__ __launch_bounds__(64) void solve_kernel(const SolveArgs A) {
     const double eps = A.eps[i];
     int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
     if (code == 1) {
-      const int64_t glane = (int64_t)blockIdx.x * 64 + threadIdx.x;
-      solve_eigen_fallback(H, eps, sc, b, A.ws + glane, A.ws_stride, delta);
+      double* ws = A.ws + (int64_t)blockIdx.x * 64 + threadIdx.x;
+      solve_eigen_fallback(A.H + i * 55, 1, A.g + i * NPAR, 1, eps, A.free_mask, ws, A.ws_stride);
+#pragma unroll
+      for (int q = 0; q < NPAR; ++q) delta[q] = ws[(int64_t)(200 + q) * A.ws_stride];
     }
 #pragma unroll
     for (int p = 0; p < NPAR; ++p) A.delta[i * NPAR + p] = delta[p];

@@ -427,17 +427,32 @@ __device__ __forceinline__ int solve_cholesky(const float* H, const float* g, do
 
 // Eigen (= SVD, the matrix being symmetric) fallback: cyclic Jacobi on
 // C + eps I held in a lane-strided float64 workspace (A at ws[e*stride],
-// eigenvectors at ws[(100 + e)*stride]); components with |lambda| below
-// 1e-12 of the largest are discarded.
-__device__ __noinline__ void solve_eigen_fallback(const float* H, double eps, const double* sc,
-                                                  const double* b, double* ws, int64_t stride,
-                                                  double* delta) {
+// eigenvectors at ws[(100 + e)*stride], the step written to
+// ws[(200 + p)*stride]); components with |lambda| below 1e-12 of the
+// largest are discarded.  H (packed, element stride hs) and g (stride gs)
+// are read through generic pointers (LDS or global) so that the caller keeps
+// its own arrays in registers.
+constexpr int WS_DOUBLES = 210;
+
+__device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const float* g, int gs,
+                                                  double eps, uint32_t free_mask, double* ws,
+                                                  int64_t stride) {
   auto A = [&](int i, int j) -> double& { return ws[(int64_t)(i * NPAR + j) * stride]; };
   auto V = [&](int i, int j) -> double& { return ws[(int64_t)(100 + i * NPAR + j) * stride]; };
+  double sc[NPAR], b[NPAR];
+  double maxd = 0.0;
+  for (int p = 0; p < NPAR; ++p)
+    if ((free_mask >> p) & 1u) maxd = fmax(maxd, (double)H[pk(p, p) * hs]);
+  for (int p = 0; p < NPAR; ++p) {
+    const double d = (double)H[pk(p, p) * hs];
+    const bool act = ((free_mask >> p) & 1u) && maxd > 0.0 && d > 1e-30 * maxd;
+    sc[p] = act ? 1.0 / sqrt(d) : 0.0;
+    b[p] = sc[p] * (double)g[p * gs];
+  }
   for (int i = 0; i < NPAR; ++i)
     for (int j = 0; j < NPAR; ++j) {
       const int hi = i > j ? pk(i, j) : pk(j, i);
-      double v = sc[i] * (double)H[hi] * sc[j];
+      double v = sc[i] * (double)H[hi * hs] * sc[j];
       if (i == j) v = (sc[i] != 0.0) ? 1.0 + eps : 1.0;
       A(i, j) = v;
       V(i, j) = (i == j) ? 1.0 : 0.0;
@@ -487,7 +502,7 @@ __device__ __noinline__ void solve_eigen_fallback(const float* H, double eps, co
     pr /= lam;
     for (int i = 0; i < NPAR; ++i) y[i] = fma(V(i, j), pr, y[i]);
   }
-  for (int p = 0; p < NPAR; ++p) delta[p] = sc[p] * y[p];
+  for (int p = 0; p < NPAR; ++p) ws[(int64_t)(200 + p) * stride] = sc[p] * y[p];
 }
 
 // Table 2 (rows read top-down).
