@@ -43,6 +43,39 @@ FLOP_SAMPLE_JAC = 115 + 4 * 140  # assemble 4 Jacobian rows + normal equations
 FLOP_SOLVE_FP64 = 1100       # equilibration, 10x10 Cholesky, substitutions, projection
 
 
+# HBM traffic of one plain-LM launch, from the committed rocprofv3 counter runs
+# (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter over a device
+# copy of known size).  Reported only while the kernel sources hash to the
+# value recorded with the counters; otherwise the figure is stale and null.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_plain_traffic.md")
+KERNEL_SOURCES = ("paper_0901_2702_amd/csrc/kernels.hip", "paper_0901_2702_amd/csrc/kernels.h",
+                  "paper_0901_2702_amd/csrc/me_device.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(n):
+    """HBM bytes per plain-LM launch over n pixels, or None when no counter
+    run matches the current kernel sources and batch size."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(line.strip("- `\n").split(": ", 1) for line in fh
+                      if line.startswith("- `") and ": " in line)
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv["pixels"]) != n:
+            return None
+        return {"fetch_bytes": float(kv["fetch_bytes_per_launch"]),
+                "write_bytes": float(kv["write_bytes_per_launch"])}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def work_model(n_pts, n_taps, n_obs):
     f_trial = n_pts * FLOP_POINT_VALUES + n_taps * FLOP_TAP_VALUES + n_obs * FLOP_SAMPLE_VALUES
     f_jac = (n_pts * (FLOP_POINT_VALUES + FLOP_POINT_JAC_EXTRA) + n_taps * FLOP_TAP_JAC
@@ -180,6 +213,8 @@ def main():
     def q(a, p):
         return float(np.quantile(a, p))
 
+    tr = committed_traffic(n)
+
     result = {
         "metric": "inverted pixels/s on 1 MI355X, learned-init LM vs plain LM at matched chi^2",
         "value": round(n / (ms_l * 1e-3), 1),
@@ -229,7 +264,10 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None,
+            "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
+            "traffic_detail": None if tr is None else dict(
+                tr, algorithmic_bytes=n * (4 * n_obs * 4 + 56), source=os.path.relpath(
+                    TRAFFIC_PROFILE, ROOT)),
             "kernel": "lm_kernel (plain-LM leg: one launch per step)",
             "kernel_ms": round(ev_p, 4),
             "executed_tflops": round(executed, 3),

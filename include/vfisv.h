@@ -93,6 +93,9 @@ typedef struct {
   double rel_tol;      /* relative chi^2 decrease ending the fit (1e-5)     */
   uint32_t free_mask;  /* bit p set: parameter p free (0x3FF)               */
   int grid_waves;      /* persistent grid size in waves; 0 = auto           */
+  int chunk_log2;      /* pixel queue block = 2^chunk_log2 consecutive      */
+                       /* pixels, 0..20 (default 8); scheduling only: the   */
+                       /* per-pixel results do not depend on it             */
 } vfisv_options;
 
 /* Work counters of the most recent vfisv_invert on a context. */
@@ -175,6 +178,19 @@ int vfisv_invert(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
 /* Work counters of the most recent vfisv_invert (synchronises the
  * context's device). */
 int vfisv_get_counters(vfisv_ctx *ctx, vfisv_counters *out);
+
+/* Histogram of per-pixel iteration counts (the iters output of an
+ * inversion; the paper's fixed-iteration scheme, Sect. 4.2, is replaced here
+ * by exits whose cost varies per pixel, and this is its distribution).
+ *   iters: dev [n] int32 (may be NULL when n == 0).
+ *   hist:  host [n_bins] int64, 1 <= n_bins <= 4096; hist[i] = number of
+ *          pixels with iters == i for i < n_bins - 1, the last bin counts
+ *          iters >= n_bins - 1 (negative values count in bin 0).
+ * Enqueued on `stream` after the work already there, then synchronises that
+ * stream and writes hist.  Uses a context-owned device buffer: calls on one
+ * context must not overlap.  Exact integer counts. */
+int vfisv_iter_histogram(vfisv_ctx *ctx, int64_t n, const int32_t *iters, int n_bins,
+                         int64_t *hist, void *stream);
 
 /* ---- damped normal-equation solve (Eqs. 3-5), for verification -------- */
 

@@ -42,7 +42,8 @@ class _InstInfo(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
-                ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int)]
+                ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int),
+                ("chunk_log2", ctypes.c_int)]
 
 
 class _Counters(ctypes.Structure):
@@ -58,7 +59,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
-           "vfisv_mlp_load", "vfisv_invert_learned")
+           "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram")
 
 _LIB = None
 
@@ -87,6 +88,8 @@ def lib():
         L.vfisv_get_counters.argtypes = [_vp, ctypes.POINTER(_Counters)]
         L.vfisv_solve.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_uint32, _vp,
                                   _vp, _vp]
+        L.vfisv_iter_histogram.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int64), _vp]
         _LIB = L
     return _LIB
 
@@ -197,10 +200,11 @@ class Options:
     rel_tol: float = 1e-5
     free_mask: int = 0x3FF
     grid_waves: int = 0
+    chunk_log2: int = 8
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
-                        self.grid_waves)
+                        self.grid_waves, self.chunk_log2)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None):
@@ -243,6 +247,19 @@ def invert(ctx, inst, stokes, W, init=None, opts=None, out=None):
         _ptr(out["iters"], torch.int32, dev, name="iters"),
         _ptr(out["status"], torch.int32, dev, name="status"), _stream(dev)), "vfisv_invert")
     return out
+
+
+def iter_histogram(ctx, iters, n_bins=51):
+    """Histogram of iteration counts (device int32 tensor [n]) as a host
+    numpy int64 array [n_bins]; the last bin counts iters >= n_bins - 1."""
+    import numpy as np
+    dev = ctx.device
+    hist = np.zeros(n_bins, dtype=np.int64)
+    ctx._check(lib().vfisv_iter_histogram(
+        ctx._h, iters.shape[0], _ptr(iters, torch.int32, dev, name="iters"), int(n_bins),
+        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(dev)),
+        "vfisv_iter_histogram")
+    return hist
 
 
 def solve(ctx, H, g, eps, free_mask=0x3FF):

@@ -52,6 +52,8 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
       !std::isfinite(o.rel_tol))
     return fail(ctx, VFISV_E_INVALID, "options: eps0, eps_max must be > 0 and rel_tol >= 0");
   if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "options: grid_waves < 0");
+  if (o.chunk_log2 < 0 || o.chunk_log2 > 20)
+    return fail(ctx, VFISV_E_INVALID, "options: chunk_log2 outside 0..20");
   o.free_mask &= 0x3FFu;
   int nfree = 0;
   for (int p = 0; p < NPAR; ++p) nfree += (o.free_mask >> p) & 1u;
@@ -90,6 +92,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.max_iter = o.max_iter;
   a.W_pp = W_pp ? 1 : 0;
   a.free_mask = o.free_mask & 0x3FFu;
+  a.chunk_log2 = o.chunk_log2;
   int64_t cap = (int64_t)ctx->num_cus * ctx->lm_blocks_per_cu;
   if (o.grid_waves > 0) cap = o.grid_waves;
   if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
@@ -170,7 +173,7 @@ int vfisv_create(vfisv_ctx** out, int device) {
     delete c;
     return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: workspace allocation");
   }
-  e = hipMalloc(&c->d_work, sizeof(unsigned long long) * WORK_SLOTS);
+  e = hipMalloc(&c->d_work, sizeof(unsigned long long) * (WORK_SLOTS + HIST_MAX));
   if (e != hipSuccess) {
     hipFree(c->d_ws);
     delete c;
@@ -212,6 +215,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->rel_tol = 1e-5;
   o->free_mask = 0x3FFu;
   o->grid_waves = 0;
+  o->chunk_log2 = 8;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -390,6 +394,27 @@ int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
   out->passes = (int64_t)w[4];
   out->svd_fallbacks = (int64_t)w[5];
   out->grid_waves = (int64_t)w[6];
+  return VFISV_OK;
+}
+
+int vfisv_iter_histogram(vfisv_ctx* ctx, int64_t n, const int32_t* iters, int n_bins,
+                         int64_t* hist, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "iter_histogram: ctx is NULL");
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "iter_histogram: n < 0");
+  if (n_bins < 1 || n_bins > HIST_MAX)
+    return fail(ctx, VFISV_E_INVALID, "iter_histogram: n_bins outside 1..4096");
+  if (!hist || (n > 0 && !iters)) return fail(ctx, VFISV_E_INVALID, "iter_histogram: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* bins = ctx->d_work + WORK_SLOTS;
+  e = launch_hist(iters, n, n_bins, bins, ctx->num_cus * 8, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "iter_histogram launch");
+  std::vector<unsigned long long> h((size_t)n_bins);
+  e = hipMemcpyAsync(h.data(), bins, sizeof(unsigned long long) * n_bins, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "iter_histogram copy");
+  for (int b = 0; b < n_bins; ++b) hist[b] = (int64_t)h[(size_t)b];
   return VFISV_OK;
 }
 

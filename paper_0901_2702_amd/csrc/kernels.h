@@ -9,9 +9,12 @@
 
 namespace vfisv {
 
-// work[] slots: 0 next pixel, 1 pixels done, 2 trials, 3 accepts,
-// 4 passes, 5 eigen fallbacks, 6 waves
-constexpr int WORK_SLOTS = 8;
+// work[] slots: 1 pixels done, 2 trials, 3 accepts, 4 passes, 5 eigen
+// fallbacks, 6 waves; QUEUE_SLOT0 + q: head of pixel queue q (one per XCD)
+constexpr int NQ = 8;
+constexpr int QUEUE_SLOT0 = 8;
+constexpr int WORK_SLOTS = QUEUE_SLOT0 + NQ;
+constexpr int HIST_MAX = 4096;  // iteration-histogram bins (kept after the work slots)
 
 struct LMArgs {
   Consts C;
@@ -33,6 +36,7 @@ struct LMArgs {
   int max_iter;
   int W_pp;
   uint32_t free_mask;
+  int chunk_log2;  // pixels per queue block = 2^chunk_log2
 };
 
 struct SynthArgs {
@@ -58,6 +62,8 @@ struct SolveArgs {
 };
 
 hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s);
+hipError_t launch_hist(const int32_t* iters, int64_t n, int n_bins, unsigned long long* out,
+                       int max_blocks, hipStream_t s);
 hipError_t launch_lm(const LMArgs& a, int grid, hipStream_t s);
 hipError_t launch_synth(const SynthArgs& a, bool deriv, int grid, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);

@@ -21,7 +21,8 @@
 namespace vfisv {
 
 __global__ void reset_work_kernel(unsigned long long* work, int all) {
-  if (threadIdx.x < (all ? WORK_SLOTS : 1)) work[threadIdx.x] = 0ull;
+  const int t = threadIdx.x;
+  if (t < WORK_SLOTS && (all || t >= QUEUE_SLOT0)) work[t] = 0ull;
 }
 
 __device__ __forceinline__ unsigned long long bcast_lane0(unsigned long long v) {
@@ -47,6 +48,16 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
 
   const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
+  // Pixel queues: queue q owns the blocks b of 2^chunk_log2 consecutive
+  // positions with b % NQ == q; its k-th position is
+  // ((k / chunk) * NQ + q) * chunk + k % chunk.  A wave takes positions from the queue of its XCD first
+  // (workgroups are dispatched to the XCDs round-robin), so the lines of the
+  // pixels one XCD works on stay in that XCD's L2, then from the others.
+  const int home = blockIdx.x % NQ;
+  const int sh = A.chunk_log2;
+  const unsigned long long ch = 1ull << sh;
+  const unsigned long long full = n_total >> (sh + 3), rem = n_total & ((ch << 3) - 1ull);
+  unsigned dry = 0u;  // queues this wave has seen empty (wave-uniform)
   bool live = false, fresh = false, exhausted = false;
   int64_t pix = 0;
   float Mb[NPAR], Mc[NPAR];
@@ -56,55 +67,61 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
 
   for (;;) {
     // ---- refill lanes whose pixel finished --------------------------------
-    {
-      const bool need = !live && !exhausted;
-      const unsigned long long nm = __ballot(need);
-      if (nm) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&A.work[0], (unsigned long long)__popcll(nm));
-        base = bcast_lane0(base);
-        if (need) {
-          const int rank = __popcll(nm & ((1ull << lane) - 1ull));
-          const unsigned long long idx = base + (unsigned long long)rank;
-          if (idx < n_total) {
-            pix = A.idx ? (int64_t)A.idx[idx] : (int64_t)idx;
-            const float* obs = A.stokes + pix * ROWS;
-            const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
-            bool finite = true;
+    unsigned long long nm = __ballot(!live && !exhausted);
+    for (int j = 0; j < NQ && nm != 0ull; ++j) {
+      const int q = (home + j) % NQ;
+      if (dry & (1u << q)) continue;
+      const unsigned long long r0 = rem > (unsigned long long)q * ch ? rem - q * ch : 0ull;
+      const unsigned long long cnt = full * ch + (r0 < ch ? r0 : ch);
+      const unsigned long long m = (unsigned long long)__popcll(nm);
+      unsigned long long k0 = 0;
+      if (lane == 0) k0 = atomicAdd(&A.work[QUEUE_SLOT0 + q], m);
+      k0 = bcast_lane0(k0);
+      const unsigned long long got = k0 < cnt ? (cnt - k0 < m ? cnt - k0 : m) : 0ull;
+      if (got < m) dry |= 1u << q;
+      if (got == 0ull) continue;
+      const bool need = (nm >> lane) & 1ull;
+      const unsigned long long rank = (unsigned long long)__popcll(nm & ((1ull << lane) - 1ull));
+      const bool take = need && rank < got;
+      if (take) {
+        const unsigned long long k = k0 + rank;
+        const unsigned long long pos =
+            ((((k >> sh) << 3) + (unsigned long long)q) << sh) + (k & (ch - 1ull));
+        pix = A.idx ? (int64_t)A.idx[pos] : (int64_t)pos;
+        const float* obs = A.stokes + pix * ROWS;
+        const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
+        bool finite = true;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r)
-              finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
-            if (!finite) {
+        for (int r = 0; r < ROWS; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
+        if (!finite) {
 #pragma unroll
-              for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = __builtin_nanf("");
-              A.chi2[pix] = __builtin_nan("");
-              A.iters[pix] = 0;
-              if (A.status) A.status[pix] = 3;
-              ++n_pix;
-            } else {
-              double M0[NPAR];
-              if (A.init) {
+          for (int q2 = 0; q2 < NPAR; ++q2) A.params[pix * NPAR + q2] = __builtin_nanf("");
+          A.chi2[pix] = __builtin_nan("");
+          A.iters[pix] = 0;
+          if (A.status) A.status[pix] = 3;
+          ++n_pix;
+        } else {
+          double M0[NPAR];
+          if (A.init) {
 #pragma unroll
-                for (int q = 0; q < NPAR; ++q) M0[q] = (double)A.init[pix * NPAR + q];
-              } else {
-                const double d0[NPAR] = {1500.0, 90.0, 90.0, 0.0, 35.0, 0.25, 15.5, 0.3, 0.7, 0.6};
-#pragma unroll
-                for (int q = 0; q < NPAR; ++q) M0[q] = d0[q];
-              }
-              project(M0);
-#pragma unroll
-              for (int q = 0; q < NPAR; ++q) Mc[q] = (float)M0[q];
-              live = true;
-              fresh = true;
-              eps = A.eps0;
-              it = 0;
-            }
+            for (int q2 = 0; q2 < NPAR; ++q2) M0[q2] = (double)A.init[pix * NPAR + q2];
           } else {
-            exhausted = true;
+            const double d0[NPAR] = {1500.0, 90.0, 90.0, 0.0, 35.0, 0.25, 15.5, 0.3, 0.7, 0.6};
+#pragma unroll
+            for (int q2 = 0; q2 < NPAR; ++q2) M0[q2] = d0[q2];
           }
+          project(M0);
+#pragma unroll
+          for (int q2 = 0; q2 < NPAR; ++q2) Mc[q2] = (float)M0[q2];
+          live = true;
+          fresh = true;
+          eps = A.eps0;
+          it = 0;
         }
       }
+      nm &= ~__ballot(take);
     }
+    if (nm != 0ull && dry == (1u << NQ) - 1u) exhausted = exhausted || ((nm >> lane) & 1ull);
     if (__ballot(live) == 0ull) {
       if (__ballot(!exhausted) == 0ull) break;
       continue;  // lanes that met non-finite input refill first
@@ -295,6 +312,39 @@ __global__ __launch_bounds__(64) void solve_kernel(const SolveArgs A) {
 }
 
 // ---- launch helpers (host) --------------------------------------------------
+
+// Histogram of iteration counts: per-block LDS counts, flushed with one
+// atomic per non-empty bin and block.  Values >= n_bins - 1 land in the last
+// bin, negative values in bin 0.
+__global__ __launch_bounds__(256) void hist_kernel(const int32_t* __restrict__ iters, int64_t n,
+                                                   int n_bins, unsigned long long* out) {
+  __shared__ unsigned int h[HIST_MAX];
+  for (int b = threadIdx.x; b < n_bins; b += 256) h[b] = 0u;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int v = iters[i];
+    atomicAdd(&h[v < 0 ? 0 : (v >= n_bins ? n_bins - 1 : v)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_bins; b += 256)
+    if (h[b]) atomicAdd(&out[b], (unsigned long long)h[b]);
+}
+
+__global__ void zero_bins_kernel(unsigned long long* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+hipError_t launch_hist(const int32_t* iters, int64_t n, int n_bins, unsigned long long* out,
+                       int max_blocks, hipStream_t s) {
+  zero_bins_kernel<<<(n_bins + 255) / 256, 256, 0, s>>>(out, n_bins);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  const int64_t want = (n + 255) / 256;
+  const int blocks = (int)(want < max_blocks ? want : max_blocks);
+  hist_kernel<<<blocks, 256, 0, s>>>(iters, n, n_bins, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
   reset_work_kernel<<<1, 64, 0, s>>>(work, all ? 1 : 0);

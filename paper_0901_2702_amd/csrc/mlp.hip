@@ -293,15 +293,26 @@ __global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
   for (int c = 0; c < NPAR; ++c) params[m * NPAR + c] = (float)P[c];
 }
 
-__global__ void fallback_select_kernel(const double* __restrict__ chi2, int64_t n, double tau,
-                                       int32_t* list, unsigned long long* count) {
+__global__ __launch_bounds__(256) void fallback_select_kernel(const double* __restrict__ chi2,
+                                                              int64_t n, double tau,
+                                                              int32_t* list,
+                                                              unsigned long long* count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double c = chi2[i];
-  if (!(c <= tau) && !isnan(c)) {  // not acceptable (non-finite input stays as is)
-    const unsigned long long slot = atomicAdd(count, 1ull);
-    list[slot] = (int32_t)i;
+  bool sel = false;
+  if (i < n) {
+    const double c = chi2[i];
+    sel = !(c <= tau) && !isnan(c);  // not acceptable (non-finite input stays as is)
   }
+  // one counter update per wave: lanes take consecutive slots by rank
+  const unsigned long long m = __ballot(sel);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == __ffsll((long long)m) - 1) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  const unsigned lo = __shfl((unsigned)(base & 0xffffffffull), __ffsll((long long)m) - 1);
+  const unsigned hi = __shfl((unsigned)(base >> 32), __ffsll((long long)m) - 1);
+  base = ((unsigned long long)hi << 32) | lo;
+  if (sel) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
 }
 
 __global__ void fallback_merge_kernel(const int32_t* __restrict__ list,

@@ -273,8 +273,34 @@ def test_scheduling_does_not_change_results(ctx, hmi):
     c = ctx.counters()
     assert c["pixels"] == 3000 and c["trials"] == ref["iters"].sum()
     assert c["passes"] == c["trials"] + 3000
-    for gw in (1, 3, 17, 500):
-        out = vf.invert(ctx, inst, o, W, opts=vf.Options(grid_waves=gw))
-        assert ctx.counters()["grid_waves"] == min(gw, (3000 + 63) // 64)
+    for gw, cl in ((1, 8), (3, 0), (17, 3), (500, 8), (0, 20), (0, 6)):
+        out = vf.invert(ctx, inst, o, W, opts=vf.Options(grid_waves=gw, chunk_log2=cl))
+        c = ctx.counters()
+        assert c["grid_waves"] == min(gw or 10 ** 9, (3000 + 63) // 64)
+        assert c["pixels"] == 3000 and c["passes"] == c["trials"] + 3000
         for k in ref:
-            assert np.array_equal(out[k].cpu().numpy(), ref[k]), (gw, k)
+            assert np.array_equal(out[k].cpu().numpy(), ref[k]), (gw, cl, k)
+
+
+@pytest.mark.gpu
+def test_iter_histogram_is_exact(ctx, hmi):
+    """Integer work: the device histogram equals numpy's count exactly."""
+    import torch
+    rng = np.random.default_rng(77)
+    for n, n_bins in ((0, 5), (1, 1), (1000, 51), (300_001, 51), (70_000, 4096), (5000, 7)):
+        it = rng.integers(0, 80, size=n).astype(np.int32)
+        h = vf.iter_histogram(ctx, torch.tensor(it, device=ctx.device), n_bins)
+        want = np.bincount(np.minimum(it, n_bins - 1), minlength=n_bins)
+        assert h.dtype == np.int64 and np.array_equal(h, want), (n, n_bins)
+    with pytest.raises(Exception):
+        vf.iter_histogram(ctx, torch.zeros(3, dtype=torch.int32, device=ctx.device), 0)
+    with pytest.raises(Exception):
+        vf.iter_histogram(ctx, torch.zeros(3, dtype=torch.int32, device=ctx.device), 4097)
+    # on an inversion's own output
+    spec, inst, oi = hmi
+    P, obs = _observations(oi, spec, 2000, 61)
+    out = vf.invert(ctx, inst, _dev(ctx, obs), _dev(ctx, wl.weights(spec.n_obs)))
+    it = out["iters"].cpu().numpy()
+    h = vf.iter_histogram(ctx, out["iters"], 51)
+    assert np.array_equal(h, np.bincount(it, minlength=51)) and h.sum() == 2000
+    assert (h * np.arange(51)).sum() == ctx.counters()["trials"]
