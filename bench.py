@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
+    ap.add_argument("--workload", choices=("learned", "full-disk"), default="learned",
+                    help="learned: the learned-start vs plain LM line (default); full-disk: "
+                         "plain LM over the 13.2M-pixel disk with clustered active regions")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -133,6 +136,8 @@ def main():
 
     if args.plain_only:
         return plain_only(args, ctx, inst, spec, log)
+    if args.workload == "full-disk":
+        return full_disk(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -294,6 +299,131 @@ def main():
                       "model, max 50 iterations" % (m, n),
             "seconds": round(dt, 3),
         }
+    print(json.dumps(result), flush=True)
+
+
+def full_disk(args, ctx, inst, spec, log):
+    """Plain LM over the full disk (13,176,792 pixels, 20% active in clustered
+    regions), the i.i.d. variant, and the pixel-queue block size."""
+    import numpy as np
+    import torch
+
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    dev = ctx.device
+    stream = torch.cuda.current_stream(dev)
+    seed = wl.CONFIGS["cfg2"]["seed"]
+    n_obs = spec.n_obs
+    W = torch.tensor(wl.weights(n_obs), device=dev)
+
+    def make(clustered):
+        P, active, mask = wl.full_disk(seed=seed, clustered=clustered)
+        noise = wl.draw_noise(P.shape[0], n_obs, seed).astype(np.float32)
+        obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                            noise=torch.tensor(noise, device=dev))
+        torch.cuda.synchronize()
+        return P, active, noise, obs
+
+    def timed(obs, out, opts, steps):
+        for _ in range(args.warmup):
+            vf.invert(ctx, inst, obs, W, opts=opts, out=out)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            vf.invert(ctx, inst, obs, W, opts=opts, out=out)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) * 1e3 / steps
+        return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    t0 = time.perf_counter()
+    P, active, noise, obs = make(True)
+    n = P.shape[0]
+    log("full disk: %d pixels, %.4f active, generated in %.1f s"
+        % (n, active.mean(), time.perf_counter() - t0))
+    out = dict(params=torch.empty((n, 10), device=dev, dtype=torch.float32),
+               chi2=torch.empty(n, device=dev, dtype=torch.float64),
+               iters=torch.empty(n, device=dev, dtype=torch.int32),
+               status=torch.empty(n, device=dev, dtype=torch.int32))
+    opts = vf.Options()
+    ms, ev_ms = timed(obs, out, opts, args.steps)
+    c = ctx.counters()
+    iters = out["iters"].cpu().numpy()
+    hist = vf.iter_histogram(ctx, out["iters"], opts.max_iter + 1)
+    st = out["status"].cpu().numpy()
+    chi2 = out["chi2"].cpu().numpy()
+    log("clustered: %.2f ms per step" % ms)
+
+    sweep = {}
+    for cl in (0, 4, 8, 12, 16):
+        sweep[str(cl)] = round(timed(obs, out, vf.Options(chunk_log2=cl), 2)[1], 3)
+    log("chunk_log2 sweep (ms): %s" % sweep)
+
+    f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
+    alg = c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
+    achieved = alg / (ev_ms * 1e-3) / 1e12
+
+    del obs
+    torch.cuda.empty_cache()
+    P_iid, active_iid, _, obs_iid = make(False)
+    ms_iid, _ = timed(obs_iid, out, opts, max(2, args.steps // 2))
+    iters_iid = out["iters"].cpu().numpy()
+    del obs_iid
+    log("i.i.d.: %.2f ms per step" % ms_iid)
+
+    result = {
+        "metric": "inverted pixels/s on 1 MI355X, full disk, plain LM",
+        "value": round(n / (ms * 1e-3), 1),
+        "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "full disk 4096^2 (13,176,792 pixels), 80%% quiet "
+                               "(B ~ U[0,200] G) / 20%% active (B ~ U[500,3500] G) in clustered "
+                               "regions, cfg0 priors otherwise, seed %d; plain LM from the "
+                               "default model, <= 50 trials" % seed,
+                   "pixels": n, "active_fraction": round(float(active.mean()), 5)},
+        "iterations": {
+            "histogram": hist.tolist(),
+            "mean": float(iters.mean()),
+            "mean_quiet": float(iters[~active].mean()),
+            "mean_active": float(iters[active].mean()),
+            "status_counts": np.bincount(st, minlength=4).tolist(),
+            "median_chi2": float(np.median(chi2)),
+            "frac_chi2_below_2": float(np.mean(chi2 < 2.0)),
+        },
+        "iid_variant": {"ms_per_step": round(ms_iid, 3),
+                        "value": round(n / (ms_iid * 1e-3), 1),
+                        "active_fraction": round(float(active_iid.mean()), 5),
+                        "mean_iters": float(iters_iid.mean())},
+        "chunk_log2_sweep_ms": sweep,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None, "kernel": "lm_kernel (one launch per step)",
+                     "kernel_ms": round(ev_ms, 3),
+                     "work": {k: c[k] for k in ("trials", "accepts", "passes", "pixels")}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(args.cpu_sample, n)
+        sel = np.linspace(0, n - 1, m).astype(np.int64)  # every (n/m)-th disk pixel
+        oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+        obs_cpu = (oracle.forward_batch(oi, P[sel]) + noise[sel].astype(np.float64)) \
+            .astype(np.float32)
+        t1 = time.perf_counter()
+        ref = oracle.invert(oi, obs_cpu, wl.weights(n_obs))
+        dt = time.perf_counter() - t1
+        result["cpu_baseline"] = {
+            "value": round(m / dt, 2), "unit": "pixels/s", "cores": ref["threads"],
+            "kind": "oracle",
+            "sample": "%d disk pixels evenly spaced in disk order (same parameters and "
+                      "noise, observations synthesised by the FP64 oracle), plain LM from "
+                      "the default model, max 50 iterations" % m,
+            "seconds": round(dt, 3)}
     print(json.dumps(result), flush=True)
 
 

@@ -19,15 +19,20 @@
  *    pointers are read during the call only.
  *  - stream is a hipStream_t passed as void* (NULL: the null stream).  Work
  *    is enqueued asynchronously; the caller synchronises.
- *  - A context is not thread-safe: use one per host thread, or lock.  Two
- *    inversions in flight on different streams of one context race on the
- *    context's work counters (results stay correct; counters do not).
+ *  - A context is not thread-safe: use one per host thread, or lock.  The
+ *    inversions of one context share its pixel-queue heads and counters:
+ *    they must not be in flight at the same time (enqueue them on one
+ *    stream, or use one context per stream).
  *
  * Model parameters (API order and units), 10 per pixel, float32:
  *   0 B [G], 1 inclination gamma [deg], 2 azimuth psi [deg],
  *   3 line-of-sight velocity [km/s] (positive = redshift),
  *   4 Doppler width [mA], 5 damping a, 6 eta0 (line-to-continuum absorption
  *   ratio), 7 S0, 8 S1 (source function S0 + S1 tau), 9 filling factor alpha.
+ *   Fitted models lie in the box B [0, 5000], gamma [0, 180], psi [0, 180]
+ *   (0 and 180 are the same azimuth; values just below 180 round to 180 in
+ *   float32), v [-20, 20], Doppler width [5, 150], a [0, 5], eta0
+ *   [1e-3, 1e3], S0 [-1, 3], S1 [0, 5], alpha [0, 1].
  *   (Sect. 2 model vector with the macroturbulence fixed at zero, which
  *   Sect. 4.1 shows can be dropped.)
  *

@@ -16,6 +16,12 @@ synthetic; shapes follow the paper's HMI set-up of Sect. 1 and Sect. 5):
   profile; synthesis on a x4 grid padded by 8 points per side (464 points),
   15-tap rows.
 
+Full disk ("cfg2"): the pixels of a 4096 x 4096 image inside the disk of
+centre (2047.5, 2047.5) and radius 2048 (13,176,792 pixels, row-major), 80%
+quiet (B ~ U[0,200] G) and 20% active (B ~ U[500,3500] G); active pixels are
+a seeded union of random discs (spatially clustered load), or i.i.d. in the
+variant; the other parameters follow the cfg0 priors.
+
 Parameter priors ("cfg0"): B ~ U[0,3000] G, cos(gamma) ~ U[-1,1],
 psi ~ U[0,180) deg, v ~ U[-3,3] km/s, Doppler width ~ U[20,50] mA,
 a ~ U[0,0.5], eta0 ~ U[1,30], S0 ~ U[0.1,0.5], S1 = 1 - S0,
@@ -125,3 +131,40 @@ def disk_mask(grid=4096):
     c = (grid - 1) / 2.0
     y, x = np.mgrid[0:grid, 0:grid]
     return (x - c) ** 2 + (y - c) ** 2 <= (grid / 2.0) ** 2
+
+
+def full_disk(grid=4096, seed=1002, clustered=True, active_frac=0.2, r_range=(16.0, 128.0)):
+    """Config-2 parameters.  Returns (P [n, 10] float64 in disk row-major
+    order, active [n] bool, mask [grid, grid] bool).
+
+    Clustered: discs with centres uniform over the bounding square and radii
+    ~ U[r_range] are added until the active pixels cover at least
+    active_frac of the disk.  I.i.d.: each disk pixel is active with
+    probability active_frac."""
+    mask = disk_mask(grid)
+    n = int(mask.sum())
+    rng = np.random.default_rng([seed, 11])
+    if clustered:
+        img = np.zeros((grid, grid), dtype=bool)
+        target = active_frac * n
+        covered = 0
+        while covered < target:
+            cx, cy = rng.uniform(0.0, grid, 2)
+            r = rng.uniform(*r_range)
+            x0, x1 = max(int(cx - r), 0), min(int(cx + r) + 2, grid)
+            y0, y1 = max(int(cy - r), 0), min(int(cy + r) + 2, grid)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            yy, xx = np.mgrid[y0:y1, x0:x1]
+            disc = (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+            sub = img[y0:y1, x0:x1]
+            covered += int((disc & ~sub & mask[y0:y1, x0:x1]).sum())
+            sub |= disc
+        active = img[mask]
+    else:
+        active = rng.random(n) < active_frac
+    P = draw_params(n, seed)
+    quiet_B = rng.uniform(0.0, 200.0, n)
+    active_B = rng.uniform(500.0, 3500.0, n)
+    P[:, 0] = np.where(active, active_B, quiet_B)
+    return P, active, mask
