@@ -133,10 +133,17 @@ const char *vfisv_version(void);
 
 /* ---- instrument ------------------------------------------------------- */
 
-/* Copy the instrument to the device (host inputs are copied; the
- * instrument owns its device tables).  Validates sizes, finiteness and
- * non-negativity of the filter.  n_obs other than 6 returns
- * VFISV_E_UNSUPPORTED in this build. */
+/* Copy the instrument (line, synthesis grid and filter of Sect. 5: the
+ * observed samples are linear combinations of the synthesised profile on
+ * the fine grid) to the device; host inputs are copied and the instrument
+ * owns its device tables.  Validates sizes (1 <= n_fine, n_obs <= 4096),
+ * finiteness and non-negativity of the filter.  Two layouts are served:
+ *  - n_obs == 6 (HMI-shaped): taps anywhere on the grid;
+ *  - banded (any other n_obs): the kept taps of row i lie within the 16
+ *    synthesis points a0 + 4 i .. a0 + 4 i + 15 for one a0, as for a
+ *    Gaussian instrumental profile of up to 16 taps on a grid oversampled
+ *    4 times (e.g. 112 samples, 15 taps, 464 points).
+ * Any other filter returns VFISV_E_UNSUPPORTED. */
 int vfisv_instrument_create(vfisv_ctx *ctx, const vfisv_instrument_desc *desc,
                             vfisv_instrument **out);
 int vfisv_instrument_info_get(const vfisv_instrument *inst, vfisv_instrument_info *info);
@@ -180,8 +187,33 @@ int vfisv_invert(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                  const float *init, const vfisv_options *opt, float *params,
                  double *chi2, int32_t *iters, int32_t *status, void *stream);
 
-/* Work counters of the most recent vfisv_invert (synchronises the
- * context's device). */
+/* Several batches in one persistent launch (e.g. fine-spectrum and
+ * HMI-shaped pixels together).  Each batch has its own instrument, pixels,
+ * weights, optional start and outputs, with the same meaning as the
+ * arguments of vfisv_invert; all share opt (the degrees of freedom of
+ * Eq. 1 follow each batch's instrument).  Every wave of the launch works
+ * through the batches in the order given, moving on when the current
+ * batch has no pixel left, so put the batch with the most work per pixel
+ * first: the later batches then fill the waves that the earlier ones leave
+ * idle.  1 <= n_batches <= 4; batches with n == 0 are allowed.  The
+ * per-pixel results equal those of vfisv_invert on each batch alone. */
+typedef struct {
+  const vfisv_instrument *inst;
+  int64_t n;
+  const float *stokes;   /* dev [n][4][n_obs]                          */
+  const float *W;        /* dev [4][n_obs], or [n][4][n_obs]            */
+  int W_per_pixel;
+  const float *init;     /* dev [n][10] or NULL (default model)         */
+  float *params;         /* dev [n][10]                                 */
+  double *chi2;          /* dev [n]                                     */
+  int32_t *iters;        /* dev [n]                                     */
+  int32_t *status;       /* dev [n] or NULL                             */
+} vfisv_batch;
+int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batches,
+                         const vfisv_options *opt, void *stream);
+
+/* Work counters of the most recent vfisv_invert or vfisv_invert_batches
+ * (synchronises the context's device). */
 int vfisv_get_counters(vfisv_ctx *ctx, vfisv_counters *out);
 
 /* Histogram of per-pixel iteration counts (the iters output of an

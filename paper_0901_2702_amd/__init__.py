@@ -46,6 +46,14 @@ class _Options(ctypes.Structure):
                 ("chunk_log2", ctypes.c_int)]
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_void_p), ("n", ctypes.c_int64), ("stokes", ctypes.c_void_p),
+                ("W", ctypes.c_void_p), ("W_per_pixel", ctypes.c_int),
+                ("init", ctypes.c_void_p), ("params", ctypes.c_void_p),
+                ("chi2", ctypes.c_void_p), ("iters", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
 class _Counters(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("trials", ctypes.c_int64),
                 ("accepts", ctypes.c_int64), ("passes", ctypes.c_int64),
@@ -59,7 +67,8 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
-           "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram")
+           "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
+           "vfisv_invert_batches")
 
 _LIB = None
 
@@ -90,6 +99,8 @@ def lib():
                                   _vp, _vp]
         L.vfisv_iter_histogram.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int64), _vp]
+        L.vfisv_invert_batches.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.c_int,
+                                           ctypes.POINTER(_Options), _vp]
         _LIB = L
     return _LIB
 
@@ -247,6 +258,41 @@ def invert(ctx, inst, stokes, W, init=None, opts=None, out=None):
         _ptr(out["iters"], torch.int32, dev, name="iters"),
         _ptr(out["status"], torch.int32, dev, name="status"), _stream(dev)), "vfisv_invert")
     return out
+
+
+def _alloc_out(n, dev):
+    return dict(params=torch.empty((n, NPAR), device=dev, dtype=torch.float32),
+                chi2=torch.empty(n, device=dev, dtype=torch.float64),
+                iters=torch.empty(n, device=dev, dtype=torch.int32),
+                status=torch.empty(n, device=dev, dtype=torch.int32))
+
+
+def invert_batches(ctx, batches, opts=None):
+    """Several batches in one launch.  ``batches``: list of dicts with keys
+    inst, stokes [n, 4, n_obs], W ([4, n_obs] or [n, 4, n_obs]), and
+    optionally init [n, 10] and out (as returned by ``invert``).  Returns
+    the list of output dicts, in order."""
+    dev = ctx.device
+    opts = opts or Options()
+    arr = (_Batch * len(batches))()
+    outs = []
+    for i, b in enumerate(batches):
+        n = b["stokes"].shape[0]
+        out = b.get("out") or _alloc_out(n, dev)
+        outs.append(out)
+        W = b["W"]
+        h = b["inst"]._h
+        arr[i] = _Batch(h.value if isinstance(h, ctypes.c_void_p) else h, n, _ptr(b["stokes"], torch.float32, dev, name="stokes"),
+                        _ptr(W, torch.float32, dev, name="W"), 1 if W.dim() == 3 else 0,
+                        _ptr(b.get("init"), torch.float32, dev, name="init"),
+                        _ptr(out["params"], torch.float32, dev, name="params"),
+                        _ptr(out["chi2"], torch.float64, dev, name="chi2"),
+                        _ptr(out["iters"], torch.int32, dev, name="iters"),
+                        _ptr(out["status"], torch.int32, dev, name="status"))
+    o = opts.c()
+    ctx._check(lib().vfisv_invert_batches(ctx._h, arr, len(batches), ctypes.byref(o),
+                                          _stream(dev)), "vfisv_invert_batches")
+    return outs
 
 
 def iter_histogram(ctx, iters, n_bins=51):

@@ -3,7 +3,10 @@
 // launches.  No torch types cross this boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -65,14 +68,16 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   return VFISV_OK;
 }
 
-int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
-               const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
-               const float* W, int W_pp, const float* init, const vfisv_options& o,
-               double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
-               hipStream_t s, bool reset_all) {
-  LMArgs a;
+static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                         const unsigned long long* n_dev, const int32_t* idx,
+                         const float* stokes, const float* W, int W_pp, const float* init,
+                         const vfisv_options& o, double inv_dof, float* params, double* chi2,
+                         int32_t* iters, int32_t* status, LMArgs& a) {
   a.C = inst->C;
   a.pts = inst->d_pts;
+  a.blocks = inst->d_blocks;
+  a.row_sums = inst->d_row_sums;
+  a.qbase = QUEUE_SLOT0;
   a.stokes = stokes;
   a.W = W;
   a.init = init;
@@ -82,6 +87,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.status = status;
   a.work = ctx->d_work;
   a.ws = ctx->d_ws;
+  a.ws_stride = 0;
   a.n = n;
   a.n_dev = n_dev;
   a.idx = idx;
@@ -93,14 +99,30 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.W_pp = W_pp ? 1 : 0;
   a.free_mask = o.free_mask & 0x3FFu;
   a.chunk_log2 = o.chunk_log2;
-  int64_t cap = (int64_t)ctx->num_cus * ctx->lm_blocks_per_cu;
+}
+
+static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o) {
+  int64_t cap = (int64_t)ctx->num_cus * bpc;
   if (o.grid_waves > 0) cap = o.grid_waves;
   if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
-  const int grid = grid_for(n, cap);
+  return grid_for(n, cap);
+}
+
+int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+               const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
+               const float* W, int W_pp, const float* init, const vfisv_options& o,
+               double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
+               hipStream_t s, bool reset_all) {
+  LMArgs a;
+  fill_lm_args(ctx, inst, n, n_dev, idx, stokes, W, W_pp, init, o, inv_dof, params, chi2, iters,
+               status, a);
+  const int grid = lm_grid(ctx, n,
+                           inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
+                                                     : ctx->band_blocks_per_cu, o);
   a.ws_stride = (int64_t)grid * 64;
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
-  e = launch_lm(a, grid, s);
+  e = launch_lm(a, inst->kind, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert launch");
   return VFISV_OK;
 }
@@ -166,6 +188,10 @@ int vfisv_create(vfisv_ctx** out, int device) {
   e = lm_blocks_per_cu(&bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
   c->lm_blocks_per_cu = bpc;
+  bpc = 0;
+  e = band_blocks_per_cu(&bpc);
+  if (e != hipSuccess || bpc < 1) bpc = 1;
+  c->band_blocks_per_cu = bpc;
   // fallback workspace: WS_DOUBLES per lane of the largest persistent grid
   c->ws_lanes = (int64_t)c->num_cus * 8 * 64;
   e = hipMalloc(&c->d_ws, sizeof(double) * WS_DOUBLES * c->ws_lanes);
@@ -239,9 +265,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   for (int64_t i = 0; i < (int64_t)nf * no; ++i)
     if (!std::isfinite(d->filter[i]) || d->filter[i] < 0.0)
       return fail(ctx, VFISV_E_INVALID, "instrument_create: filter taps must be finite and >= 0");
-  if (no != NOBS_HMI)
-    return fail(ctx, VFISV_E_UNSUPPORTED,
-                "instrument_create: this build serves n_obs == 6 (HMI-shaped) instruments");
+  if (no > 4096) return fail(ctx, VFISV_E_INVALID, "instrument_create: n_obs must be <= 4096");
 
   vfisv_instrument* inst = new (std::nothrow) vfisv_instrument();
   if (!inst) return fail(ctx, VFISV_E_NOMEM, "instrument_create: host allocation");
@@ -249,6 +273,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   std::memset(&inst->C, 0, sizeof(Consts));
   double max_drop = 0.0;
   std::vector<double> kept((size_t)no * nf);
+  std::vector<float> row_sum((size_t)no);
   for (int i = 0; i < no; ++i) {
     double rmax = 0.0, rsum = 0.0, drop = 0.0, ksum = 0.0;
     for (int k = 0; k < nf; ++k) {
@@ -263,24 +288,74 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
       ksum += keep ? (double)(float)w : 0.0;
     }
     if (rsum > 0.0) max_drop = std::fmax(max_drop, drop / rsum);
-    inst->C.row_sum[i] = (float)ksum;
+    row_sum[(size_t)i] = (float)ksum;
   }
   std::vector<Point> pts;
-  int n_taps = 0;
-  for (int k = 0; k < nf; ++k) {
-    Point p;
-    std::memset(&p, 0, sizeof p);
-    p.dl = (float)d->fine_offset_mA[k];
-    uint32_t mask = 0;
+  std::vector<Block> blocks;
+  int n_taps = 0, n_active = 0;
+  if (no == NOBS_HMI) {
+    // dense: one record per synthesis point with a non-zero tap
+    for (int i = 0; i < no; ++i) inst->C.row_sum[i] = row_sum[(size_t)i];
+    for (int k = 0; k < nf; ++k) {
+      Point p;
+      std::memset(&p, 0, sizeof p);
+      p.dl = (float)d->fine_offset_mA[k];
+      uint32_t mask = 0;
+      for (int i = 0; i < no; ++i) {
+        p.w[i] = (float)kept[(size_t)i * nf + k];
+        if (p.w[i] != 0.f) {
+          mask |= 1u << i;
+          ++n_taps;
+        }
+      }
+      std::memcpy(&p.w[6], &mask, 4);
+      if (mask) pts.push_back(p);
+    }
+    n_active = (int)pts.size();
+  } else {
+    // banded: row i's kept taps must lie in points a0 + 4 i .. a0 + 4 i + 15
+    int64_t a0 = INT64_MAX;
+    std::vector<int> first((size_t)no, -1), last((size_t)no, -1);
     for (int i = 0; i < no; ++i) {
-      p.w[i] = (float)kept[(size_t)i * nf + k];
-      if (p.w[i] != 0.f) {
-        mask |= 1u << i;
-        ++n_taps;
+      for (int k = 0; k < nf; ++k)
+        if (kept[(size_t)i * nf + k] != 0.0) {
+          if (first[(size_t)i] < 0) first[(size_t)i] = k;
+          last[(size_t)i] = k;
+        }
+      if (first[(size_t)i] >= 0) a0 = std::min<int64_t>(a0, first[(size_t)i] - (int64_t)BAND_S * i);
+    }
+    bool band = a0 != INT64_MAX;
+    for (int i = 0; band && i < no; ++i)
+      if (first[(size_t)i] >= 0 && last[(size_t)i] - (a0 + (int64_t)BAND_S * i) > BAND_S * BAND_R - 1)
+        band = false;
+    if (!band) {
+      delete inst;
+      return fail(ctx, VFISV_E_UNSUPPORTED,
+                  "instrument_create: the filter must have 6 rows, or be banded with each row "
+                  "within 16 consecutive synthesis points advancing 4 points per row");
+    }
+    const int nb = no + BAND_R - 1;
+    blocks.resize((size_t)nb);
+    std::vector<char> used((size_t)nf, 0);
+    for (int b2 = 0; b2 < nb; ++b2) {
+      Block& B = blocks[(size_t)b2];
+      for (int q = 0; q < BAND_S; ++q) {
+        const int64_t k = a0 + (int64_t)BAND_S * b2 + q;
+        const bool in = k >= 0 && k < nf;
+        B.dl[q] = in ? (float)d->fine_offset_mA[k] : 0.f;
+        for (int r = 0; r < BAND_R; ++r) {
+          const int j = b2 - (BAND_R - 1) + r;
+          const double w = (in && j >= 0 && j < no) ? kept[(size_t)j * nf + (size_t)k] : 0.0;
+          B.w[q][r] = (float)w;
+          if (B.w[q][r] != 0.f) {
+            ++n_taps;
+            used[(size_t)k] = 1;
+          }
+        }
       }
     }
-    std::memcpy(&p.w[6], &mask, 4);
-    if (mask) pts.push_back(p);
+    for (int k = 0; k < nf; ++k) n_active += used[(size_t)k];
+    inst->kind = KIND_BAND;
   }
   const double lam0_mA = d->lambda0_A * 1000.0;
   inst->C.lam_over_c = (float)(lam0_mA / C_KMS);
@@ -292,7 +367,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   inst->C.wL = ctx->wL;
   inst->C.wL2 = ctx->wL * ctx->wL;
   inst->C.w2L = 2.f * ctx->wL;
-  inst->info.n_active_fine = (int)pts.size();
+  inst->info.n_active_fine = n_active;
   inst->info.n_taps = n_taps;
   inst->info.max_dropped_rel = max_drop;
   inst->info.cz_mA_per_G = cz;
@@ -302,18 +377,27 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     delete inst;
     return hip_fail(ctx, e, "hipSetDevice");
   }
-  const size_t bytes = sizeof(Point) * (pts.empty() ? 1 : pts.size());
-  e = hipMalloc(&inst->d_pts, bytes);
-  if (e != hipSuccess) {
-    delete inst;
-    return fail(ctx, VFISV_E_NOMEM, "instrument_create: device allocation");
+  if (inst->kind == KIND_DENSE6) {
+    const size_t bytes = sizeof(Point) * (pts.empty() ? 1 : pts.size());
+    e = hipMalloc(&inst->d_pts, bytes);
+    if (e == hipSuccess && !pts.empty())
+      e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(), hipMemcpyHostToDevice);
+  } else {
+    e = hipMalloc(&inst->d_blocks, sizeof(Block) * blocks.size());
+    if (e == hipSuccess) e = hipMalloc(&inst->d_row_sums, sizeof(float) * (size_t)no);
+    if (e == hipSuccess)
+      e = hipMemcpy(inst->d_blocks, blocks.data(), sizeof(Block) * blocks.size(),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(inst->d_row_sums, row_sum.data(), sizeof(float) * (size_t)no,
+                    hipMemcpyHostToDevice);
   }
-  if (!pts.empty())
-    e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(inst->d_pts);
+    if (inst->d_pts) hipFree(inst->d_pts);
+    if (inst->d_blocks) hipFree(inst->d_blocks);
+    if (inst->d_row_sums) hipFree(inst->d_row_sums);
     delete inst;
-    return hip_fail(ctx, e, "instrument_create: copy");
+    return hip_fail(ctx, e, "instrument_create: device tables");
   }
   *out = inst;
   return VFISV_OK;
@@ -329,7 +413,9 @@ int vfisv_instrument_destroy(vfisv_instrument* inst) {
   if (!inst) return VFISV_OK;
   hipSetDevice(inst->ctx->device);
   hipDeviceSynchronize();
-  hipFree(inst->d_pts);
+  if (inst->d_pts) hipFree(inst->d_pts);
+  if (inst->d_blocks) hipFree(inst->d_blocks);
+  if (inst->d_row_sums) hipFree(inst->d_row_sums);
   delete inst;
   return VFISV_OK;
 }
@@ -348,13 +434,15 @@ int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   SynthArgs a;
   a.C = inst->C;
   a.pts = inst->d_pts;
+  a.blocks = inst->d_blocks;
+  a.row_sums = inst->d_row_sums;
   a.params = params;
   a.noise = noise;
   a.stokes = stokes;
   a.jac = jac;
   a.n = n;
   const int grid = grid_for(n, (int64_t)ctx->num_cus * 16);
-  e = launch_synth(a, jac != nullptr, grid, (hipStream_t)stream);
+  e = launch_synth(a, inst->kind, jac != nullptr, grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
   return VFISV_OK;
 }
@@ -378,6 +466,47 @@ int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const 
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   return enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, o, inv_dof,
                     params, chi2, iters, status, (hipStream_t)stream, true);
+}
+
+int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batches,
+                         const vfisv_options* opt, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert_batches: ctx is NULL");
+  if (!batches) return fail(ctx, VFISV_E_INVALID, "invert_batches: batches is NULL");
+  if (n_batches < 1 || n_batches > MAX_BATCHES)
+    return fail(ctx, VFISV_E_INVALID, "invert_batches: n_batches must be in 1..4");
+  BatchArgs B;
+  std::memset(&B, 0, sizeof B);
+  B.n_batches = n_batches;
+  int64_t total = 0;
+  vfisv_options o;
+  for (int i = 0; i < n_batches; ++i) {
+    const vfisv_batch& b = batches[i];
+    int rc = check_inst(ctx, b.inst, "invert_batches");
+    if (rc) return rc;
+    double inv_dof;
+    rc = check_options(ctx, b.inst, opt, &o, &inv_dof);
+    if (rc) return rc;
+    if (b.n < 0 || b.n > INT32_MAX)
+      return fail(ctx, VFISV_E_INVALID, "invert_batches: n must be in 0 .. 2^31 - 1");
+    if (b.n > 0 && (!b.stokes || !b.W || !b.params || !b.chi2 || !b.iters))
+      return fail(ctx, VFISV_E_INVALID, "invert_batches: NULL buffer");
+    fill_lm_args(ctx, b.inst, b.n, nullptr, nullptr, b.stokes, b.W, b.W_per_pixel, b.init, o,
+                 inv_dof, b.params, b.chi2, b.iters, b.status, B.a[i]);
+    B.a[i].qbase = QUEUE_SLOT0 + NQ * i;
+    B.kind[i] = b.inst->kind;
+    total += b.n;
+  }
+  if (total == 0) return VFISV_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o);
+  for (int i = 0; i < n_batches; ++i) B.a[i].ws_stride = (int64_t)grid * 64;
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_reset(ctx->d_work, true, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches: counter reset");
+  e = launch_lm_batches(B, grid, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches launch");
+  return VFISV_OK;
 }
 
 int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {

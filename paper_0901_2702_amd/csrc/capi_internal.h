@@ -13,6 +13,7 @@ struct vfisv_ctx {
   int device = 0;
   int num_cus = 0;
   int lm_blocks_per_cu = 1;
+  int band_blocks_per_cu = 1;
   unsigned long long* d_work = nullptr;  // WORK_SLOTS counters
   double* d_ws = nullptr;                // eigen-fallback workspace
   int64_t ws_lanes = 0;
@@ -26,7 +27,10 @@ struct vfisv_ctx {
 
 struct vfisv_instrument {
   vfisv_ctx* ctx = nullptr;
-  vfisv::Point* d_pts = nullptr;
+  int kind = vfisv::KIND_DENSE6;
+  vfisv::Point* d_pts = nullptr;       // KIND_DENSE6
+  vfisv::Block* d_blocks = nullptr;    // KIND_BAND
+  float* d_row_sums = nullptr;         // KIND_BAND
   vfisv::Consts C;
   vfisv_instrument_info info;
 };

@@ -10,15 +10,23 @@
 namespace vfisv {
 
 // work[] slots: 1 pixels done, 2 trials, 3 accepts, 4 passes, 5 eigen
-// fallbacks, 6 waves; QUEUE_SLOT0 + q: head of pixel queue q (one per XCD)
+// fallbacks, 6 waves; QUEUE_SLOT0 + NQ * batch + q: head of pixel queue q
+// (one per XCD) of a batch
 constexpr int NQ = 8;
 constexpr int QUEUE_SLOT0 = 8;
-constexpr int WORK_SLOTS = QUEUE_SLOT0 + NQ;
+constexpr int MAX_BATCHES = 4;
+constexpr int WORK_SLOTS = QUEUE_SLOT0 + NQ * MAX_BATCHES;
+
+// Instrument layouts: six observed samples with taps anywhere on the grid
+// (HMI-shaped), or a banded filter (Block records).
+enum InstKind : int { KIND_DENSE6 = 0, KIND_BAND = 1 };
 constexpr int HIST_MAX = 4096;  // iteration-histogram bins (kept after the work slots)
 
 struct LMArgs {
   Consts C;
-  const Point* pts;
+  const Point* pts;        // KIND_DENSE6
+  const Block* blocks;     // KIND_BAND: C.n_obs + BAND_R - 1 blocks
+  const float* row_sums;   // KIND_BAND: [n_obs] sums of the kept taps
   const float* stokes;
   const float* W;
   const float* init;
@@ -37,11 +45,22 @@ struct LMArgs {
   int W_pp;
   uint32_t free_mask;
   int chunk_log2;  // pixels per queue block = 2^chunk_log2
+  int qbase;       // first of this batch's NQ queue-head slots in work[]
+};
+
+// Several batches (instrument + pixels + outputs) in one persistent launch:
+// every wave works through the batches in order.
+struct BatchArgs {
+  LMArgs a[MAX_BATCHES];
+  int kind[MAX_BATCHES];
+  int n_batches;
 };
 
 struct SynthArgs {
   Consts C;
   const Point* pts;
+  const Block* blocks;
+  const float* row_sums;
   const float* params;
   const float* noise;
   float* stokes;
@@ -64,9 +83,11 @@ struct SolveArgs {
 hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s);
 hipError_t launch_hist(const int32_t* iters, int64_t n, int n_bins, unsigned long long* out,
                        int max_blocks, hipStream_t s);
-hipError_t launch_lm(const LMArgs& a, int grid, hipStream_t s);
-hipError_t launch_synth(const SynthArgs& a, bool deriv, int grid, hipStream_t s);
+hipError_t launch_lm(const LMArgs& a, int kind, int grid, hipStream_t s);
+hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_synth(const SynthArgs& a, int kind, bool deriv, int grid, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t lm_blocks_per_cu(int* out);
+hipError_t band_blocks_per_cu(int* out);
 
 }  // namespace vfisv

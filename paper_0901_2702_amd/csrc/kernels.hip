@@ -40,19 +40,125 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
-template <int NOBS>
-__global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
-  constexpr int ROWS = 4 * NOBS;
-  __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
-  const int lane = threadIdx.x;
-  const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
+struct WaveCounters {
+  unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0;
+};
 
+// One synthesis pass with derivatives at Mc for the pixel's observations:
+// returns the reduced chi^2 (Eq. 1) in float64 and, when the trial is
+// accepted (fresh start, or finite and below chib), leaves the float32
+// normal equations H (55, packed) and g (10) of Mc in this lane's LDS
+// column.  NOBS = 6: dense HMI-shaped filter, all 174 row accumulators held
+// until chi^2 decides whether H and g are built.  NOBS = 0: banded filter,
+// rows folded into chi^2, H and g as they complete (H and g are built for
+// every trial, since the rows are gone once chi^2 is known).
+template <int NOBS>
+__device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int64_t pix,
+                                          bool fresh, double chib, float* sHG, int lane,
+                                          bool& accept) {
+  Pix px;
+  pix_setup(Mc, A.C, px);
+  RowFactors rf;
+  row_factors(Mc, px, A.C, rf);
+  double chi = 0.0;
+  if constexpr (NOBS > 0) {
+    constexpr int ROWS = 4 * NOBS;
+    const float* obs = A.stokes + pix * ROWS;
+    const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
+    float acc[NOBS][NACC];
+    synth_accumulate<NOBS, true>(A.pts, px, A.C, acc);
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      float S[4], J[4][NPAR];
+      assemble_sample<false>(acc[i], A.C.row_sum[i], rf, S, J);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float r = obs[s * NOBS + i] - S[s];
+        chi = fma((double)Wp[s * NOBS + i] * (double)r, (double)r, chi);
+      }
+    }
+    chi *= A.inv_dof;
+    accept = fresh || (isfinite(chi) && chi < chib);
+    if (accept) {
+      float H[55], g[NPAR];
+#pragma unroll
+      for (int e = 0; e < 55; ++e) H[e] = 0.f;
+#pragma unroll
+      for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
+#pragma unroll
+      for (int i = 0; i < NOBS; ++i) {
+        float S[4], J[4][NPAR];
+        assemble_sample<true>(acc[i], A.C.row_sum[i], rf, S, J);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float w = Wp[s * NOBS + i];
+          const float r = obs[s * NOBS + i] - S[s];
+#pragma unroll
+          for (int p = 0; p < NPAR; ++p) {
+            const float wj = w * J[s][p];
+            g[p] = fmaf(wj, r, g[p]);
+#pragma unroll
+            for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+#pragma unroll
+      for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
+    }
+  } else {
+    const int no = A.C.n_obs;
+    const float* obs = A.stokes + pix * (int64_t)(4 * no);
+    const float* Wp = A.W_pp ? A.W + pix * (int64_t)(4 * no) : A.W;
+    float H[55], g[NPAR];
+#pragma unroll
+    for (int e = 0; e < 55; ++e) H[e] = 0.f;
+#pragma unroll
+    for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
+    band_accumulate<true>(A.blocks, no, px, A.C, [&](int j, const float* a) {
+      float S[4], J[4][NPAR];
+      assemble_sample<true>(a, A.row_sums[j], rf, S, J);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float w = Wp[s * no + j];
+        const float r = obs[s * no + j] - S[s];
+        chi = fma((double)w * (double)r, (double)r, chi);
+#pragma unroll
+        for (int p = 0; p < NPAR; ++p) {
+          const float wj = w * J[s][p];
+          g[p] = fmaf(wj, r, g[p]);
+#pragma unroll
+          for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+        }
+      }
+    });
+    chi *= A.inv_dof;
+    accept = fresh || (isfinite(chi) && chi < chib);
+    if (accept) {
+#pragma unroll
+      for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+#pragma unroll
+      for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
+    }
+  }
+  return chi;
+}
+
+// The persistent LM loop of one wave over one batch: lanes take pixels
+// from the batch's queues, fit them, and return when the queues are empty
+// and every lane has finished.
+template <int NOBS>
+__device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, int64_t glane,
+                                        WaveCounters& wc) {
   const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
+  const int rows = NOBS > 0 ? 4 * NOBS : 4 * A.C.n_obs;
   // Pixel queues: queue q owns the blocks b of 2^chunk_log2 consecutive
   // positions with b % NQ == q; its k-th position is
-  // ((k / chunk) * NQ + q) * chunk + k % chunk.  A wave takes positions from the queue of its XCD first
-  // (workgroups are dispatched to the XCDs round-robin), so the lines of the
-  // pixels one XCD works on stay in that XCD's L2, then from the others.
+  // ((k / chunk) * NQ + q) * chunk + k % chunk.  A wave takes positions
+  // from the queue of its XCD first (workgroups are dispatched to the XCDs
+  // round-robin), so the lines of the pixels one XCD works on stay in that
+  // XCD's L2, then from the others.
   const int home = blockIdx.x % NQ;
   const int sh = A.chunk_log2;
   const unsigned long long ch = 1ull << sh;
@@ -63,7 +169,6 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   float Mb[NPAR], Mc[NPAR];
   double chib = 0.0, eps = 0.0;
   int it = 0;
-  unsigned long long n_pix = 0, n_trial = 0, n_acc = 0, n_pass = 0, n_fb = 0;
 
   for (;;) {
     // ---- refill lanes whose pixel finished --------------------------------
@@ -75,7 +180,7 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       const unsigned long long cnt = full * ch + (r0 < ch ? r0 : ch);
       const unsigned long long m = (unsigned long long)__popcll(nm);
       unsigned long long k0 = 0;
-      if (lane == 0) k0 = atomicAdd(&A.work[QUEUE_SLOT0 + q], m);
+      if (lane == 0) k0 = atomicAdd(&A.work[A.qbase + q], m);
       k0 = bcast_lane0(k0);
       const unsigned long long got = k0 < cnt ? (cnt - k0 < m ? cnt - k0 : m) : 0ull;
       if (got < m) dry |= 1u << q;
@@ -88,18 +193,22 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
         const unsigned long long pos =
             ((((k >> sh) << 3) + (unsigned long long)q) << sh) + (k & (ch - 1ull));
         pix = A.idx ? (int64_t)A.idx[pos] : (int64_t)pos;
-        const float* obs = A.stokes + pix * ROWS;
-        const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
+        const float* obs = A.stokes + pix * rows;
+        const float* Wp = A.W_pp ? A.W + pix * rows : A.W;
         bool finite = true;
+        if constexpr (NOBS > 0) {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
+          for (int r = 0; r < 4 * NOBS; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
+        } else {
+          for (int r = 0; r < rows; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
+        }
         if (!finite) {
 #pragma unroll
           for (int q2 = 0; q2 < NPAR; ++q2) A.params[pix * NPAR + q2] = __builtin_nanf("");
           A.chi2[pix] = __builtin_nan("");
           A.iters[pix] = 0;
           if (A.status) A.status[pix] = 3;
-          ++n_pix;
+          ++wc.pix;
         } else {
           double M0[NPAR];
           if (A.init) {
@@ -129,57 +238,9 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
     if (!live) continue;
 
     // ---- synthesis pass with derivatives at Mc ----------------------------
-    ++n_pass;
-    Pix px;
-    pix_setup(Mc, A.C, px);
-    float acc[NOBS][NACC];
-    synth_accumulate<NOBS, true>(A.pts, px, A.C, acc);
-    RowFactors rf;
-    row_factors(Mc, px, A.C, rf);
-    const float* obs = A.stokes + pix * ROWS;
-    const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
-
-    double chi = 0.0;
-#pragma unroll
-    for (int i = 0; i < NOBS; ++i) {
-      float S[4], J[4][NPAR];
-      assemble_sample<false>(acc[i], A.C.row_sum[i], rf, S, J);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float r = obs[s * NOBS + i] - S[s];
-        chi = fma((double)Wp[s * NOBS + i] * (double)r, (double)r, chi);
-      }
-    }
-    chi *= A.inv_dof;
-    const bool accept = fresh || (isfinite(chi) && chi < chib);
-    if (accept) {
-      float H[55], g[NPAR];
-#pragma unroll
-      for (int e = 0; e < 55; ++e) H[e] = 0.f;
-#pragma unroll
-      for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
-#pragma unroll
-      for (int i = 0; i < NOBS; ++i) {
-        float S[4], J[4][NPAR];
-        assemble_sample<true>(acc[i], A.C.row_sum[i], rf, S, J);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const float w = Wp[s * NOBS + i];
-          const float r = obs[s * NOBS + i] - S[s];
-#pragma unroll
-          for (int p = 0; p < NPAR; ++p) {
-            const float wj = w * J[s][p];
-            g[p] = fmaf(wj, r, g[p]);
-#pragma unroll
-            for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
-          }
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
-#pragma unroll
-      for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
-    }
+    ++wc.pass;
+    bool accept = false;
+    const double chi = lm_pass<NOBS>(A, Mc, pix, fresh, chib, sHG, lane, accept);
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
@@ -190,14 +251,14 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       chib = chi;
     } else {
       ++it;
-      ++n_trial;
+      ++wc.trial;
       if (accept) {
         const double dec = chib - chi;
 #pragma unroll
         for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
         chib = chi;
         eps = eps_down(eps);
-        ++n_acc;
+        ++wc.acc;
         if (dec < A.rel_tol * (chi + dec)) done = 0;
       } else {
         eps = eps_up(eps);
@@ -213,7 +274,7 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       A.chi2[pix] = chib;
       A.iters[pix] = it;
       if (A.status) A.status[pix] = done;
-      ++n_pix;
+      ++wc.pix;
       live = false;
     } else {
       // ---- damped float64 step from the best model ------------------------
@@ -225,7 +286,7 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       double delta[NPAR], sc[NPAR], b[NPAR];
       const int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
       if (code == 1) {
-        ++n_fb;
+        ++wc.fb;
         double* ws = A.ws + glane;
         solve_eigen_fallback(&sHG[lane], 64, &sHG[55 * 64 + lane], 64, eps, A.free_mask, ws,
                              A.ws_stride);
@@ -240,21 +301,48 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
       for (int q = 0; q < NPAR; ++q) Mc[q] = (float)Mt[q];
     }
   }
+}
 
-  // ---- work counters: one atomic per wave and counter ----------------------
-  n_pix = wave_sum(n_pix);
-  n_trial = wave_sum(n_trial);
-  n_acc = wave_sum(n_acc);
-  n_pass = wave_sum(n_pass);
-  n_fb = wave_sum(n_fb);
+// ---- work counters: one atomic per wave and counter ----------------------
+__device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCounters wc,
+                                               int lane) {
+  const unsigned long long p = wave_sum(wc.pix), t = wave_sum(wc.trial), a = wave_sum(wc.acc),
+                           s = wave_sum(wc.pass), f = wave_sum(wc.fb);
   if (lane == 0) {
-    atomicAdd(&A.work[1], n_pix);
-    atomicAdd(&A.work[2], n_trial);
-    atomicAdd(&A.work[3], n_acc);
-    atomicAdd(&A.work[4], n_pass);
-    atomicAdd(&A.work[5], n_fb);
-    atomicAdd(&A.work[6], 1ull);
+    atomicAdd(&work[1], p);
+    atomicAdd(&work[2], t);
+    atomicAdd(&work[3], a);
+    atomicAdd(&work[4], s);
+    atomicAdd(&work[5], f);
+    atomicAdd(&work[6], 1ull);
   }
+}
+
+template <int NOBS>
+__global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
+  __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
+  const int lane = threadIdx.x;
+  WaveCounters wc;
+  lm_loop<NOBS>(A, sHG, lane, (int64_t)blockIdx.x * 64 + lane, wc);
+  flush_counters(A.work, wc, lane);
+}
+
+// Several batches in one launch: each wave finishes its share of batch i
+// (until that batch's queues are empty) before it turns to batch i + 1, so
+// waves are uniform in instrument and the last batch fills the tail left by
+// the earlier ones.
+__global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
+  __shared__ float sHG[65 * 64];
+  const int lane = threadIdx.x;
+  const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
+  WaveCounters wc;
+  for (int i = 0; i < B.n_batches; ++i) {
+    if (B.kind[i] == KIND_DENSE6)
+      lm_loop<NOBS_HMI>(B.a[i], sHG, lane, glane, wc);
+    else
+      lm_loop<0>(B.a[i], sHG, lane, glane, wc);
+  }
+  flush_counters(B.a[0].work, wc, lane);
 }
 
 template <int NOBS, bool DERIV>
@@ -285,6 +373,35 @@ __global__ __launch_bounds__(64) void synth_kernel(const SynthArgs A) {
         }
       }
     }
+  }
+}
+
+// Synthesis through a banded instrument: rows are written as they complete.
+template <bool DERIV>
+__global__ __launch_bounds__(64) void synth_band_kernel(const SynthArgs A) {
+  const int no = A.C.n_obs;
+  for (int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x; i < A.n;
+       i += (int64_t)gridDim.x * 64) {
+    float M[NPAR];
+#pragma unroll
+    for (int q = 0; q < NPAR; ++q) M[q] = A.params[i * NPAR + q];
+    Pix px;
+    pix_setup(M, A.C, px);
+    RowFactors rf;
+    row_factors(M, px, A.C, rf);
+    band_accumulate<DERIV>(A.blocks, no, px, A.C, [&](int j, const float* a) {
+      float S[4], J[4][NPAR];
+      assemble_sample<DERIV>(a, A.row_sums[j], rf, S, J);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t r = i * (int64_t)(4 * no) + s * no + j;
+        A.stokes[r] = A.noise ? S[s] + A.noise[r] : S[s];
+        if (DERIV) {
+#pragma unroll
+          for (int p = 0; p < NPAR; ++p) A.jac[r * NPAR + p] = J[s][p];
+        }
+      }
+    });
   }
 }
 
@@ -351,14 +468,25 @@ hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_lm(const LMArgs& a, int grid, hipStream_t s) {
-  lm_kernel<NOBS_HMI><<<grid, 64, 0, s>>>(a);
+hipError_t launch_lm(const LMArgs& a, int kind, int grid, hipStream_t s) {
+  if (kind == KIND_DENSE6) lm_kernel<NOBS_HMI><<<grid, 64, 0, s>>>(a);
+  else lm_kernel<0><<<grid, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_synth(const SynthArgs& a, bool deriv, int grid, hipStream_t s) {
-  if (deriv) synth_kernel<NOBS_HMI, true><<<grid, 64, 0, s>>>(a);
-  else synth_kernel<NOBS_HMI, false><<<grid, 64, 0, s>>>(a);
+hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s) {
+  lm_batches_kernel<<<grid, 64, 0, s>>>(b);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth(const SynthArgs& a, int kind, bool deriv, int grid, hipStream_t s) {
+  if (kind == KIND_DENSE6) {
+    if (deriv) synth_kernel<NOBS_HMI, true><<<grid, 64, 0, s>>>(a);
+    else synth_kernel<NOBS_HMI, false><<<grid, 64, 0, s>>>(a);
+  } else {
+    if (deriv) synth_band_kernel<true><<<grid, 64, 0, s>>>(a);
+    else synth_band_kernel<false><<<grid, 64, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -369,6 +497,10 @@ hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s) {
 
 hipError_t lm_blocks_per_cu(int* out) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_kernel<NOBS_HMI>, 64, 0);
+}
+
+hipError_t band_blocks_per_cu(int* out) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_batches_kernel, 64, 0);
 }
 
 }  // namespace vfisv

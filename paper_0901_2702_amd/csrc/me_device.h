@@ -286,6 +286,55 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   }
 }
 
+// Banded instruments (many observed samples, each seeing a short window of
+// the synthesis grid that advances BAND_S points per sample, at most
+// BAND_S * BAND_R points long).  The grid is cut into blocks of BAND_S
+// consecutive points; block b feeds the rows b - BAND_R + 1 .. b, and row j
+// is complete once block j + BAND_R - 1 has been added.  w[q][r] is the tap
+// of point q of the block in row b - BAND_R + 1 + r (zero outside the band).
+constexpr int BAND_S = 4;
+constexpr int BAND_R = 4;
+struct __attribute__((aligned(16))) Block {
+  float dl[BAND_S];
+  float w[BAND_S][BAND_R];
+};
+
+// Sliding-window accumulation over a banded instrument: only the BAND_R rows
+// a block touches are held in registers; each completed row is handed to
+// row(j, acc_j) in increasing j, then its registers are reused.
+template <bool DERIV, class RowFn>
+__device__ __forceinline__ void band_accumulate(const Block* __restrict__ blk, int n_obs,
+                                                const Pix& p, const Consts& C, RowFn&& row) {
+  constexpr int NC = DERIV ? NACC : 5;
+  float acc[BAND_R][NACC];
+#pragma unroll
+  for (int r = 0; r < BAND_R; ++r)
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) acc[r][m] = 0.f;
+  const int nb = n_obs + BAND_R - 1;
+  for (int b = 0; b < nb; ++b) {
+    const Block* B = blk + b;  // wave-uniform: scalar loads
+#pragma unroll 1
+    for (int q = 0; q < BAND_S; ++q) {
+      float c[NACC];
+      point_contrib<DERIV>(B->dl[q], p, C, c);
+#pragma unroll
+      for (int r = 0; r < BAND_R; ++r) {
+        const float w = B->w[q][r];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) acc[r][m] = fmaf(w, c[m], acc[r][m]);
+      }
+    }
+    if (b >= BAND_R - 1) row(b - (BAND_R - 1), acc[0]);
+#pragma unroll
+    for (int r = 0; r < BAND_R - 1; ++r)
+#pragma unroll
+      for (int m = 0; m < NC; ++m) acc[r][m] = acc[r + 1][m];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) acc[BAND_R - 1][m] = 0.f;
+  }
+}
+
 // Per-pixel factors that turn accumulated sums into Stokes values and
 // Jacobian rows (API units).
 struct RowFactors {
