@@ -97,9 +97,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
-    ap.add_argument("--workload", choices=("learned", "full-disk"), default="learned",
+    ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed"),
+                    default="learned",
                     help="learned: the learned-start vs plain LM line (default); full-disk: "
-                         "plain LM over the 13.2M-pixel disk with clustered active regions")
+                         "plain LM over the 13.2M-pixel disk with clustered active regions; "
+                         "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -138,6 +140,8 @@ def main():
         return plain_only(args, ctx, inst, spec, log)
     if args.workload == "full-disk":
         return full_disk(args, ctx, inst, spec, log)
+    if args.workload == "fine-mixed":
+        return fine_mixed(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -424,6 +428,121 @@ def full_disk(args, ctx, inst, spec, log):
                       "noise, observations synthesised by the FP64 oracle), plain LM from "
                       "the default model, max 50 iterations" % m,
             "seconds": round(dt, 3)}
+    print(json.dumps(result), flush=True)
+
+
+def fine_mixed(args, ctx, inst, spec, log):
+    """1M fine-spectrum pixels (112 samples, banded 15-tap filter, 464-point
+    grid) and 1M HMI-shaped pixels inverted by plain LM in one launch, against
+    the same work as two launches."""
+    import numpy as np
+    import torch
+
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    dev = ctx.device
+    stream = torch.cuda.current_stream(dev)
+    n_f = n_h = args.n
+    fspec = wl.fine_instrument()
+    finst = vf.Instrument.from_spec(ctx, fspec)
+
+    def make(sp, ins, n, seed):
+        P = wl.draw_params(n, seed)
+        noise = wl.draw_noise(n, sp.n_obs, seed).astype(np.float32)
+        obs = vf.synthesize(ctx, ins, torch.tensor(P.astype(np.float32), device=dev),
+                            noise=torch.tensor(noise, device=dev))
+        return P, noise, obs, torch.tensor(wl.weights(sp.n_obs), device=dev)
+
+    t0 = time.perf_counter()
+    Pf, nf_, of, Wf = make(fspec, finst, n_f, wl.CONFIGS["cfg4_fine"]["seed"])
+    Ph, nh_, oh, Wh = make(spec, inst, n_h, wl.CONFIGS["cfg4_hmi"]["seed"])
+    torch.cuda.synchronize()
+    log("fine + HMI inputs in %.1f s" % (time.perf_counter() - t0))
+    out_f, out_h = vf._alloc_out(n_f, dev), vf._alloc_out(n_h, dev)
+    batches = [dict(inst=finst, stokes=of, W=Wf, out=out_f),
+               dict(inst=inst, stokes=oh, W=Wh, out=out_h)]
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return ((time.perf_counter() - t) * 1e3 / steps,
+                float(np.mean([a.elapsed_time(b) for a, b in ev])))
+
+    ms_mix, _ = timed(lambda: vf.invert_batches(ctx, batches), args.steps)
+    c_mix = ctx.counters()
+    ms_f, ev_f = timed(lambda: vf.invert(ctx, finst, of, Wf, out=out_f), max(2, args.steps // 2))
+    c_f = ctx.counters()
+    it_f = out_f["iters"].cpu().numpy()
+    ch_f = out_f["chi2"].cpu().numpy()
+    ms_h, _ = timed(lambda: vf.invert(ctx, inst, oh, Wh, out=out_h), max(2, args.steps // 2))
+    it_h = out_h["iters"].cpu().numpy()
+    log("mixed %.2f ms, fine alone %.2f ms, HMI alone %.2f ms" % (ms_mix, ms_f, ms_h))
+
+    fi = finst.info
+    f_trial, f_jac, f_solve = work_model(fi["n_active_fine"], fi["n_taps"], fspec.n_obs)
+    alg = c_f["trials"] * (f_trial + f_solve) + (c_f["pixels"] + c_f["accepts"]) * f_jac
+    achieved = alg / (ev_f * 1e-3) / 1e12
+    n = n_f + n_h
+    result = {
+        "metric": "inverted pixels/s on 1 MI355X, fine-spectrum + HMI pixels in one launch, "
+                  "plain LM",
+        "value": round(n / (ms_mix * 1e-3), 1), "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_mix, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "%d fine-spectrum pixels (Fe I 6302.4936 A, 112 samples at "
+                               "21.5 mA, 15-tap Gaussian of 25 mA FWHM on a 464-point grid, "
+                               "seed %d) + %d HMI-shaped pixels (seed %d), cfg0 priors, noise "
+                               "1e-3; plain LM from the default model, <= 50 trials; one "
+                               "launch, fine batch first"
+                               % (n_f, wl.CONFIGS["cfg4_fine"]["seed"], n_h,
+                                  wl.CONFIGS["cfg4_hmi"]["seed"]),
+                   "pixels": n},
+        "separate_launches_ms": {"fine": round(ms_f, 3), "hmi": round(ms_h, 3),
+                                 "sum": round(ms_f + ms_h, 3)},
+        "fine": {"mean_iters": float(it_f.mean()), "median_chi2": float(np.median(ch_f)),
+                 "frac_chi2_below_1.5": float(np.mean(ch_f < 1.5))},
+        "hmi": {"mean_iters": float(it_h.mean())},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None, "kernel": "lm_kernel<0> (banded, fine pixels alone)",
+                     "kernel_ms": round(ev_f, 3), "flop_per_trial": f_trial,
+                     "flop_per_jacobian_pass": f_jac,
+                     "work_fine": {k: c_f[k] for k in ("trials", "accepts", "passes", "pixels")},
+                     "work_mixed": {k: c_mix[k] for k in ("trials", "accepts", "passes",
+                                                          "pixels")}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        mf, mh = 2048, 4096
+        ofi = oracle.Instrument(fspec.lambda0_A, fspec.geff, fspec.fine_offset_mA, fspec.filter)
+        ohi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+        obs_f = (oracle.forward_batch(ofi, Pf[:mf]) + nf_[:mf].astype(np.float64)).astype(np.float32)
+        obs_h = (oracle.forward_batch(ohi, Ph[:mh]) + nh_[:mh].astype(np.float64)).astype(np.float32)
+        t1 = time.perf_counter()
+        rf = oracle.invert(ofi, obs_f, wl.weights(fspec.n_obs))
+        dtf = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.invert(ohi, obs_h, wl.weights(spec.n_obs))
+        dth = time.perf_counter() - t1
+        # the same 1:1 mix of fine and HMI pixels as the GPU run
+        per_pair = dtf / mf + dth / mh
+        result["cpu_baseline"] = {
+            "value": round(2.0 / per_pair, 2), "unit": "pixels/s", "cores": rf["threads"],
+            "kind": "oracle",
+            "sample": "first %d fine and first %d HMI pixels (same parameters and noise, "
+                      "observations synthesised by the FP64 oracle), plain LM; rate for the "
+                      "1:1 mix" % (mf, mh),
+            "seconds": round(dtf + dth, 3)}
     print(json.dumps(result), flush=True)
 
 

@@ -116,23 +116,34 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
     for (int e = 0; e < 55; ++e) H[e] = 0.f;
 #pragma unroll
     for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
-    band_accumulate<true>(A.blocks, no, px, A.C, [&](int j, const float* a) {
-      float S[4], J[4][NPAR];
-      assemble_sample<true>(a, A.row_sums[j], rf, S, J);
+    float ob[4], wb[4], rs = 0.f;
+    band_accumulate<true>(
+        A.blocks, no, px, A.C,
+        [&](int j) {
+          rs = A.row_sums[j];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float w = Wp[s * no + j];
-        const float r = obs[s * no + j] - S[s];
-        chi = fma((double)w * (double)r, (double)r, chi);
+          for (int s = 0; s < 4; ++s) {
+            ob[s] = obs[s * no + j];
+            wb[s] = Wp[s * no + j];
+          }
+        },
+        [&](int, const float* a) {
+          float S[4], J[4][NPAR];
+          assemble_sample<true>(a, rs, rf, S, J);
 #pragma unroll
-        for (int p = 0; p < NPAR; ++p) {
-          const float wj = w * J[s][p];
-          g[p] = fmaf(wj, r, g[p]);
+          for (int s = 0; s < 4; ++s) {
+            const float w = wb[s];
+            const float r = ob[s] - S[s];
+            chi = fma((double)w * (double)r, (double)r, chi);
 #pragma unroll
-          for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
-        }
-      }
-    });
+            for (int p = 0; p < NPAR; ++p) {
+              const float wj = w * J[s][p];
+              g[p] = fmaf(wj, r, g[p]);
+#pragma unroll
+              for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+            }
+          }
+        });
     chi *= A.inv_dof;
     accept = fresh || (isfinite(chi) && chi < chib);
     if (accept) {
@@ -389,7 +400,7 @@ __global__ __launch_bounds__(64) void synth_band_kernel(const SynthArgs A) {
     pix_setup(M, A.C, px);
     RowFactors rf;
     row_factors(M, px, A.C, rf);
-    band_accumulate<DERIV>(A.blocks, no, px, A.C, [&](int j, const float* a) {
+    band_accumulate<DERIV>(A.blocks, no, px, A.C, [](int) {}, [&](int j, const float* a) {
       float S[4], J[4][NPAR];
       assemble_sample<DERIV>(a, A.row_sums[j], rf, S, J);
 #pragma unroll

@@ -301,10 +301,14 @@ struct __attribute__((aligned(16))) Block {
 
 // Sliding-window accumulation over a banded instrument: only the BAND_R rows
 // a block touches are held in registers; each completed row is handed to
-// row(j, acc_j) in increasing j, then its registers are reused.
-template <bool DERIV, class RowFn>
+// row(j, acc_j) in increasing j, then its registers are reused.  pre(j) is
+// called when the block that completes row j starts, so that the caller can
+// issue that row's loads early (one wave per SIMD leaves little else to
+// hide their latency).
+template <bool DERIV, class PreFn, class RowFn>
 __device__ __forceinline__ void band_accumulate(const Block* __restrict__ blk, int n_obs,
-                                                const Pix& p, const Consts& C, RowFn&& row) {
+                                                const Pix& p, const Consts& C, PreFn&& pre,
+                                                RowFn&& row) {
   constexpr int NC = DERIV ? NACC : 5;
   float acc[BAND_R][NACC];
 #pragma unroll
@@ -313,19 +317,21 @@ __device__ __forceinline__ void band_accumulate(const Block* __restrict__ blk, i
     for (int m = 0; m < NACC; ++m) acc[r][m] = 0.f;
   const int nb = n_obs + BAND_R - 1;
   for (int b = 0; b < nb; ++b) {
-    const Block* B = blk + b;  // wave-uniform: scalar loads
-#pragma unroll 1
+    const Block B = blk[b];  // wave-uniform: one scalar load of the record
+    const int j = b - (BAND_R - 1);
+    if (j >= 0) pre(j);
+#pragma unroll
     for (int q = 0; q < BAND_S; ++q) {
       float c[NACC];
-      point_contrib<DERIV>(B->dl[q], p, C, c);
+      point_contrib<DERIV>(B.dl[q], p, C, c);
 #pragma unroll
       for (int r = 0; r < BAND_R; ++r) {
-        const float w = B->w[q][r];
+        const float w = B.w[q][r];
 #pragma unroll
         for (int m = 0; m < NC; ++m) acc[r][m] = fmaf(w, c[m], acc[r][m]);
       }
     }
-    if (b >= BAND_R - 1) row(b - (BAND_R - 1), acc[0]);
+    if (j >= 0) row(j, acc[0]);
 #pragma unroll
     for (int r = 0; r < BAND_R - 1; ++r)
 #pragma unroll

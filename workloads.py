@@ -43,6 +43,7 @@ CONFIGS = {
     "cfg3_control": dict(n=250_000, seed=1103),
     "cfg3_heldout": dict(n=1_000_000, seed=2003),
     "cfg4_fine": dict(n=1_000_000, seed=1004),
+    "cfg4_hmi": dict(n=1_000_000, seed=1104),
 }
 
 
