@@ -66,6 +66,22 @@ struct __attribute__((aligned(32))) Point {
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Instrument tables are written once, before any launch, and only read by
+// the kernels: reading them through the constant address space lets the
+// compiler use scalar loads (one per wave, through the scalar cache) for
+// these wave-uniform records instead of per-lane vector loads.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p, int i) {
+  static_assert(sizeof(T) % 4 == 0, "records are made of 32-bit words");
+  typedef const __attribute__((address_space(4))) float* ConstWords;
+  const ConstWords src = (ConstWords)(p + i);
+  T out;
+  float* dst = reinterpret_cast<float*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
 // Per-pixel quantities of one synthesis pass.
 struct Pix {
   float vsi, invD, zs, a, twoa, denr, denr2, c0;
@@ -271,7 +287,7 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
 #pragma unroll
     for (int m = 0; m < NACC; ++m) acc[i][m] = 0.f;
   for (int k = 0; k < C.n_pts; ++k) {
-    const Point P = pts[k];  // wave-uniform: scalar loads
+    const Point P = load_uniform(pts, k);  // wave-uniform: scalar loads
     float c[NACC];
     point_contrib<DERIV>(P.dl, p, C, c);
     const uint32_t mask = __float_as_uint(P.w[6]);
@@ -317,7 +333,7 @@ __device__ __forceinline__ void band_accumulate(const Block* __restrict__ blk, i
     for (int m = 0; m < NACC; ++m) acc[r][m] = 0.f;
   const int nb = n_obs + BAND_R - 1;
   for (int b = 0; b < nb; ++b) {
-    const Block B = blk[b];  // wave-uniform: one scalar load of the record
+    const Block B = load_uniform(blk, b);  // wave-uniform: one scalar load of the record
     const int j = b - (BAND_R - 1);
     if (j >= 0) pre(j);
 #pragma unroll
