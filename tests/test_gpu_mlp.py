@@ -59,8 +59,8 @@ def _random_net(ctx, n_in, seed):
     return net, flat, in_mean, in_std
 
 
-def test_forward_matches_oracle(ctx):
-    n_in = 24
+@pytest.mark.parametrize("n_in", [24, 448])
+def test_forward_matches_oracle(ctx, n_in):
     net, flat, mean, std = _random_net(ctx, n_in, 1)
     x = (np.random.default_rng(2).normal(size=(1000, n_in)) * std + mean).astype(np.float32)
     codes, params = net.forward(torch.tensor(x, device=ctx.device))
@@ -79,8 +79,8 @@ def test_forward_matches_oracle(ctx):
     np.testing.assert_allclose(p[:, [0, 1, 3]], dec[:, [0, 1, 3]], rtol=1e-4, atol=1e-3)
 
 
-def test_gradient_matches_oracle(ctx):
-    n_in = 24
+@pytest.mark.parametrize("n_in", [24, 448])
+def test_gradient_matches_oracle(ctx, n_in):
     net, flat, mean, std = _random_net(ctx, n_in, 3)
     rng = np.random.default_rng(4)
     x = (rng.normal(size=(512, n_in)) * std + mean).astype(np.float32)
@@ -98,7 +98,8 @@ def test_gradient_matches_oracle(ctx):
         assert rel < 3e-2, k
     # the padding of the first and last layers receives no gradient
     gf = g.cpu().numpy()
-    assert np.all(gf[n_in * H:32 * H] == 0.0)
+    K0 = (n_in + 31) // 32 * 32
+    assert np.all(gf[n_in * H:K0 * H] == 0.0)
 
 
 def test_save_load_round_trip(ctx):
@@ -159,3 +160,33 @@ def test_learned_start_needs_fewer_iterations(ctx, small_trained):
     assert li.mean() < 0.8 * pi.mean()
     assert np.median(lc) <= np.median(pc) * 1.01
     assert np.mean(lc > 1.01 * pc) < 0.2
+
+
+def test_fine_learned_start_with_448_inputs(ctx):
+    """The network's first layer takes the 448 samples of a fine spectrum;
+    trained on fine pixels it shortens the LM on held-out fine pixels."""
+    spec = wl.fine_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    S, P = learned.make_training_set(ctx, inst, 196608, 21, wl.draw_params, wl.draw_noise,
+                                     chunk=65536)
+    Sc, Pc = learned.make_training_set(ctx, inst, 16384, 22, wl.draw_params, wl.draw_noise)
+    assert S.shape == (196608, 448)
+    net, info = learned.train(ctx, inst, S, P, Sc, Pc, epochs=6, batch=2048, lr=2e-3,
+                              log=lambda m: print("[gpu-fine] " + m, flush=True))
+    assert info["best_control_mse"] < 0.3
+    n = 2048
+    Ph = wl.draw_params(n, 23)
+    noise = wl.draw_noise(n, spec.n_obs, 23)
+    obs = vf.synthesize(ctx, inst, torch.tensor(Ph.astype(np.float32), device=ctx.device),
+                        noise=torch.tensor(noise.astype(np.float32), device=ctx.device))
+    W = torch.tensor(wl.weights(spec.n_obs), device=ctx.device)
+    plain = vf.invert(ctx, inst, obs, W)
+    lrn = learned.invert_learned(ctx, inst, net, obs.view(n, 448), W)
+    pc, lc = plain["chi2"].cpu().numpy(), lrn["chi2"].cpu().numpy()
+    pi, li = plain["iters"].cpu().numpy(), lrn["iters"].cpu().numpy()
+    fb = (lrn["status"].cpu().numpy() & vf.FALLBACK_USED) != 0
+    print("[gpu-fine] plain: median chi2 %.4f, mean iters %.2f; learned: median chi2 %.4f, "
+          "mean iters %.2f, fallback %.3f" % (np.median(pc), pi.mean(), np.median(lc),
+                                              li.mean(), fb.mean()), flush=True)
+    assert li.mean() < 0.8 * pi.mean()
+    assert np.median(lc) <= np.median(pc) * 1.01
