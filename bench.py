@@ -177,6 +177,10 @@ def main():
 
     out_l, out_p = alloc(), alloc()
     opts = vf.Options()
+    # scheduling (persistent grid, pixel-queue block) chosen by the library's
+    # autotuner on a sample of this batch; results do not depend on it
+    tuning = vf.autotune(ctx, inst, obs, W, opts=opts, sample=131072)
+    log("autotune: %s" % tuning)
 
     def learned_step():
         learned.invert_learned(ctx, inst, net, obs2, W, opts=opts,
@@ -252,6 +256,7 @@ def main():
             "mean_iters": float(pi.mean()), "status_counts": np.bincount(ps, minlength=4).tolist(),
         },
         "speedup_vs_plain": round(ms_p / ms_l, 3),
+        "autotune": tuning,
         "matched_chi2": {
             "median_learned": q(lc, 0.5), "median_plain": q(pc, 0.5),
             "p90_learned": q(lc, 0.9), "p90_plain": q(pc, 0.9),
@@ -353,6 +358,8 @@ def full_disk(args, ctx, inst, spec, log):
                iters=torch.empty(n, device=dev, dtype=torch.int32),
                status=torch.empty(n, device=dev, dtype=torch.int32))
     opts = vf.Options()
+    tuning = vf.autotune(ctx, inst, obs, W, opts=opts, sample=262144)
+    log("autotune: %s" % tuning)
     ms, ev_ms = timed(obs, out, opts, args.steps)
     c = ctx.counters()
     iters = out["iters"].cpu().numpy()
@@ -405,6 +412,7 @@ def full_disk(args, ctx, inst, spec, log):
                         "active_fraction": round(float(active_iid.mean()), 5),
                         "mean_iters": float(iters_iid.mean())},
         "chunk_log2_sweep_ms": sweep,
+        "autotune": tuning,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": None, "kernel": "lm_kernel (one launch per step)",
@@ -459,6 +467,9 @@ def fine_mixed(args, ctx, inst, spec, log):
     torch.cuda.synchronize()
     log("fine + HMI inputs in %.1f s" % (time.perf_counter() - t0))
     out_f, out_h = vf._alloc_out(n_f, dev), vf._alloc_out(n_h, dev)
+    tuning = {"fine": vf.autotune(ctx, finst, of, Wf, sample=65536),
+              "hmi": vf.autotune(ctx, inst, oh, Wh, sample=131072)}
+    log("autotune: %s" % tuning)
     batches = [dict(inst=finst, stokes=of, W=Wf, out=out_f),
                dict(inst=inst, stokes=oh, W=Wh, out=out_h)]
 
@@ -507,6 +518,7 @@ def fine_mixed(args, ctx, inst, spec, log):
                                % (n_f, wl.CONFIGS["cfg4_fine"]["seed"], n_h,
                                   wl.CONFIGS["cfg4_hmi"]["seed"]),
                    "pixels": n},
+        "autotune": tuning,
         "separate_launches_ms": {"fine": round(ms_f, 3), "hmi": round(ms_h, 3),
                                  "sum": round(ms_f + ms_h, 3)},
         "fine": {"mean_iters": float(it_f.mean()), "median_chi2": float(np.median(ch_f)),

@@ -97,11 +97,24 @@ typedef struct {
   double eps_max;      /* stall threshold (1e8)                             */
   double rel_tol;      /* relative chi^2 decrease ending the fit (1e-5)     */
   uint32_t free_mask;  /* bit p set: parameter p free (0x3FF)               */
-  int grid_waves;      /* persistent grid size in waves; 0 = auto           */
+  int grid_waves;      /* persistent grid size in waves; 0 = auto: the      */
+                       /* vfisv_autotune choice for the instrument's layout */
+                       /* if there is one, else CUs x occupancy             */
   int chunk_log2;      /* pixel queue block = 2^chunk_log2 consecutive      */
-                       /* pixels, 0..20 (default 8); scheduling only: the   */
-                       /* per-pixel results do not depend on it             */
+                       /* pixels, 0..20, or -1 = auto (default: the tuned   */
+                       /* value, else 8).  Scheduling only: the per-pixel   */
+                       /* results do not depend on grid_waves or chunk_log2 */
 } vfisv_options;
+
+/* Result of vfisv_autotune. */
+typedef struct {
+  int grid_waves;     /* chosen persistent grid (waves)                 */
+  int chunk_log2;     /* chosen pixel-queue block                        */
+  double best_ms;     /* sample inversion time with the choice           */
+  double default_ms;  /* with the untuned default (-1 if not a candidate) */
+  int candidates;     /* configurations timed                            */
+  int64_t sample;     /* pixels in the timed sample                      */
+} vfisv_tuning;
 
 /* Work counters of the most recent vfisv_invert on a context. */
 typedef struct {
@@ -211,6 +224,22 @@ typedef struct {
 } vfisv_batch;
 int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batches,
                          const vfisv_options *opt, void *stream);
+
+/* Scheduling autotuner: inverts the first `sample` pixels (<= 0: 131072,
+ * at most n) of the caller's data, from the default model with opt's fit
+ * settings, with every candidate persistent grid
+ * (1, 2, 3, 4, 6 or 8 waves per CU, within the fallback workspace) and
+ * pixel-queue block (2^4, 2^8, 2^12 pixels), twice each, timed with HIP
+ * events on `stream`, and keeps the fastest for this instrument's layout in
+ * the context; later inversions with grid_waves == 0 and chunk_log2 == -1
+ * use it.  Results go to library scratch (the caller's outputs are not
+ * touched) and are identical for every candidate, so only speed changes.
+ * Allocates and synchronises: call it at set-up, not under graph capture.
+ * out may be NULL.  Overwrites the work counters. */
+int vfisv_autotune(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                   const float *stokes, const float *W, int W_per_pixel,
+                   const vfisv_options *opt, int64_t sample, vfisv_tuning *out,
+                   void *stream);
 
 /* Work counters of the most recent vfisv_invert or vfisv_invert_batches
  * (synchronises the context's device). */

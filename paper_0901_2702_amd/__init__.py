@@ -54,6 +54,12 @@ class _Batch(ctypes.Structure):
                 ("status", ctypes.c_void_p)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("grid_waves", ctypes.c_int), ("chunk_log2", ctypes.c_int),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("sample", ctypes.c_int64)]
+
+
 class _Counters(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("trials", ctypes.c_int64),
                 ("accepts", ctypes.c_int64), ("passes", ctypes.c_int64),
@@ -68,7 +74,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
-           "vfisv_invert_batches")
+           "vfisv_invert_batches", "vfisv_autotune")
 
 _LIB = None
 
@@ -101,6 +107,9 @@ def lib():
                                            ctypes.POINTER(ctypes.c_int64), _vp]
         L.vfisv_invert_batches.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.c_int,
                                            ctypes.POINTER(_Options), _vp]
+        L.vfisv_autotune.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
+                                     ctypes.POINTER(_Options), ctypes.c_int64,
+                                     ctypes.POINTER(_Tuning), _vp]
         _LIB = L
     return _LIB
 
@@ -211,7 +220,7 @@ class Options:
     rel_tol: float = 1e-5
     free_mask: int = 0x3FF
     grid_waves: int = 0
-    chunk_log2: int = 8
+    chunk_log2: int = -1
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
@@ -293,6 +302,20 @@ def invert_batches(ctx, batches, opts=None):
     ctx._check(lib().vfisv_invert_batches(ctx._h, arr, len(batches), ctypes.byref(o),
                                           _stream(dev)), "vfisv_invert_batches")
     return outs
+
+
+def autotune(ctx, inst, stokes, W, opts=None, sample=0):
+    """Pick the persistent grid and pixel-queue block for this instrument's
+    layout by timing them on the first ``sample`` pixels; later inversions
+    with automatic scheduling options use the choice.  Returns a dict."""
+    dev = ctx.device
+    o = (opts or Options()).c()
+    t = _Tuning()
+    ctx._check(lib().vfisv_autotune(
+        ctx._h, inst._h, stokes.shape[0], _ptr(stokes, torch.float32, dev, name="stokes"),
+        _ptr(W, torch.float32, dev, name="W"), 1 if W.dim() == 3 else 0, ctypes.byref(o),
+        int(sample), ctypes.byref(t), _stream(dev)), "vfisv_autotune")
+    return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
 
 def iter_histogram(ctx, iters, n_bins=51):

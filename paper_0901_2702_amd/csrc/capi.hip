@@ -55,8 +55,8 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
       !std::isfinite(o.rel_tol))
     return fail(ctx, VFISV_E_INVALID, "options: eps0, eps_max must be > 0 and rel_tol >= 0");
   if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "options: grid_waves < 0");
-  if (o.chunk_log2 < 0 || o.chunk_log2 > 20)
-    return fail(ctx, VFISV_E_INVALID, "options: chunk_log2 outside 0..20");
+  if (o.chunk_log2 < -1 || o.chunk_log2 > 20)
+    return fail(ctx, VFISV_E_INVALID, "options: chunk_log2 outside -1..20");
   o.free_mask &= 0x3FFu;
   int nfree = 0;
   for (int p = 0; p < NPAR; ++p) nfree += (o.free_mask >> p) & 1u;
@@ -98,12 +98,14 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.max_iter = o.max_iter;
   a.W_pp = W_pp ? 1 : 0;
   a.free_mask = o.free_mask & 0x3FFu;
-  a.chunk_log2 = o.chunk_log2;
+  const vfisv_ctx::Tuned& t = ctx->tuned[inst->kind];
+  a.chunk_log2 = o.chunk_log2 >= 0 ? o.chunk_log2 : (t.valid ? t.chunk_log2 : 8);
 }
 
-static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o) {
+static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, int kind) {
   int64_t cap = (int64_t)ctx->num_cus * bpc;
   if (o.grid_waves > 0) cap = o.grid_waves;
+  else if (kind >= 0 && ctx->tuned[kind].valid) cap = ctx->tuned[kind].grid_waves;
   if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
   return grid_for(n, cap);
 }
@@ -118,7 +120,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                status, a);
   const int grid = lm_grid(ctx, n,
                            inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
-                                                     : ctx->band_blocks_per_cu, o);
+                                                     : ctx->band_blocks_per_cu, o, inst->kind);
   a.ws_stride = (int64_t)grid * 64;
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
@@ -241,7 +243,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->rel_tol = 1e-5;
   o->free_mask = 0x3FFu;
   o->grid_waves = 0;
-  o->chunk_log2 = 8;
+  o->chunk_log2 = -1;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -499,13 +501,96 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
   if (total == 0) return VFISV_OK;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-  const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o);
+  const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o, -1);
   for (int i = 0; i < n_batches; ++i) B.a[i].ws_stride = (int64_t)grid * 64;
   hipStream_t s = (hipStream_t)stream;
   e = launch_reset(ctx->d_work, true, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches: counter reset");
   e = launch_lm_batches(B, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches launch");
+  return VFISV_OK;
+}
+
+int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                   const float* stokes, const float* W, int W_per_pixel, const vfisv_options* opt,
+                   int64_t sample, vfisv_tuning* out, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "autotune: ctx is NULL");
+  int rc = check_inst(ctx, inst, "autotune");
+  if (rc) return rc;
+  vfisv_options o;
+  double inv_dof;
+  rc = check_options(ctx, inst, opt, &o, &inv_dof);
+  if (rc) return rc;
+  if (n < 1 || n > INT32_MAX) return fail(ctx, VFISV_E_INVALID, "autotune: n must be in 1..2^31-1");
+  if (!stokes || !W) return fail(ctx, VFISV_E_INVALID, "autotune: NULL buffer");
+  if (sample <= 0) sample = 131072;
+  const int64_t m = sample < n ? sample : n;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  float* params = nullptr;
+  double* chi2 = nullptr;
+  int32_t* iters = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  e = hipMalloc(&params, sizeof(float) * NPAR * (size_t)m);
+  if (e == hipSuccess) e = hipMalloc(&chi2, sizeof(double) * (size_t)m);
+  if (e == hipSuccess) e = hipMalloc(&iters, sizeof(int32_t) * (size_t)m);
+  if (e == hipSuccess) e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  // candidates: persistent grid (waves per CU) x queue block size
+  const int bpc_default = inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
+                                                    : ctx->band_blocks_per_cu;
+  const int waves_per_cu[] = {1, 2, 3, 4, 6, 8};
+  const int chunks[] = {4, 8, 12};
+  vfisv_tuning best;
+  std::memset(&best, 0, sizeof best);
+  best.best_ms = 1e300;
+  best.default_ms = -1.0;
+  int cand = 0;
+  for (int wi = 0; e == hipSuccess && wi < 6; ++wi) {
+    const int64_t gw = (int64_t)ctx->num_cus * waves_per_cu[wi];
+    if (gw > ctx->ws_lanes / 64) continue;
+    for (int ci = 0; e == hipSuccess && ci < 3; ++ci) {
+      vfisv_options oc = o;
+      oc.grid_waves = (int)gw;
+      oc.chunk_log2 = chunks[ci];
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(ev0, s);
+        if (e != hipSuccess) break;
+        rc = enqueue_lm(ctx, inst, m, nullptr, nullptr, stokes, W, W_per_pixel, nullptr, oc,
+                        inv_dof, params, chi2, iters, nullptr, s, true);
+        if (rc) break;
+        e = hipEventRecord(ev1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev0, ev1);
+        if (e == hipSuccess && t < ms) ms = t;
+      }
+      if (rc) break;
+      ++cand;
+      if (waves_per_cu[wi] == bpc_default && chunks[ci] == 8) best.default_ms = ms;
+      if (e == hipSuccess && ms < best.best_ms) {
+        best.best_ms = ms;
+        best.grid_waves = (int)gw;
+        best.chunk_log2 = chunks[ci];
+      }
+    }
+  }
+  if (ev0) hipEventDestroy(ev0);
+  if (ev1) hipEventDestroy(ev1);
+  if (params) hipFree(params);
+  if (chi2) hipFree(chi2);
+  if (iters) hipFree(iters);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+  best.candidates = cand;
+  best.sample = m;
+  vfisv_ctx::Tuned& t = ctx->tuned[inst->kind];
+  t.valid = true;
+  t.grid_waves = best.grid_waves;
+  t.chunk_log2 = best.chunk_log2;
+  if (out) *out = best;
   return VFISV_OK;
 }
 

@@ -19,6 +19,12 @@ struct vfisv_ctx {
   int64_t ws_lanes = 0;
   float wc[vfisv::NW + 1];
   float wL = 0.f;
+  // scheduling picked by vfisv_autotune, per instrument layout (KIND_*)
+  struct Tuned {
+    bool valid = false;
+    int grid_waves = 0;
+    int chunk_log2 = 8;
+  } tuned[2];
   // learned-start scratch (grown on demand)
   void* d_learn = nullptr;
   size_t learn_bytes = 0;

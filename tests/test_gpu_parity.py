@@ -304,3 +304,21 @@ def test_iter_histogram_is_exact(ctx, hmi):
     h = vf.iter_histogram(ctx, out["iters"], 51)
     assert np.array_equal(h, np.bincount(it, minlength=51)) and h.sum() == 2000
     assert (h * np.arange(51)).sum() == ctx.counters()["trials"]
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(ctx, hmi):
+    spec, inst, oi = hmi
+    P, obs = _observations(oi, spec, 20000, 91)
+    o = _dev(ctx, obs)
+    W = _dev(ctx, wl.weights(spec.n_obs))
+    ref = {k: v.cpu().numpy() for k, v in vf.invert(ctx, inst, o, W).items()}
+    t = vf.autotune(ctx, inst, o, W, sample=8192)
+    cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    print("[gpu] autotune %s" % t, flush=True)
+    assert t["sample"] == 8192 and t["candidates"] >= 12
+    assert t["grid_waves"] % cus == 0 and t["chunk_log2"] in (4, 8, 12)
+    assert 0 < t["best_ms"] <= t["default_ms"]
+    out = vf.invert(ctx, inst, o, W)
+    assert ctx.counters()["grid_waves"] == min(t["grid_waves"], (20000 + 63) // 64)
+    for k in ref:
+        assert np.array_equal(out[k].cpu().numpy(), ref[k]), k
