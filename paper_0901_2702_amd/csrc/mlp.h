@@ -76,6 +76,11 @@ hipError_t mlp_forward(const MlpDev& net, MlpWork& w, int64_t M, const float* st
                        const int32_t* rows, bool train, hipStream_t s);
 hipError_t mlp_decode(const MlpDev& net, const float* Y4, int64_t M, float* codes,
                       float* params, hipStream_t s);
+// Fused inference (inputs -> decoded codes/params in one kernel); LDS bytes
+// it needs for an input width K0.
+hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* codes,
+                     float* params, hipStream_t s);
+size_t mlp_infer_lds_bytes(int K0);
 hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* targets,
                         const int32_t* rows, hipStream_t s);
 hipError_t mlp_adam(const MlpDev& net, const MlpWork& w, float lr, float beta1, float beta2,

@@ -184,20 +184,25 @@ __global__ void loss_grad_kernel(const float* __restrict__ Y4, const float* __re
   if (threadIdx.x == 0) atomicAdd(loss, (double)red[0]);
 }
 
-// db[n] = sum over the batch of dZ^T[n][:]
-__global__ void bias_grad_kernel(const bf16* __restrict__ dZt, int64_t M, int64_t cap,
-                                 float* grad_b) {
-  __shared__ float red[64];
+// db[n] = sum over the batch of dZ^T[n][:].  One block of 256 threads per
+// column; the batch dimension is contiguous, so each thread reads 8 values
+// per load (M and cap are multiples of 32: 16-byte aligned rows), then a
+// wave reduction and one LDS step combine the 256 partial sums.
+__global__ __launch_bounds__(256) void bias_grad_kernel(const bf16* __restrict__ dZt, int64_t M,
+                                                        int64_t cap, float* grad_b) {
+  __shared__ float red[4];
   const int n = blockIdx.x;
+  const bf16* row = dZt + (int64_t)n * cap;
   float s = 0.f;
-  for (int64_t m = threadIdx.x; m < M; m += 64) s += (float)dZt[(int64_t)n * cap + m];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 32; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  for (int64_t m = (int64_t)threadIdx.x * 8; m < M; m += 256 * 8) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + m);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (float)v[k];
   }
-  if (threadIdx.x == 0) grad_b[n] = red[0];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) grad_b[n] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 struct AdamArgs {
@@ -268,17 +273,15 @@ __global__ void refresh_kernel(const RefreshArgs a, int l) {
 
 // Network outputs -> model parameters (the field vector is encoded as
 // (B cos g, B sin g cos 2psi, B sin g sin 2psi) / 3000), then the box.
-__global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
-                              const float* __restrict__ out_mean,
-                              const float* __restrict__ out_std, float* codes, float* params) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
+__device__ __forceinline__ void decode_row(const float* y_in, const float* __restrict__ out_mean,
+                                           const float* __restrict__ out_std, float* codes,
+                                           float* params) {
   float y[MLP_NCODE];
 #pragma unroll
-  for (int c = 0; c < MLP_NCODE; ++c) y[c] = Y4[m * MLP_OUT + c];
+  for (int c = 0; c < MLP_NCODE; ++c) y[c] = y_in[c];
   if (codes) {
 #pragma unroll
-    for (int c = 0; c < MLP_NCODE; ++c) codes[m * MLP_NCODE + c] = y[c];
+    for (int c = 0; c < MLP_NCODE; ++c) codes[c] = y[c];
   }
   if (!params) return;
   double P[NPAR];
@@ -290,29 +293,205 @@ __global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
   for (int c = 3; c < MLP_NCODE; ++c) P[c] = (double)y[c] * out_std[c - 3] + out_mean[c - 3];
   project(P);
 #pragma unroll
-  for (int c = 0; c < NPAR; ++c) params[m * NPAR + c] = (float)P[c];
+  for (int c = 0; c < NPAR; ++c) params[c] = (float)P[c];
 }
 
+__global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
+                              const float* __restrict__ out_mean,
+                              const float* __restrict__ out_std, float* codes, float* params) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  decode_row(Y4 + m * MLP_OUT, out_mean, out_std, codes ? codes + m * MLP_NCODE : nullptr,
+             params ? params + m * NPAR : nullptr);
+}
+
+// ---- fused inference ---------------------------------------------------------
+// One workgroup of four waves carries FT rows through the whole network:
+// standardised inputs and hidden activations stay in one LDS tile
+// (bfloat16, rows padded by 8 elements so that the 16 rows an MFMA operand
+// reads fall in different banks; each layer finishes reading the tile before
+// any wave overwrites it with the layer's outputs), weights are read as MFMA
+// operands from L2, and the outputs are decoded in place.  Wave w owns hidden columns [64 w, 64 w + 64)
+// and output rows [16 w, 16 w + 16).  The MFMA sequence per output element
+// (same instruction, same k order, same epilogue) is that of gemm_abt, so
+// the results equal those of the layer-by-layer path.
+constexpr int FT = 64;
+constexpr int LDH = MLP_H + 8;
+
+struct MlpInferArgs {
+  const float* stokes;
+  int64_t M;
+  int n_in, K0;
+  const float* mean;
+  const float* istd;
+  const bf16* Wt[4];
+  const float* bias[4];
+  const float* out_mean;
+  const float* out_std;
+  float* codes;
+  float* params;
+};
+
+template <int KS>
+__device__ __forceinline__ void fused_hidden(bf16* buf, int ldin, int Kd, const bf16* W,
+                                             const float* __restrict__ bias, int wave, int l) {
+  const bf16* in = buf;
+  const int K = KS > 0 ? KS : Kd;
+  const int lr = l & 15, lk = (l >> 4) * 8;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll(KS > 0 ? KS / 32 : 2)
+  for (int k = 0; k < K; k += 32) {
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      b[cb] = *(const bf16x8*)(W + (int64_t)(wave * 64 + cb * 16 + lr) * K + k + lk);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x8*)(in + (rb * 16 + lr) * ldin + k + lk);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read the layer's inputs
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + (l >> 4) * 4 + j;
+        const int col = wave * 64 + cb * 16 + lr;
+        buf[row * LDH + col] = (bf16)gelu(acc[rb][cb][j] + bias[col]);
+      }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const MlpInferArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int ldx = a.K0 + 8;
+  bf16* buf = (bf16*)smem;  // [FT][max(K0 + 8, LDH)]
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int64_t row0 = (int64_t)blockIdx.x * FT;
+  for (int idx = tid; idx < FT * a.K0; idx += 256) {
+    const int r = idx / a.K0, k = idx - r * a.K0;
+    const int64_t row = row0 + r;
+    float x = 0.f;
+    if (k < a.n_in && row < a.M) x = (a.stokes[row * a.n_in + k] - a.mean[k]) * a.istd[k];
+    buf[r * ldx + k] = (bf16)x;
+  }
+  __syncthreads();
+  fused_hidden<0>(buf, ldx, a.K0, a.Wt[0], a.bias[0], wave, l);
+  fused_hidden<MLP_H>(buf, LDH, MLP_H, a.Wt[1], a.bias[1], wave, l);
+  fused_hidden<MLP_H>(buf, LDH, MLP_H, a.Wt[2], a.bias[2], wave, l);
+  float* y4 = (float*)smem;  // [FT][MLP_OUT + 1], over the tile once it is read
+  {  // output layer: rows [16 wave, 16 wave + 16), 32 columns
+    const int lr = l & 15, lk = (l >> 4) * 8;
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int k = 0; k < MLP_H; k += 32) {
+      const bf16x8 av = *(const bf16x8*)(buf + (wave * 16 + lr) * LDH + k + lk);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const bf16x8 bv = *(const bf16x8*)(a.Wt[3] + (int64_t)(cb * 16 + lr) * MLP_H + k + lk);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[cb], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the tile is read; its space takes the outputs
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wave * 16 + (l >> 4) * 4 + j;
+        const int col = cb * 16 + lr;
+        y4[row * (MLP_OUT + 1) + col] = acc[cb][j] + a.bias[3][col];
+      }
+  }
+  __syncthreads();
+  if (tid < FT) {
+    const int64_t row = row0 + tid;
+    if (row < a.M)
+      decode_row(&y4[tid * (MLP_OUT + 1)], a.out_mean, a.out_std,
+                 a.codes ? a.codes + row * MLP_NCODE : nullptr,
+                 a.params ? a.params + row * NPAR : nullptr);
+  }
+}
+
+size_t mlp_infer_lds_bytes(int K0) {
+  const int ldx = K0 + 8, ld = ldx > LDH ? ldx : LDH;
+  const size_t tile = sizeof(bf16) * (size_t)FT * ld;
+  const size_t outs = sizeof(float) * FT * (MLP_OUT + 1);
+  return tile > outs ? tile : outs;
+}
+
+hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* codes,
+                     float* params, hipStream_t s) {
+  const MlpLayout& L = net.L;
+  MlpInferArgs a;
+  a.stokes = stokes;
+  a.M = M;
+  a.n_in = L.n_in;
+  a.K0 = L.K0;
+  a.mean = net.in_mean;
+  a.istd = net.in_istd;
+  for (int l = 0; l < 4; ++l) {
+    a.Wt[l] = net.Wt[l];
+    a.bias[l] = net.master + L.ob[l];
+  }
+  a.out_mean = net.out_mean;
+  a.out_std = net.out_std;
+  a.codes = codes;
+  a.params = params;
+  const size_t lds = mlp_infer_lds_bytes(L.K0);
+  mlp_infer_kernel<<<(unsigned)((M + FT - 1) / FT), 256, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+// Pixels whose fit is not acceptable go to the list.  Each block takes a
+// contiguous chunk of SELECT_PER_THREAD * 256 pixels, ranks its selections
+// with a block-wide scan in LDS and reserves its slots with one atomic, so
+// the counter sees one update per 4096 pixels (same-address atomics
+// serialise in L2).
+constexpr int SELECT_PER_THREAD = 16;
 __global__ __launch_bounds__(256) void fallback_select_kernel(const double* __restrict__ chi2,
                                                               int64_t n, double tau,
                                                               int32_t* list,
                                                               unsigned long long* count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool sel = false;
-  if (i < n) {
-    const double c = chi2[i];
-    sel = !(c <= tau) && !isnan(c);  // not acceptable (non-finite input stays as is)
+  __shared__ unsigned int scan[256];
+  __shared__ unsigned long long base;
+  const int t = threadIdx.x;
+  const int64_t start = (int64_t)blockIdx.x * 256 * SELECT_PER_THREAD;
+  unsigned int mask = 0u, c = 0u;
+#pragma unroll
+  for (int k = 0; k < SELECT_PER_THREAD; ++k) {
+    const int64_t i = start + (int64_t)k * 256 + t;
+    if (i < n) {
+      const double v = chi2[i];
+      if (!(v <= tau) && !isnan(v)) {  // not acceptable (non-finite input stays as is)
+        mask |= 1u << k;
+        ++c;
+      }
+    }
   }
-  // one counter update per wave: lanes take consecutive slots by rank
-  const unsigned long long m = __ballot(sel);
-  if (m == 0ull) return;
-  const int lane = threadIdx.x & 63;
-  unsigned long long base = 0;
-  if (lane == __ffsll((long long)m) - 1) base = atomicAdd(count, (unsigned long long)__popcll(m));
-  const unsigned lo = __shfl((unsigned)(base & 0xffffffffull), __ffsll((long long)m) - 1);
-  const unsigned hi = __shfl((unsigned)(base >> 32), __ffsll((long long)m) - 1);
-  base = ((unsigned long long)hi << 32) | lo;
-  if (sel) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  scan[t] = c;
+  __syncthreads();
+  // inclusive Hillis-Steele scan over the 256 counts
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned int v = t >= off ? scan[t - off] : 0u;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  if (t == 255) base = scan[255] ? atomicAdd(count, (unsigned long long)scan[255]) : 0ull;
+  __syncthreads();
+  unsigned long long pos = base + scan[t] - c;
+#pragma unroll
+  for (int k = 0; k < SELECT_PER_THREAD; ++k)
+    if (mask & (1u << k)) list[pos++] = (int32_t)(start + (int64_t)k * 256 + t);
 }
 
 __global__ void fallback_merge_kernel(const int32_t* __restrict__ list,
@@ -395,7 +574,7 @@ hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* t
     EpiDW ed{w.dW + off, stride, in};
     e = gemm<4>(w.dZt[l], w.cap, Xt, w.cap, out, in, M, MLP_SPLITK, ed, s);
     if (e != hipSuccess) return e;
-    bias_grad_kernel<<<out, 64, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
+    bias_grad_kernel<<<out, 256, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (l > 0) {  // input gradient through W and the previous GELU
@@ -460,7 +639,8 @@ hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t s) {
 
 hipError_t fallback_select(const double* chi2, int64_t n, double tau, int32_t* list,
                            unsigned long long* count, hipStream_t s) {
-  fallback_select_kernel<<<blocks_for(n, 256), 256, 0, s>>>(chi2, n, tau, list, count);
+  fallback_select_kernel<<<blocks_for(n, 256 * SELECT_PER_THREAD), 256, 0, s>>>(chi2, n, tau,
+                                                                               list, count);
   return hipGetLastError();
 }
 

@@ -22,14 +22,12 @@ struct vfisv_mlp {
   vfisv_ctx* ctx = nullptr;
   MlpDev dev;
   MlpWork train;
-  MlpWork infer;
   int step = 0;
   std::vector<float> in_mean, in_std, out_mean, out_std;  // host copies
 };
 
 namespace {
 
-constexpr int64_t INFER_CHUNK = 262144;
 constexpr uint32_t FILE_VERSION = 1;
 const char FILE_MAGIC[8] = {'V', 'F', 'I', 'S', 'V', 'M', 'L', 'P'};
 
@@ -115,7 +113,6 @@ int build(vfisv_ctx* ctx, int n_in, const float* in_mean, const float* in_std,
   m->ctx = ctx;
   std::memset(&m->dev, 0, sizeof m->dev);
   std::memset(&m->train, 0, sizeof m->train);
-  std::memset(&m->infer, 0, sizeof m->infer);
   MlpDev& d = m->dev;
   d.L = mlp_layout(n_in);
   const MlpLayout& L = d.L;
@@ -186,14 +183,6 @@ int ensure_train(vfisv_mlp* m, int64_t rows) {
   return VFISV_OK;
 }
 
-int ensure_infer(vfisv_mlp* m, int64_t rows) {
-  if (m->infer.cap >= rows) return VFISV_OK;
-  hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = alloc_work(m->infer, m->dev.L, rows, false);
-  if (e != hipSuccess) return fail(m->ctx, VFISV_E_NOMEM, "mlp: inference buffers");
-  return VFISV_OK;
-}
-
 int check_mlp(vfisv_ctx* ctx, const vfisv_mlp* m, const char* fn) {
   if (!m) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": mlp is NULL");
   if (m->ctx != ctx) return fail(ctx, VFISV_E_INVALID, std::string(fn) + ": mlp of another context");
@@ -234,7 +223,6 @@ int vfisv_mlp_destroy(vfisv_mlp* m) {
   hipSetDevice(m->ctx->device);
   hipDeviceSynchronize();
   free_work(m->train);
-  free_work(m->infer);
   free_dev(m->dev);
   delete m;
   return VFISV_OK;
@@ -279,18 +267,9 @@ int vfisv_mlp_forward(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stok
   if (!stokes || (!codes && !params)) return fail(ctx, VFISV_E_INVALID, "mlp_forward: NULL buffer");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-  rc = ensure_infer(m, n < INFER_CHUNK ? n : INFER_CHUNK);
-  if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  const int n_in = m->dev.L.n_in;
-  for (int64_t off = 0; off < n; off += m->infer.cap) {
-    const int64_t rows = n - off < m->infer.cap ? n - off : m->infer.cap;
-    e = mlp_forward(m->dev, m->infer, rows, stokes + off * n_in, nullptr, false, s);
-    if (e == hipSuccess)
-      e = mlp_decode(m->dev, m->infer.Y4, rows, codes ? codes + off * MLP_NCODE : nullptr,
-                     params ? params + off * NPAR : nullptr, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_forward");
-  }
+  // one fused launch: inputs -> decoded codes / starting models, no scratch
+  e = mlp_infer(m->dev, n, stokes, codes, params, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_forward");
   return VFISV_OK;
 }
 
