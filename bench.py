@@ -97,11 +97,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
-    ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed"),
+    ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity"),
                     default="learned",
                     help="learned: the learned-start vs plain LM line (default); full-disk: "
                          "plain LM over the 13.2M-pixel disk with clustered active regions; "
-                         "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch")
+                         "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch; "
+                         "parity: per-parameter differences from the FP64 oracle on the "
+                         "262,144-pixel HMI set")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -142,6 +144,8 @@ def main():
         return full_disk(args, ctx, inst, spec, log)
     if args.workload == "fine-mixed":
         return fine_mixed(args, ctx, inst, spec, log)
+    if args.workload == "parity":
+        return parity(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -555,6 +559,76 @@ def fine_mixed(args, ctx, inst, spec, log):
                       "observations synthesised by the FP64 oracle), plain LM; rate for the "
                       "1:1 mix" % (mf, mh),
             "seconds": round(dtf + dth, 3)}
+    print(json.dumps(result), flush=True)
+
+
+def parity(args, ctx, inst, spec, log):
+    """Per-parameter differences between the GPU inversion and the FP64
+    oracle on the 512 x 512 HMI set (seed 1001): the GPU inverts all 262,144
+    pixels; the oracle inverts a sample of them from the same float32
+    observations (synthesised by the oracle) and the same start."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    dev = ctx.device
+    n = wl.CONFIGS["cfg1"]["n"]
+    seed = wl.CONFIGS["cfg1"]["seed"]
+    m = min(args.cpu_sample, n)
+    n_obs = spec.n_obs
+    P = wl.draw_params(n, seed)
+    oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+    t0 = time.perf_counter()
+    obs = (oracle.forward_batch(oi, P) + wl.draw_noise(n, n_obs, seed)).astype(np.float32)
+    log("oracle synthesis of %d pixels: %.1f s" % (n, time.perf_counter() - t0))
+    W = wl.weights(n_obs)
+    o_d, W_d = torch.tensor(obs, device=dev), torch.tensor(W, device=dev)
+    names = ["B", "gamma", "psi", "v", "dlD", "a", "eta0", "S0", "S1", "alpha"]
+    tol = {"B": 1.0, "gamma": 0.1, "psi": 0.1, "v": 1e-3}
+    result = {"metric": "per-parameter |GPU - FP64 oracle| on the 512x512 HMI set",
+              "config": {"workload": "262,144 HMI-shaped pixels (cfg0 priors, seed %d, noise "
+                                     "1e-3); GPU on all, oracle on the first %d" % (seed, m),
+                         "tolerances": "B 1 G, gamma and psi 0.1 deg, v 1 m/s, chi2 1e-4 "
+                                       "relative"}}
+    for start in ("default", "truth"):
+        init = None if start == "default" else P.astype(np.float32)
+        t = time.perf_counter()
+        out = vf.invert(ctx, inst, o_d, W_d,
+                        init=None if init is None else torch.tensor(init, device=dev))
+        torch.cuda.synchronize()
+        gpu_s = time.perf_counter() - t
+        gp, gc = out["params"].cpu().numpy()[:m], out["chi2"].cpu().numpy()[:m]
+        gs = out["status"].cpu().numpy()[:m]
+        t = time.perf_counter()
+        ref = oracle.invert(oi, obs[:m], W,
+                            init=None if init is None else init[:m].astype(np.float64))
+        cpu_s = time.perf_counter() - t
+        both = (gs == 0) & (ref["status"] == 0)
+        dchi = np.abs(gc - ref["chi2"]) / ref["chi2"]
+        same = both & (dchi < 1e-4)
+        d = np.abs(gp.astype(np.float64) - ref["params"])
+        d[:, 2] = np.minimum(d[:, 2], 180.0 - d[:, 2])
+        # angles are undetermined without a field: report them where B > 50 G
+        field = ref["params"][:, 0] > 50.0
+        per = {}
+        for k, name in enumerate(names):
+            sel = same & field if name in ("gamma", "psi") else same
+            v = d[sel, k]
+            per[name] = {"median": float(np.median(v)), "p90": float(np.quantile(v, 0.9)),
+                         "p99": float(np.quantile(v, 0.99)), "max": float(v.max())}
+            if name in tol:
+                per[name]["frac_within_tol"] = float(np.mean(v < tol[name]))
+        result[start + "_start"] = {
+            "gpu_seconds_all_pixels": round(gpu_s, 3), "oracle_seconds_sample": round(cpu_s, 3),
+            "frac_converged_both": float(both.mean()),
+            "frac_same_minimum": float(same.mean()),
+            "chi2_rel_diff_converged_both": {"median": float(np.median(dchi[both])),
+                                             "p90": float(np.quantile(dchi[both], 0.9)),
+                                             "frac_below_1e-4": float(np.mean(dchi[both] < 1e-4))},
+            "abs_diff_on_same_minimum": per}
+        log("%s start: converged both %.3f, same minimum %.3f" % (start, both.mean(), same.mean()))
     print(json.dumps(result), flush=True)
 
 
