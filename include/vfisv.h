@@ -104,6 +104,14 @@ typedef struct {
                        /* pixels, 0..20, or -1 = auto (default: the tuned   */
                        /* value, else 8).  Scheduling only: the per-pixel   */
                        /* results do not depend on grid_waves or chunk_log2 */
+  int lanes_per_pixel; /* 1 (default) or 2: with 2, HMI-shaped pixels use a  */
+                       /* pair of lanes each (half the synthesis points per */
+                       /* lane, ~1.8x faster passes) whenever the grid can   */
+                       /* give every pixel two lanes (at most 65,536 pixels */
+                       /* on MI355X); results then differ from the one-lane */
+                       /* path by float32 rounding of the synthesis sums.    */
+                       /* The learned path's refit uses pairs when they fit; */
+                       /* vfisv_invert_batches keeps one lane per pixel.     */
 } vfisv_options;
 
 /* Result of vfisv_autotune. */

@@ -43,7 +43,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
                 ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int),
-                ("chunk_log2", ctypes.c_int)]
+                ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int)]
 
 
 class _Batch(ctypes.Structure):
@@ -221,10 +221,11 @@ class Options:
     free_mask: int = 0x3FF
     grid_waves: int = 0
     chunk_log2: int = -1
+    lanes_per_pixel: int = 1
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
-                        self.grid_waves, self.chunk_log2)
+                        self.grid_waves, self.chunk_log2, self.lanes_per_pixel)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None):

@@ -57,6 +57,8 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   if (o.grid_waves < 0) return fail(ctx, VFISV_E_INVALID, "options: grid_waves < 0");
   if (o.chunk_log2 < -1 || o.chunk_log2 > 20)
     return fail(ctx, VFISV_E_INVALID, "options: chunk_log2 outside -1..20");
+  if (o.lanes_per_pixel != 1 && o.lanes_per_pixel != 2)
+    return fail(ctx, VFISV_E_INVALID, "options: lanes_per_pixel must be 1 or 2");
   o.free_mask &= 0x3FFu;
   int nfree = 0;
   for (int p = 0; p < NPAR; ++p) nfree += (o.free_mask >> p) & 1u;
@@ -78,6 +80,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.blocks = inst->d_blocks;
   a.row_sums = inst->d_row_sums;
   a.qbase = QUEUE_SLOT0;
+  a.lpp_max = 1;
   a.stokes = stokes;
   a.W = W;
   a.init = init;
@@ -114,11 +117,16 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
                const float* W, int W_pp, const float* init, const vfisv_options& o,
                double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
-               hipStream_t s, bool reset_all) {
+               hipStream_t s, bool reset_all, int lpp_max) {
   LMArgs a;
   fill_lm_args(ctx, inst, n, n_dev, idx, stokes, W, W_pp, init, o, inv_dof, params, chi2, iters,
                status, a);
-  const int grid = lm_grid(ctx, n,
+  if (o.lanes_per_pixel > lpp_max) lpp_max = o.lanes_per_pixel;
+  if (inst->kind != KIND_DENSE6) lpp_max = 1;
+  a.lpp_max = lpp_max;
+  // with lane pairs the grid is sized for two lanes per pixel (the kernel
+  // falls back to one lane per pixel when they do not fit)
+  const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n,
                            inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
                                                      : ctx->band_blocks_per_cu, o, inst->kind);
   a.ws_stride = (int64_t)grid * 64;
@@ -244,6 +252,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->free_mask = 0x3FFu;
   o->grid_waves = 0;
   o->chunk_log2 = -1;
+  o->lanes_per_pixel = 1;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,

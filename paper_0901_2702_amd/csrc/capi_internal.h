@@ -52,11 +52,14 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
 
 // Enqueue the persistent LM kernel.  With idx != NULL the pixels are
 // idx[0 .. count), count read from n_dev on the device (n bounds the grid);
-// reset_all clears every work counter, otherwise only the queue head.
+// reset_all clears every work counter, otherwise only the queue heads.
+// lpp_max = 2 lets dense pixels use a pair of lanes each when the grid has
+// at least twice as many lanes as pixels (results then differ from the
+// one-lane path by float32 rounding of the synthesis sums).
 int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
                const float* W, int W_pp, const float* init, const vfisv_options& o,
                double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
-               hipStream_t s, bool reset_all);
+               hipStream_t s, bool reset_all, int lpp_max = 1);
 
 }  // namespace vfisv_capi

@@ -46,6 +46,8 @@ struct LMArgs {
   uint32_t free_mask;
   int chunk_log2;  // pixels per queue block = 2^chunk_log2
   int qbase;       // first of this batch's NQ queue-head slots in work[]
+  int lpp_max;     // 2: dense pixels may use a pair of lanes when the grid has
+                   // at least two lanes per pixel, else 1
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:

@@ -52,7 +52,7 @@ struct WaveCounters {
 // until chi^2 decides whether H and g are built.  NOBS = 0: banded filter,
 // rows folded into chi^2, H and g as they complete (H and g are built for
 // every trial, since the rows are gone once chi^2 is known).
-template <int NOBS>
+template <int NOBS, int LPP>
 __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int64_t pix,
                                           bool fresh, double chib, float* sHG, int lane,
                                           bool& accept) {
@@ -66,7 +66,10 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
     const float* obs = A.stokes + pix * ROWS;
     const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
     float acc[NOBS][NACC];
-    synth_accumulate<NOBS, true>(A.pts, px, A.C, acc);
+    if constexpr (LPP == 2)
+      synth_accumulate_pair<NOBS>(A.pts, px, A.C, acc, lane & 1);
+    else
+      synth_accumulate<NOBS, true>(A.pts, px, A.C, acc);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
       float S[4], J[4][NPAR];
@@ -159,9 +162,16 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // The persistent LM loop of one wave over one batch: lanes take pixels
 // from the batch's queues, fit them, and return when the queues are empty
 // and every lane has finished.
-template <int NOBS>
+// LPP = 2 (dense only): a pair of lanes carries one pixel; the even lane is
+// the pair's leader (it takes queue positions, writes the results and counts
+// the work), the odd lane mirrors its state: both see the same inputs and
+// the same pair sums, so they take the same decisions.
+template <int NOBS, int LPP>
 __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, int64_t glane,
                                         WaveCounters& wc) {
+  static_assert(LPP == 1 || (LPP == 2 && NOBS > 0), "lane pairs serve the dense layout");
+  const bool leader = LPP == 1 || (lane & 1) == 0;
+  const int mate = lane & ~(LPP - 1);
   const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
   const int rows = NOBS > 0 ? 4 * NOBS : 4 * A.C.n_obs;
   // Pixel queues: queue q owns the blocks b of 2^chunk_log2 consecutive
@@ -183,7 +193,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
 
   for (;;) {
     // ---- refill lanes whose pixel finished --------------------------------
-    unsigned long long nm = __ballot(!live && !exhausted);
+    unsigned long long nm = __ballot(!live && !exhausted && leader);
     for (int j = 0; j < NQ && nm != 0ull; ++j) {
       const int q = (home + j) % NQ;
       if (dry & (1u << q)) continue;
@@ -199,8 +209,15 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
       const bool need = (nm >> lane) & 1ull;
       const unsigned long long rank = (unsigned long long)__popcll(nm & ((1ull << lane) - 1ull));
       const bool take = need && rank < got;
-      if (take) {
-        const unsigned long long k = k0 + rank;
+      unsigned long long k = k0 + rank;
+      bool mine = take;
+      if constexpr (LPP == 2) {  // the odd lane follows its leader
+        mine = __shfl(take ? 1 : 0, mate) != 0;
+        const unsigned lo = __shfl((unsigned)(k & 0xffffffffull), mate);
+        const unsigned hi = __shfl((unsigned)(k >> 32), mate);
+        k = ((unsigned long long)hi << 32) | lo;
+      }
+      if (mine) {
         const unsigned long long pos =
             ((((k >> sh) << 3) + (unsigned long long)q) << sh) + (k & (ch - 1ull));
         pix = A.idx ? (int64_t)A.idx[pos] : (int64_t)pos;
@@ -214,12 +231,14 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
           for (int r = 0; r < rows; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
         }
         if (!finite) {
+          if (leader) {
 #pragma unroll
-          for (int q2 = 0; q2 < NPAR; ++q2) A.params[pix * NPAR + q2] = __builtin_nanf("");
-          A.chi2[pix] = __builtin_nan("");
-          A.iters[pix] = 0;
-          if (A.status) A.status[pix] = 3;
-          ++wc.pix;
+            for (int q2 = 0; q2 < NPAR; ++q2) A.params[pix * NPAR + q2] = __builtin_nanf("");
+            A.chi2[pix] = __builtin_nan("");
+            A.iters[pix] = 0;
+            if (A.status) A.status[pix] = 3;
+            ++wc.pix;
+          }
         } else {
           double M0[NPAR];
           if (A.init) {
@@ -242,6 +261,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
       nm &= ~__ballot(take);
     }
     if (nm != 0ull && dry == (1u << NQ) - 1u) exhausted = exhausted || ((nm >> lane) & 1ull);
+    if constexpr (LPP == 2) exhausted = __shfl(exhausted ? 1 : 0, mate) != 0;
     if (__ballot(live) == 0ull) {
       if (__ballot(!exhausted) == 0ull) break;
       continue;  // lanes that met non-finite input refill first
@@ -249,9 +269,9 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     if (!live) continue;
 
     // ---- synthesis pass with derivatives at Mc ----------------------------
-    ++wc.pass;
+    if (leader) ++wc.pass;
     bool accept = false;
-    const double chi = lm_pass<NOBS>(A, Mc, pix, fresh, chib, sHG, lane, accept);
+    const double chi = lm_pass<NOBS, LPP>(A, Mc, pix, fresh, chib, sHG, lane, accept);
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
@@ -262,14 +282,14 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
       chib = chi;
     } else {
       ++it;
-      ++wc.trial;
+      if (leader) ++wc.trial;
       if (accept) {
         const double dec = chib - chi;
 #pragma unroll
         for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
         chib = chi;
         eps = eps_down(eps);
-        ++wc.acc;
+        if (leader) ++wc.acc;
         if (dec < A.rel_tol * (chi + dec)) done = 0;
       } else {
         eps = eps_up(eps);
@@ -280,12 +300,14 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     if (done < 0 && it >= A.max_iter) done = 1;
 
     if (done >= 0) {
+      if (leader) {
 #pragma unroll
-      for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = Mb[q];
-      A.chi2[pix] = chib;
-      A.iters[pix] = it;
-      if (A.status) A.status[pix] = done;
-      ++wc.pix;
+        for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = Mb[q];
+        A.chi2[pix] = chib;
+        A.iters[pix] = it;
+        if (A.status) A.status[pix] = done;
+        ++wc.pix;
+      }
       live = false;
     } else {
       // ---- damped float64 step from the best model ------------------------
@@ -297,7 +319,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
       double delta[NPAR], sc[NPAR], b[NPAR];
       const int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
       if (code == 1) {
-        ++wc.fb;
+        if (leader) ++wc.fb;
         double* ws = A.ws + glane;
         solve_eigen_fallback(&sHG[lane], 64, &sHG[55 * 64 + lane], 64, eps, A.free_mask, ws,
                              A.ws_stride);
@@ -333,8 +355,17 @@ template <int NOBS>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
   const int lane = threadIdx.x;
+  const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
   WaveCounters wc;
-  lm_loop<NOBS>(A, sHG, lane, (int64_t)blockIdx.x * 64 + lane, wc);
+  if constexpr (NOBS > 0) {
+    const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
+    if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)gridDim.x * 64ull)
+      lm_loop<NOBS, 2>(A, sHG, lane, glane, wc);
+    else
+      lm_loop<NOBS, 1>(A, sHG, lane, glane, wc);
+  } else {
+    lm_loop<NOBS, 1>(A, sHG, lane, glane, wc);
+  }
   flush_counters(A.work, wc, lane);
 }
 
@@ -349,9 +380,9 @@ __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   WaveCounters wc;
   for (int i = 0; i < B.n_batches; ++i) {
     if (B.kind[i] == KIND_DENSE6)
-      lm_loop<NOBS_HMI>(B.a[i], sHG, lane, glane, wc);
+      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, lane, glane, wc);
     else
-      lm_loop<0>(B.a[i], sHG, lane, glane, wc);
+      lm_loop<0, 1>(B.a[i], sHG, lane, glane, wc);
   }
   flush_counters(B.a[0].work, wc, lane);
 }

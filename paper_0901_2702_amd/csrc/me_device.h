@@ -302,6 +302,47 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   }
 }
 
+// The same accumulation shared by a pair of lanes (lane & 1 = odd): each
+// lane takes every other synthesis point (two wave-uniform records per
+// step, each lane selecting its own), then the pair adds its partial sums,
+// so both lanes hold the full sums.  Used when a launch has at least two
+// lanes per pixel: a pass then takes about half the time.
+template <int NOBS>
+__device__ __forceinline__ void synth_accumulate_pair(const Point* __restrict__ pts,
+                                                      const Pix& p, const Consts& C,
+                                                      float (&acc)[NOBS][NACC], bool odd) {
+#pragma unroll
+  for (int i = 0; i < NOBS; ++i)
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) acc[i][m] = 0.f;
+  for (int k = 0; k < C.n_pts; k += 2) {
+    const Point P0 = load_uniform(pts, k);
+    Point P1;
+    if (k + 1 < C.n_pts) {
+      P1 = load_uniform(pts, k + 1);
+    } else {
+      P1.dl = 0.f;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) P1.w[i] = 0.f;  // taps and mask zero: contributes nothing
+    }
+    float c[NACC];
+    point_contrib<true>(odd ? P1.dl : P0.dl, p, C, c);
+    const uint32_t mask = __float_as_uint(P0.w[6]) | __float_as_uint(P1.w[6]);
+#pragma unroll
+    for (int i = 0; i < NOBS; ++i) {
+      if (mask & (1u << i)) {  // a record's taps are zero outside its own mask
+        const float w = odd ? P1.w[i] : P0.w[i];
+#pragma unroll
+        for (int m = 0; m < NACC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NOBS; ++i)
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) acc[i][m] += __shfl_xor(acc[i][m], 1);
+}
+
 // Banded instruments (many observed samples, each seeing a short window of
 // the synthesis grid that advances BAND_S points per sample, at most
 // BAND_S * BAND_R points long).  The grid is cut into blocks of BAND_S

@@ -470,7 +470,7 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
   if (e == hipSuccess) e = fallback_select(chi2, n, tau, list, count, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: fallback selection");
   rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, nullptr, o, inv_dof, p_fb,
-                  c_fb, i_fb, s_fb, s, false);
+                  c_fb, i_fb, s_fb, s, false, 2);
   if (rc) return rc;
   // 4. keep the better of the two fits; flag the pixel
   e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, params, chi2, iters, status, s);

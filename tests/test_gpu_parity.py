@@ -322,3 +322,34 @@ def test_autotune_picks_a_candidate_and_keeps_results(ctx, hmi):
     assert ctx.counters()["grid_waves"] == min(t["grid_waves"], (20000 + 63) // 64)
     for k in ref:
         assert np.array_equal(out[k].cpu().numpy(), ref[k]), k
+
+
+def test_lane_pairs_follow_the_oracle(ctx, hmi):
+    """lanes_per_pixel = 2: each pixel's synthesis is split over two lanes;
+    the fit must still follow the oracle as the one-lane path does."""
+    spec, inst, oi = hmi
+    n = 1024
+    P, obs = _observations(oi, spec, n, 1000)
+    W = wl.weights(spec.n_obs)
+    o, Wd = _dev(ctx, obs), _dev(ctx, W)
+    op0 = vf.Options(max_iter=0, lanes_per_pixel=2)
+    out0 = vf.invert(ctx, inst, o, Wd, opts=op0)
+    assert ctx.counters()["grid_waves"] == 2 * n // 64
+    ref0 = oracle.invert(oi, obs, W, opts=oracle.Options(max_iter=0))
+    np.testing.assert_allclose(out0["chi2"].cpu().numpy(), ref0["chi2"], rtol=2e-4)
+    out = vf.invert(ctx, inst, o, Wd, opts=vf.Options(lanes_per_pixel=2))
+    c = ctx.counters()
+    gc, gi = out["chi2"].cpu().numpy(), out["iters"].cpu().numpy()
+    assert c["pixels"] == n and c["trials"] == gi.sum() and c["passes"] == c["trials"] + n
+    assert np.isin(out["status"].cpu().numpy(), (0, 1, 2)).all()
+    ref = oracle.invert(oi, obs, W)
+    a, b = np.median(gc), np.median(ref["chi2"])
+    assert abs(a - b) / b < 0.05, (a, b)
+    assert abs(np.mean(gc < 2.0) - np.mean(ref["chi2"] < 2.0)) < 0.05
+    assert abs(gi.mean() - ref["iters"].mean()) / ref["iters"].mean() < 0.1
+    # against the one-lane path on the same pixels
+    one = vf.invert(ctx, inst, o, Wd)
+    oc = one["chi2"].cpu().numpy()
+    assert np.mean(np.abs(gc - oc) / oc < 1e-4) > 0.4
+    with pytest.raises(Exception):
+        vf.invert(ctx, inst, o, Wd, opts=vf.Options(lanes_per_pixel=3))
