@@ -24,7 +24,7 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 class _Instrument(ctypes.Structure):
     _fields_ = [("lambda0_A", ctypes.c_double), ("geff", ctypes.c_double),
                 ("n_fine", ctypes.c_int), ("fine_offset_mA", _dp),
-                ("n_obs", ctypes.c_int), ("filter", _dp)]
+                ("n_obs", ctypes.c_int), ("filter", _dp), ("voigt", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):
@@ -51,6 +51,10 @@ def lib():
         L.orc_zeeman_constant.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_zeeman_constant.restype = ctypes.c_double
         L.orc_synth_fine.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
+        L.orc_voigt_taylor_batch.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_voigt_taylor_batch.restype = None
+        L.orc_voigt_table_node.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.orc_voigt_table_node.restype = None
         L.orc_forward.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
         L.orc_project.argtypes = [_dp]
         L.orc_eps_decrease.argtypes = [ctypes.c_double]
@@ -94,14 +98,16 @@ class Instrument:
     filt: [n_obs, n_fine] filter matrix.
     """
 
-    def __init__(self, lambda0_A, geff, fine_offset_mA, filt):
+    def __init__(self, lambda0_A, geff, fine_offset_mA, filt, voigt=0):
         self.fine = np.ascontiguousarray(fine_offset_mA, dtype=np.float64)
         self.filt = np.ascontiguousarray(filt, dtype=np.float64)
         assert self.filt.shape[1] == self.fine.shape[0]
+        assert voigt in (0, 1, 2)
         self.n_fine = self.fine.shape[0]
         self.n_obs = self.filt.shape[0]
+        self.voigt = voigt
         self.c = _Instrument(float(lambda0_A), float(geff), self.n_fine, _d(self.fine),
-                             self.n_obs, _d(self.filt))
+                             self.n_obs, _d(self.filt), int(voigt))
 
 
 @dataclass
@@ -123,6 +129,22 @@ def faddeeva(u, a):
     F = np.empty_like(u)
     lib().orc_faddeeva_batch(u.size, _d(u), _d(a), _d(H), _d(F))
     return H, F
+
+
+def voigt_taylor(order, u, a):
+    """H, F from the Taylor table (Sect. 3.2, Eqs. 10-13) at order 1 or 2."""
+    u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+    a = np.ascontiguousarray(np.broadcast_to(a, u.shape), dtype=np.float64)
+    H = np.empty_like(u)
+    F = np.empty_like(u)
+    lib().orc_voigt_taylor_batch(int(order), u.size, _d(u), _d(a), _d(H), _d(F))
+    return H, F
+
+
+def voigt_table_node(i, j):
+    h, f = ctypes.c_double(), ctypes.c_double()
+    lib().orc_voigt_table_node(i, j, ctypes.byref(h), ctypes.byref(f))
+    return h.value, f.value
 
 
 def zeeman_constant(lambda0_A, geff):

@@ -22,6 +22,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <pthread.h>
 
 #include "oracle.h"
 
@@ -84,4 +85,70 @@ void orc_faddeeva(double u, double a, double *H, double *F) {
 
 void orc_faddeeva_batch(int64_t n, const double *u, const double *a, double *H, double *F) {
   for (int64_t i = 0; i < n; ++i) orc_faddeeva(u[i], a[i], &H[i], &F[i]);
+}
+
+/* ---- Taylor table (Sect. 3.2, Eqs. 10-13) -------------------------------- */
+
+static double vt_H[ORC_VT_NA][ORC_VT_NU], vt_F[ORC_VT_NA][ORC_VT_NU];
+static pthread_once_t vt_once = PTHREAD_ONCE_INIT;
+
+static void vt_build(void) {
+  for (int j = 0; j < ORC_VT_NA; ++j)
+    for (int i = 0; i < ORC_VT_NU; ++i)
+      orc_faddeeva(ORC_VT_STEP * i, ORC_VT_STEP * j, &vt_H[j][i], &vt_F[j][i]);
+}
+
+void orc_voigt_table_node(int i, int j, double *H, double *F) {
+  pthread_once(&vt_once, vt_build);
+  *H = vt_H[j][i];
+  *F = vt_F[j][i];
+}
+
+/* w(z) ~ (i / sqrt(pi)) (1/z) (1 + 1/(2 z^2) + 3/(4 z^4) + 15/(8 z^6)) for
+ * large |z| (the next term is below 1e-10 relative for |z| >= 24.975). */
+static void w_asymptotic(double x, double y, double *H, double *F) {
+  const double complex z = x + I * y;
+  const double complex iz2 = 1.0 / (z * z);
+  const double complex s = 1.0 + iz2 * (0.5 + iz2 * (0.75 + iz2 * 1.875));
+  const double complex w = (I / ORC_SQRT_PI) * s / z;
+  *H = creal(w);
+  *F = cimag(w);
+}
+
+void orc_voigt_taylor(int order, double u, double a, double *H, double *F) {
+  const double x = fabs(u);
+  const double sgn = u < 0.0 ? -1.0 : 1.0;
+  if (x >= ORC_VT_STEP * (ORC_VT_NU - 0.5)) {
+    w_asymptotic(x, a, H, F);
+    *F *= sgn;
+    return;
+  }
+  pthread_once(&vt_once, vt_build);
+  const int i = (int)lround(x / ORC_VT_STEP);
+  long jl = lround(a / ORC_VT_STEP);
+  if (jl < 0) jl = 0;
+  if (jl > ORC_VT_NA - 1) jl = ORC_VT_NA - 1;
+  const int j = (int)jl;
+  const double u0 = ORC_VT_STEP * i, a0 = ORC_VT_STEP * j;
+  const double h = vt_H[j][i], f = vt_F[j][i];
+  /* Eqs. 8-9 at the node */
+  const double al = -2.0 / ORC_SQRT_PI + 2.0 * a0 * h + 2.0 * u0 * f;
+  const double be = 2.0 * a0 * f - 2.0 * u0 * h;
+  const double du = x - u0, da = a - a0;
+  double Ht = h + al * da + be * du;
+  double Ft = f + be * da - al * du;
+  if (order >= 2) {
+    /* Eqs. 10-11: the second derivatives are multiples of these two */
+    const double P = h + a0 * al + u0 * be;
+    const double Q = f + a0 * be - u0 * al;
+    Ht += P * (da * da - du * du) + 2.0 * Q * da * du;
+    Ft += Q * (da * da - du * du) - 2.0 * P * da * du;
+  }
+  *H = Ht;
+  *F = sgn * Ft;
+}
+
+void orc_voigt_taylor_batch(int order, int64_t n, const double *u, const double *a, double *H,
+                            double *F) {
+  for (int64_t i = 0; i < n; ++i) orc_voigt_taylor(order, u[i], a[i], &H[i], &F[i]);
 }

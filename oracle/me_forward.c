@@ -105,9 +105,12 @@ static dual d_cos(dual a, int nd) {
 /* H and F at (a, u) with Eqs. 8-9:
  *   dH/da = -dF/du = -2/sqrt(pi) + 2aH + 2uF   (alpha)
  *   dH/du =  dF/da =  2aF - 2uH                (beta)            */
-static void d_voigt(dual u, dual a, int nd, dual *H, dual *F) {
+static void d_voigt(int variant, dual u, dual a, int nd, dual *H, dual *F) {
   double h, f;
-  orc_faddeeva(u.v, a.v, &h, &f);
+  if (variant == 0)
+    orc_faddeeva(u.v, a.v, &h, &f);
+  else
+    orc_voigt_taylor(variant, u.v, a.v, &h, &f);
   const double al = -ORC_TWO_OVER_SQRT_PI + 2.0 * a.v * h + 2.0 * u.v * f;
   const double be = 2.0 * a.v * f - 2.0 * u.v * h;
   H->v = h;
@@ -126,7 +129,7 @@ double orc_zeeman_constant(double lambda0_A, double geff) {
 }
 
 /* Stokes vector (I,Q,U,V) and its gradient at one synthesis-grid point. */
-static void synth_point(double lambda0_mA, double cz, const double *M, double dlam,
+static void synth_point(double lambda0_mA, double cz, int voigt, const double *M, double dlam,
                         int nd, dual out[4]) {
   const double deg = ORC_PI / 180.0;
   dual B = d_var(M[ORC_B], ORC_B, 1.0);
@@ -148,9 +151,9 @@ static void synth_point(double lambda0_mA, double cz, const double *M, double dl
   dual u_r = d_sub(u_p, zee, nd);
 
   dual Hp, Fp, Hb, Fb, Hr, Fr;
-  d_voigt(u_p, a, nd, &Hp, &Fp);
-  d_voigt(u_b, a, nd, &Hb, &Fb);
-  d_voigt(u_r, a, nd, &Hr, &Fr);
+  d_voigt(voigt, u_p, a, nd, &Hp, &Fp);
+  d_voigt(voigt, u_b, a, nd, &Hb, &Fb);
+  d_voigt(voigt, u_r, a, nd, &Hr, &Fr);
 
   dual sg = d_sin(gam, nd), cg = d_cos(gam, nd);
   dual sin2g = d_sq(sg, nd);
@@ -213,7 +216,7 @@ void orc_synth_fine(const orc_instrument *inst, const double *M, double *S, doub
   const double cz = orc_zeeman_constant(inst->lambda0_A, inst->geff);
   for (int k = 0; k < nf; ++k) {
     dual out[4];
-    synth_point(lambda0_mA, cz, M, inst->fine_offset_mA[k], nd, out);
+    synth_point(lambda0_mA, cz, inst->voigt, M, inst->fine_offset_mA[k], nd, out);
     for (int s = 0; s < 4; ++s) {
       S[s * nf + k] = out[s].v;
       if (dS)

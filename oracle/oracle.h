@@ -46,6 +46,9 @@ typedef struct {
   const double *fine_offset_mA;  /* [n_fine] offsets from lambda0 [mA] */
   int n_obs;                     /* observed wavelengths L */
   const double *filter;          /* [n_obs][n_fine] row-major */
+  int voigt;                     /* H, F by: 0 the Faddeeva function itself,
+                                    1 or 2 the Taylor table of Eqs. 12-13 at
+                                    first or second order */
 } orc_instrument;
 
 typedef struct {
@@ -66,6 +69,22 @@ typedef struct {
 /* Faddeeva function w(u + i a) = H + i F for a >= 0 (Sect. 3.2). */
 void orc_faddeeva(double u, double a, double *H, double *F);
 void orc_faddeeva_batch(int64_t n, const double *u, const double *a, double *H, double *F);
+
+/* Taylor-table evaluation of H and F (Sect. 3.2, Eqs. 10-13): a table of H
+ * and F at u = 0.05 i (i < 500) and a = 0.05 j (j < 100), built from
+ * orc_faddeeva; H and F at (u, a) are extrapolated from the nearest node
+ * with the first (order 1) or the first and second (order 2) derivatives of
+ * Eqs. 8-11.  H is even and F odd in u.  Where |u| is beyond the last
+ * node's cell (>= 24.975) the asymptotic series of w(z) for large |z| is
+ * used instead; a is clamped to the last node (the model's box ends at
+ * a = 5).  The table is built once per process, on first use. */
+enum { ORC_VT_NU = 500, ORC_VT_NA = 100 };
+#define ORC_VT_STEP 0.05
+void orc_voigt_taylor(int order, double u, double a, double *H, double *F);
+void orc_voigt_taylor_batch(int order, int64_t n, const double *u, const double *a, double *H,
+                            double *F);
+/* The table node values (for tests): H and F at (u_i, a_j). */
+void orc_voigt_table_node(int i, int j, double *H, double *F);
 
 /* Zeeman splitting constant of Eq. 7 [mA per G]. */
 double orc_zeeman_constant(double lambda0_A, double geff);
