@@ -112,6 +112,12 @@ typedef struct {
                        /* path by float32 rounding of the synthesis sums.    */
                        /* The learned path's refit uses pairs when they fit; */
                        /* vfisv_invert_batches keeps one lane per pixel.     */
+  int voigt;           /* H and F (Sect. 3.2) by: 0 (default) Weideman's     */
+                       /* 16-term rational series; 1 or 2 the Taylor table */
+                       /* of Eqs. 10-13 (500 u x 100 a nodes at 0.05, built */
+                       /* by the library on first use: a synchronising     */
+                       /* allocation) at first or second order.  HMI-shaped */
+                       /* instruments only; not in vfisv_invert_batches.     */
 } vfisv_options;
 
 /* Result of vfisv_autotune. */
@@ -184,6 +190,11 @@ void vfisv_options_default(vfisv_options *opt);
 int vfisv_synthesize(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                      const float *params, const float *noise, float *stokes,
                      float *jac, void *stream);
+/* The same with the Voigt evaluation chosen as in vfisv_options.voigt
+ * (0, 1 or 2; 1 and 2 need an HMI-shaped instrument). */
+int vfisv_synthesize_voigt(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                           const float *params, const float *noise, float *stokes,
+                           float *jac, int voigt, void *stream);
 
 /* ---- inversion (Sects. 2 and 4) --------------------------------------- */
 

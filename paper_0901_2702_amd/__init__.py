@@ -43,7 +43,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
                 ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int),
-                ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int)]
+                ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int),
+                ("voigt", ctypes.c_int)]
 
 
 class _Batch(ctypes.Structure):
@@ -74,7 +75,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
-           "vfisv_invert_batches", "vfisv_autotune")
+           "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt")
 
 _LIB = None
 
@@ -98,6 +99,8 @@ def lib():
         L.vfisv_options_default.argtypes = [ctypes.POINTER(_Options)]
         L.vfisv_options_default.restype = None
         L.vfisv_synthesize.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.vfisv_synthesize_voigt.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp,
+                                             ctypes.c_int, _vp]
         L.vfisv_invert.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int, _vp,
                                    ctypes.POINTER(_Options), _vp, _vp, _vp, _vp, _vp]
         L.vfisv_get_counters.argtypes = [_vp, ctypes.POINTER(_Counters)]
@@ -222,26 +225,29 @@ class Options:
     grid_waves: int = 0
     chunk_log2: int = -1
     lanes_per_pixel: int = 1
+    voigt: int = 0
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
-                        self.grid_waves, self.chunk_log2, self.lanes_per_pixel)
+                        self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt)
 
 
-def synthesize(ctx, inst, params, noise=None, jac=False, out=None):
+def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):
     """Filtered Stokes vector [n, 4, n_obs] (and Jacobian [n, 4, n_obs, 10])
-    of the models ``params`` [n, 10] (float32, on the context's device)."""
+    of the models ``params`` [n, 10] (float32, on the context's device);
+    ``voigt`` selects the H/F evaluation as Options.voigt does."""
     dev = ctx.device
     n = params.shape[0]
     p = _ptr(params, torch.float32, dev, name="params")
     stokes = out if out is not None else torch.empty((n, 4, inst.n_obs), device=dev,
                                                      dtype=torch.float32)
     J = torch.empty((n, 4, inst.n_obs, NPAR), device=dev, dtype=torch.float32) if jac else None
-    ctx._check(lib().vfisv_synthesize(ctx._h, inst._h, n, p,
-                                      _ptr(noise, torch.float32, dev, name="noise"),
-                                      _ptr(stokes, torch.float32, dev, name="out"),
-                                      _ptr(J, torch.float32, dev, name="jac"), _stream(dev)),
-               "vfisv_synthesize")
+    ctx._check(lib().vfisv_synthesize_voigt(ctx._h, inst._h, n, p,
+                                            _ptr(noise, torch.float32, dev, name="noise"),
+                                            _ptr(stokes, torch.float32, dev, name="out"),
+                                            _ptr(J, torch.float32, dev, name="jac"), int(voigt),
+                                            _stream(dev)),
+               "vfisv_synthesize_voigt")
     return (stokes, J) if jac else stokes
 
 

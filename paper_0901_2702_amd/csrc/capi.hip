@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -59,6 +60,13 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
     return fail(ctx, VFISV_E_INVALID, "options: chunk_log2 outside -1..20");
   if (o.lanes_per_pixel != 1 && o.lanes_per_pixel != 2)
     return fail(ctx, VFISV_E_INVALID, "options: lanes_per_pixel must be 1 or 2");
+  if (o.voigt < 0 || o.voigt > 2) return fail(ctx, VFISV_E_INVALID, "options: voigt must be 0, 1 or 2");
+  if (o.voigt != 0 && inst->kind != KIND_DENSE6)
+    return fail(ctx, VFISV_E_UNSUPPORTED, "options: the Taylor table serves HMI-shaped instruments");
+  if (o.voigt != 0) {
+    const int rc = ensure_vtab(ctx);
+    if (rc) return rc;
+  }
   o.free_mask &= 0x3FFu;
   int nfree = 0;
   for (int p = 0; p < NPAR; ++p) nfree += (o.free_mask >> p) & 1u;
@@ -76,6 +84,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
                          const vfisv_options& o, double inv_dof, float* params, double* chi2,
                          int32_t* iters, int32_t* status, LMArgs& a) {
   a.C = inst->C;
+  a.C.vtab = ctx->d_vtab;
   a.pts = inst->d_pts;
   a.blocks = inst->d_blocks;
   a.row_sums = inst->d_row_sums;
@@ -132,7 +141,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.ws_stride = (int64_t)grid * 64;
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
-  e = launch_lm(a, inst->kind, grid, s);
+  e = launch_lm(a, inst->kind, o.voigt, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert launch");
   return VFISV_OK;
 }
@@ -166,6 +175,43 @@ static void weideman_coefficients(int N, double* L_out, double* a /* [N + 1] */)
   *L_out = L;
 }
 
+namespace vfisv_capi {
+
+// The Taylor table's nodes {H, F}(u = 0.05 i, a = 0.05 j), i < 500, j < 100,
+// from Weideman's series with 32 terms in double precision (within 4e-14 of
+// w(z) over the table's range), rounded to float.
+int ensure_vtab(vfisv_ctx* ctx) {
+  if (ctx->d_vtab) return VFISV_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  double L, a[33];
+  weideman_coefficients(32, &L, a);
+  const double inv_sqrt_pi = 0.56418958354775628695;
+  std::vector<float2> tab((size_t)VT_NU * VT_NA);
+  for (int j = 0; j < VT_NA; ++j)
+    for (int i = 0; i < VT_NU; ++i) {
+      const std::complex<double> z(0.05 * i, 0.05 * j);
+      const std::complex<double> den = L - std::complex<double>(0.0, 1.0) * z;
+      const std::complex<double> Z = (L + std::complex<double>(0.0, 1.0) * z) / den;
+      std::complex<double> p = a[32];
+      for (int n = 31; n >= 1; --n) p = p * Z + a[n];
+      const std::complex<double> w = 2.0 * p / (den * den) + inv_sqrt_pi / den;
+      tab[(size_t)j * VT_NU + i] = make_float2((float)w.real(), (float)w.imag());
+    }
+  float2* d = nullptr;
+  e = hipMalloc(&d, sizeof(float2) * tab.size());
+  if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "Taylor table allocation");
+  e = hipMemcpy(d, tab.data(), sizeof(float2) * tab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    return hip_fail(ctx, e, "Taylor table copy");
+  }
+  ctx->d_vtab = d;
+  return VFISV_OK;
+}
+
+}  // namespace vfisv_capi
+
 extern "C" {
 
 const char* vfisv_version(void) { return "vfisv-gfx950 0.2.0"; }
@@ -173,6 +219,7 @@ const char* vfisv_version(void) { return "vfisv-gfx950 0.2.0"; }
 const char* vfisv_last_error(const vfisv_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
+
 
 int vfisv_create(vfisv_ctx** out, int device) {
   if (!out) return fail(nullptr, VFISV_E_INVALID, "vfisv_create: out is NULL");
@@ -239,6 +286,7 @@ int vfisv_destroy(vfisv_ctx* ctx) {
   hipFree(ctx->d_ws);
   hipFree(ctx->d_work);
   if (ctx->d_learn) hipFree(ctx->d_learn);
+  if (ctx->d_vtab) hipFree(ctx->d_vtab);
   delete ctx;
   return VFISV_OK;
 }
@@ -253,6 +301,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->grid_waves = 0;
   o->chunk_log2 = -1;
   o->lanes_per_pixel = 1;
+  o->voigt = 0;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -434,16 +483,30 @@ int vfisv_instrument_destroy(vfisv_instrument* inst) {
 int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                      const float* params, const float* noise, float* stokes, float* jac,
                      void* stream) {
+  return vfisv_synthesize_voigt(ctx, inst, n, params, noise, stokes, jac, 0, stream);
+}
+
+int vfisv_synthesize_voigt(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                           const float* params, const float* noise, float* stokes, float* jac,
+                           int voigt, void* stream) {
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "synthesize: ctx is NULL");
   int rc = check_inst(ctx, inst, "synthesize");
   if (rc) return rc;
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "synthesize: n < 0");
+  if (voigt < 0 || voigt > 2) return fail(ctx, VFISV_E_INVALID, "synthesize: voigt must be 0..2");
+  if (voigt != 0 && inst->kind != KIND_DENSE6)
+    return fail(ctx, VFISV_E_UNSUPPORTED, "synthesize: the Taylor table serves HMI-shaped instruments");
   if (n == 0) return VFISV_OK;
   if (!params || !stokes) return fail(ctx, VFISV_E_INVALID, "synthesize: NULL buffer");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (voigt != 0) {
+    rc = ensure_vtab(ctx);
+    if (rc) return rc;
+  }
   SynthArgs a;
   a.C = inst->C;
+  a.C.vtab = ctx->d_vtab;
   a.pts = inst->d_pts;
   a.blocks = inst->d_blocks;
   a.row_sums = inst->d_row_sums;
@@ -453,7 +516,7 @@ int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.jac = jac;
   a.n = n;
   const int grid = grid_for(n, (int64_t)ctx->num_cus * 16);
-  e = launch_synth(a, inst->kind, jac != nullptr, grid, (hipStream_t)stream);
+  e = launch_synth(a, inst->kind, voigt, jac != nullptr, grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "synthesize launch");
   return VFISV_OK;
 }
@@ -499,6 +562,8 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
     if (rc) return rc;
     if (b.n < 0 || b.n > INT32_MAX)
       return fail(ctx, VFISV_E_INVALID, "invert_batches: n must be in 0 .. 2^31 - 1");
+    if (o.voigt != 0)
+      return fail(ctx, VFISV_E_UNSUPPORTED, "invert_batches: the Taylor table is not served here");
     if (b.n > 0 && (!b.stokes || !b.W || !b.params || !b.chi2 || !b.iters))
       return fail(ctx, VFISV_E_INVALID, "invert_batches: NULL buffer");
     fill_lm_args(ctx, b.inst, b.n, nullptr, nullptr, b.stokes, b.W, b.W_per_pixel, b.init, o,

@@ -17,6 +17,7 @@ struct vfisv_ctx {
   unsigned long long* d_work = nullptr;  // WORK_SLOTS counters
   double* d_ws = nullptr;                // eigen-fallback workspace
   int64_t ws_lanes = 0;
+  float2* d_vtab = nullptr;              // Taylor table {H, F}, built on first use
   float wc[vfisv::NW + 1];
   float wL = 0.f;
   // scheduling picked by vfisv_autotune, per instrument layout (KIND_*)
@@ -47,6 +48,8 @@ int fail(vfisv_ctx* ctx, int code, const std::string& msg);
 int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what);
 int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn);
 int grid_for(int64_t n, int64_t cap);
+// Build the Taylor table of H and F on the device (once per context).
+int ensure_vtab(vfisv_ctx* ctx);
 int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_options* opt,
                   vfisv_options* out, double* inv_dof);
 

@@ -85,9 +85,10 @@ struct SolveArgs {
 hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s);
 hipError_t launch_hist(const int32_t* iters, int64_t n, int n_bins, unsigned long long* out,
                        int max_blocks, hipStream_t s);
-hipError_t launch_lm(const LMArgs& a, int kind, int grid, hipStream_t s);
+hipError_t launch_lm(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s);
 hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s);
-hipError_t launch_synth(const SynthArgs& a, int kind, bool deriv, int grid, hipStream_t s);
+hipError_t launch_synth(const SynthArgs& a, int kind, int voigt, bool deriv, int grid,
+                        hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t lm_blocks_per_cu(int* out);
 hipError_t band_blocks_per_cu(int* out);

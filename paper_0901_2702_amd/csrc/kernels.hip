@@ -52,7 +52,7 @@ struct WaveCounters {
 // until chi^2 decides whether H and g are built.  NOBS = 0: banded filter,
 // rows folded into chi^2, H and g as they complete (H and g are built for
 // every trial, since the rows are gone once chi^2 is known).
-template <int NOBS, int LPP>
+template <int NOBS, int LPP, int V>
 __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int64_t pix,
                                           bool fresh, double chib, float* sHG, int lane,
                                           bool& accept) {
@@ -67,9 +67,9 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
     const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
     float acc[NOBS][NACC];
     if constexpr (LPP == 2)
-      synth_accumulate_pair<NOBS>(A.pts, px, A.C, acc, lane & 1);
+      synth_accumulate_pair<NOBS, V>(A.pts, px, A.C, acc, lane & 1);
     else
-      synth_accumulate<NOBS, true>(A.pts, px, A.C, acc);
+      synth_accumulate<NOBS, true, V>(A.pts, px, A.C, acc);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
       float S[4], J[4][NPAR];
@@ -166,7 +166,7 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // the pair's leader (it takes queue positions, writes the results and counts
 // the work), the odd lane mirrors its state: both see the same inputs and
 // the same pair sums, so they take the same decisions.
-template <int NOBS, int LPP>
+template <int NOBS, int LPP, int V = 0>
 __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, int64_t glane,
                                         WaveCounters& wc) {
   static_assert(LPP == 1 || (LPP == 2 && NOBS > 0), "lane pairs serve the dense layout");
@@ -271,7 +271,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     // ---- synthesis pass with derivatives at Mc ----------------------------
     if (leader) ++wc.pass;
     bool accept = false;
-    const double chi = lm_pass<NOBS, LPP>(A, Mc, pix, fresh, chib, sHG, lane, accept);
+    const double chi = lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, sHG, lane, accept);
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
@@ -351,7 +351,8 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
   }
 }
 
-template <int NOBS>
+// V: Voigt evaluation (0 Weideman's series, 1/2 Taylor table; dense only).
+template <int NOBS, int V>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
   const int lane = threadIdx.x;
@@ -360,11 +361,11 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   if constexpr (NOBS > 0) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
     if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)gridDim.x * 64ull)
-      lm_loop<NOBS, 2>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 2, V>(A, sHG, lane, glane, wc);
     else
-      lm_loop<NOBS, 1>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 1, V>(A, sHG, lane, glane, wc);
   } else {
-    lm_loop<NOBS, 1>(A, sHG, lane, glane, wc);
+    lm_loop<NOBS, 1, V>(A, sHG, lane, glane, wc);
   }
   flush_counters(A.work, wc, lane);
 }
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   flush_counters(B.a[0].work, wc, lane);
 }
 
-template <int NOBS, bool DERIV>
+template <int NOBS, bool DERIV, int V>
 __global__ __launch_bounds__(64) void synth_kernel(const SynthArgs A) {
   constexpr int ROWS = 4 * NOBS;
   for (int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x; i < A.n;
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(64) void synth_kernel(const SynthArgs A) {
     Pix px;
     pix_setup(M, A.C, px);
     float acc[NOBS][NACC];
-    synth_accumulate<NOBS, DERIV>(A.pts, px, A.C, acc);
+    synth_accumulate<NOBS, DERIV, V>(A.pts, px, A.C, acc);
     RowFactors rf;
     row_factors(M, px, A.C, rf);
 #pragma unroll
@@ -510,9 +511,11 @@ hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_lm(const LMArgs& a, int kind, int grid, hipStream_t s) {
-  if (kind == KIND_DENSE6) lm_kernel<NOBS_HMI><<<grid, 64, 0, s>>>(a);
-  else lm_kernel<0><<<grid, 64, 0, s>>>(a);
+hipError_t launch_lm(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s) {
+  if (kind != KIND_DENSE6) lm_kernel<0, 0><<<grid, 64, 0, s>>>(a);
+  else if (voigt == 1) lm_kernel<NOBS_HMI, 1><<<grid, 64, 0, s>>>(a);
+  else if (voigt == 2) lm_kernel<NOBS_HMI, 2><<<grid, 64, 0, s>>>(a);
+  else lm_kernel<NOBS_HMI, 0><<<grid, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -521,10 +524,19 @@ hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_synth(const SynthArgs& a, int kind, bool deriv, int grid, hipStream_t s) {
+hipError_t launch_synth(const SynthArgs& a, int kind, int voigt, bool deriv, int grid,
+                        hipStream_t s) {
   if (kind == KIND_DENSE6) {
-    if (deriv) synth_kernel<NOBS_HMI, true><<<grid, 64, 0, s>>>(a);
-    else synth_kernel<NOBS_HMI, false><<<grid, 64, 0, s>>>(a);
+    if (voigt == 1) {
+      if (deriv) synth_kernel<NOBS_HMI, true, 1><<<grid, 64, 0, s>>>(a);
+      else synth_kernel<NOBS_HMI, false, 1><<<grid, 64, 0, s>>>(a);
+    } else if (voigt == 2) {
+      if (deriv) synth_kernel<NOBS_HMI, true, 2><<<grid, 64, 0, s>>>(a);
+      else synth_kernel<NOBS_HMI, false, 2><<<grid, 64, 0, s>>>(a);
+    } else {
+      if (deriv) synth_kernel<NOBS_HMI, true, 0><<<grid, 64, 0, s>>>(a);
+      else synth_kernel<NOBS_HMI, false, 0><<<grid, 64, 0, s>>>(a);
+    }
   } else {
     if (deriv) synth_band_kernel<true><<<grid, 64, 0, s>>>(a);
     else synth_band_kernel<false><<<grid, 64, 0, s>>>(a);
@@ -538,7 +550,7 @@ hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s) {
 }
 
 hipError_t lm_blocks_per_cu(int* out) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_kernel<NOBS_HMI>, 64, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_kernel<NOBS_HMI, 0>, 64, 0);
 }
 
 hipError_t band_blocks_per_cu(int* out) {

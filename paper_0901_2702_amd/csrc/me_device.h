@@ -55,6 +55,7 @@ struct Consts {
   int n_pts;             // synthesis points with a non-zero tap
   int n_obs;
   float row_sum[8];      // sum of the kept taps of each filter row
+  const float2* vtab;    // Taylor table {H, F} [VT_NA][VT_NU] (Voigt variants 1, 2)
 };
 
 // One synthesis point: offset and the taps of the (up to 6) filter rows;
@@ -87,6 +88,8 @@ struct Pix {
   float vsi, invD, zs, a, twoa, denr, denr2, c0;
   float hs2, hc, hI, hq, hsin2g, hsg, s2h, cgh;
   float eta0, alpha, oma;
+  int ja;          // Taylor table: damping node of this pixel
+  float a0, da;    //   its damping and the offset a - a0
 };
 
 __device__ __forceinline__ void pix_setup(const float* M, const Consts& C, Pix& p) {
@@ -115,6 +118,10 @@ __device__ __forceinline__ void pix_setup(const float* M, const Consts& C, Pix& 
   p.eta0 = eta0;
   p.alpha = al;
   p.oma = 1.f - al;
+  const float ja = fminf(fmaxf(rintf(a * 20.f), 0.f), 99.f);
+  p.ja = (int)ja;
+  p.a0 = ja * 0.05f;
+  p.da = a - p.a0;
 }
 
 // Weideman's series for w(z), z = u + i a, a >= 0:
@@ -143,6 +150,62 @@ __device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C,
   F = fmaf(idr, qi, idi * qr);
 }
 
+// H and F from the Taylor table of Sect. 3.2 (Eqs. 10-13): nodes at
+// u = 0.05 i (i < 500), a = 0.05 j (j < 100), nearest node, first or second
+// order; H even and F odd in u.  Beyond the last node's cell in |u| the
+// asymptotic series w(z) ~ (i / sqrt(pi)) (1/z)(1 + 1/(2z^2) + 3/(4z^4) +
+// 15/(8z^6)) is used.  The damping node and offset are per pixel (Pix).
+constexpr int VT_NU = 500, VT_NA = 100;
+template <int ORDER>
+__device__ __forceinline__ void faddeeva_taylor(float u, const Pix& p, const Consts& C, float& H,
+                                                float& F) {
+  const float x = fabsf(u);
+  float Ht, Ft;
+  if (x < 24.975f) {
+    const float fi = rintf(x * 20.f);
+    const float u0 = fi * 0.05f;
+    const float2 n = C.vtab[p.ja * VT_NU + (int)fi];
+    const float h = n.x, f = n.y;
+    const float al = fmaf(2.f * p.a0, h, fmaf(2.f * u0, f, -TWO_OVER_SQRT_PI));
+    const float be = 2.f * fmaf(p.a0, f, -u0 * h);
+    const float du = x - u0, da = p.da;
+    Ht = fmaf(al, da, fmaf(be, du, h));
+    Ft = fmaf(be, da, fmaf(-al, du, f));
+    if (ORDER >= 2) {
+      const float P = fmaf(p.a0, al, fmaf(u0, be, h));
+      const float Q = fmaf(p.a0, be, fmaf(-u0, al, f));
+      const float d2 = fmaf(da, da, -du * du), dd = 2.f * da * du;
+      Ht = fmaf(P, d2, fmaf(Q, dd, Ht));
+      Ft = fmaf(Q, d2, fmaf(-P, dd, Ft));
+    }
+  } else {
+    const float a = p.a;
+    const float r = frcp(fmaf(x, x, a * a));
+    const float zr = x * r, zi = -a * r;  // 1/z
+    const float z2r = fmaf(zr, zr, -zi * zi), z2i = 2.f * zr * zi;
+    float sr = fmaf(z2r, 1.875f, 0.75f), si = z2i * 1.875f;
+    float tr = fmaf(sr, z2r, fmaf(-si, z2i, 0.5f)), ti = fmaf(sr, z2i, si * z2r);
+    sr = fmaf(tr, z2r, fmaf(-ti, z2i, 1.f));
+    si = fmaf(tr, z2i, ti * z2r);
+    const float wr = fmaf(sr, zr, -si * zi), wi = fmaf(sr, zi, si * zr);  // s / z
+    Ht = -INV_SQRT_PI * wi;  // w = (i / sqrt(pi)) (s / z)
+    Ft = INV_SQRT_PI * wr;
+  }
+  H = Ht;
+  F = u < 0.f ? -Ft : Ft;
+}
+
+// H and F by the evaluation the launch uses: 0 Weideman's series,
+// 1 or 2 the Taylor table at that order.
+template <int V>
+__device__ __forceinline__ void voigt_hf(float u, const Pix& p, const Consts& C, float& H,
+                                         float& F) {
+  if constexpr (V == 0)
+    faddeeva(u, p, C, H, F);
+  else
+    faddeeva_taylor<V>(u, p, C, H, F);
+}
+
 // Contributions of one synthesis point to the per-row accumulators
 // (all normalised by S1; magnetic Q, U in the psi = 0 frame):
 //   c[0] I_mix = alpha I_m + (1 - alpha) I_0,  c[1] I_m - I_0,
@@ -150,15 +213,15 @@ __device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C,
 //   c[5 + 4q + X], q in {B, gamma, v, Doppler width, a, eta0},
 //   X in {I_mix, Q0, U0, V}: derivatives up to per-pixel factors
 //   (B: C_Z/DlD, gamma: 1 per radian, v: -(lambda0/c)/DlD, DlD: -1/DlD).
-template <bool DERIV>
+template <bool DERIV, int V = 0>
 __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Consts& C,
                                               float* c) {
   const float up = fmaf(dl, p.invD, -p.vsi);
   const float ub = up + p.zs, ur = up - p.zs;
   float Hp, Fp, Hb, Fb, Hr, Fr;
-  faddeeva(up, p, C, Hp, Fp);
-  faddeeva(ub, p, C, Hb, Fb);
-  faddeeva(ur, p, C, Hr, Fr);
+  voigt_hf<V>(up, p, C, Hp, Fp);
+  voigt_hf<V>(ub, p, C, Hb, Fb);
+  voigt_hf<V>(ur, p, C, Hr, Fr);
 
   const float sH = 0.5f * (Hb + Hr), dHl = Hp - sH, dHv = Hr - Hb;
   const float sF = 0.5f * (Fb + Fr), dFl = Fp - sF, dFv = Fr - Fb;
@@ -278,7 +341,7 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
 }
 
 // Accumulate the filtered contributions of every synthesis point.
-template <int NOBS, bool DERIV>
+template <int NOBS, bool DERIV, int V = 0>
 __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, const Pix& p,
                                                  const Consts& C, float (&acc)[NOBS][NACC]) {
   constexpr int NC = DERIV ? NACC : 5;
@@ -289,7 +352,7 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   for (int k = 0; k < C.n_pts; ++k) {
     const Point P = load_uniform(pts, k);  // wave-uniform: scalar loads
     float c[NACC];
-    point_contrib<DERIV>(P.dl, p, C, c);
+    point_contrib<DERIV, V>(P.dl, p, C, c);
     const uint32_t mask = __float_as_uint(P.w[6]);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
@@ -307,7 +370,7 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
 // step, each lane selecting its own), then the pair adds its partial sums,
 // so both lanes hold the full sums.  Used when a launch has at least two
 // lanes per pixel: a pass then takes about half the time.
-template <int NOBS>
+template <int NOBS, int V = 0>
 __device__ __forceinline__ void synth_accumulate_pair(const Point* __restrict__ pts,
                                                       const Pix& p, const Consts& C,
                                                       float (&acc)[NOBS][NACC], bool odd) {
@@ -326,7 +389,7 @@ __device__ __forceinline__ void synth_accumulate_pair(const Point* __restrict__ 
       for (int i = 0; i < 7; ++i) P1.w[i] = 0.f;  // taps and mask zero: contributes nothing
     }
     float c[NACC];
-    point_contrib<true>(odd ? P1.dl : P0.dl, p, C, c);
+    point_contrib<true, V>(odd ? P1.dl : P0.dl, p, C, c);
     const uint32_t mask = __float_as_uint(P0.w[6]) | __float_as_uint(P1.w[6]);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {

@@ -42,7 +42,7 @@ def test_options_default_and_version():
     o = vf._Options()
     L.vfisv_options_default(ctypes.byref(o))
     assert (o.max_iter, o.eps0, o.eps_max, o.rel_tol, o.free_mask, o.grid_waves,
-            o.chunk_log2, o.lanes_per_pixel) == (50, 1e-3, 1e8, 1e-5, 0x3FF, 0, -1, 1)
+            o.chunk_log2, o.lanes_per_pixel, o.voigt) == (50, 1e-3, 1e8, 1e-5, 0x3FF, 0, -1, 1, 0)
     # the Python defaults are the library's
     d = vf.Options().c()
     assert all(getattr(d, f) == getattr(o, f) for f, _ in vf._Options._fields_)
@@ -57,6 +57,7 @@ def test_null_arguments_are_rejected():
     assert L.vfisv_invert(None, None, 0, None, None, 0, None, None, None, None, None, None,
                           None) == -1
     assert L.vfisv_synthesize(None, None, 0, None, None, None, None, None) == -1
+    assert L.vfisv_synthesize_voigt(None, None, 0, None, None, None, None, 0, None) == -1
     assert L.vfisv_solve(None, 0, None, None, None, 0, None, None, None) == -1
     assert L.vfisv_iter_histogram(None, 0, None, 1, None, None) == -1
     assert L.vfisv_autotune(None, None, 0, None, None, 0, None, 0, None, None) == -1

@@ -353,3 +353,40 @@ def test_lane_pairs_follow_the_oracle(ctx, hmi):
     assert np.mean(np.abs(gc - oc) / oc < 1e-4) > 0.4
     with pytest.raises(Exception):
         vf.invert(ctx, inst, o, Wd, opts=vf.Options(lanes_per_pixel=3))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_taylor_table_follows_the_oracle(ctx, hmi, order):
+    """Voigt by the Taylor table (Sect. 3.2, Eqs. 10-13): synthesis, start
+    chi^2 and the fit statistics against the oracle using the same table.
+    Where float32 and float64 round |u| to different nearest nodes (a cell
+    boundary, rare) the two sides use different expansions, so the largest
+    difference is bounded by the expansion's own error, the rest by float32
+    rounding."""
+    spec, inst, oi = hmi
+    ot = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter,
+                           voigt=order)
+    P = wl.draw_params(1024, 31).astype(np.float32)
+    S = vf.synthesize(ctx, inst, _dev(ctx, P), voigt=order).cpu().numpy()
+    Sr = oracle.forward_batch(ot, P.astype(np.float64))
+    d = np.abs(S - Sr)
+    assert np.quantile(d, 0.999) < 2e-6 and d.max() < (1e-3 if order == 1 else 1e-4), d.max()
+    # the table against the exact evaluation, on the GPU itself
+    S0 = vf.synthesize(ctx, inst, _dev(ctx, P)).cpu().numpy()
+    assert np.abs(S - S0).max() < (2e-3 if order == 1 else 1e-4)
+    n = 512
+    Pn, obs = _observations(ot, spec, n, 32)
+    W = wl.weights(spec.n_obs)
+    o, Wd = _dev(ctx, obs), _dev(ctx, W)
+    out0 = vf.invert(ctx, inst, o, Wd, opts=vf.Options(max_iter=0, voigt=order))
+    ref0 = oracle.invert(ot, obs, W, opts=oracle.Options(max_iter=0))
+    rel = np.abs(out0["chi2"].cpu().numpy() - ref0["chi2"]) / ref0["chi2"]
+    assert np.median(rel) < 2e-5 and np.quantile(rel, 0.99) < 2e-4
+    out = vf.invert(ctx, inst, o, Wd, opts=vf.Options(voigt=order))
+    ref = oracle.invert(ot, obs, W)
+    gc, gi = out["chi2"].cpu().numpy(), out["iters"].cpu().numpy()
+    a, b = np.median(gc), np.median(ref["chi2"])
+    assert abs(a - b) / b < 0.05, (a, b)
+    assert abs(gi.mean() - ref["iters"].mean()) / ref["iters"].mean() < 0.12
+    with pytest.raises(Exception):
+        vf.invert(ctx, inst, o, Wd, opts=vf.Options(voigt=3))
