@@ -30,7 +30,8 @@ class _Instrument(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
-                ("free_mask", ctypes.c_uint32)]
+                ("free_mask", ctypes.c_uint32), ("fixed_iters", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
 class _Counters(ctypes.Structure):
@@ -65,8 +66,13 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_default_init.argtypes = [_dp]
         L.orc_lm_pixel.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
-                                   _fp, _fp, _dp, _dp, _dp, _ip, _ip,
+                                   _fp, _fp, _dp, ctypes.c_int64, _dp, _dp, _ip, _ip,
                                    ctypes.POINTER(_Counters)]
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_restart_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int]
+        L.orc_restart_uniform.restype = ctypes.c_double
         L.orc_invert.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
                                  ctypes.c_int64, _fp, _fp, ctypes.c_int, _dp, _dp, _dp,
                                  _ip, _ip, ctypes.POINTER(_Counters), ctypes.c_int]
@@ -117,9 +123,13 @@ class Options:
     eps_max: float = 1e8
     rel_tol: float = 1e-5
     free_mask: int = 0x3FF
+    fixed_iters: int = 0
+    restarts: int = 0
+    seed: int = 0
 
     def c(self):
-        return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask)
+        return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
+                        self.fixed_iters, self.restarts, self.seed)
 
 
 def faddeeva(u, a):
@@ -139,6 +149,15 @@ def voigt_taylor(order, u, a):
     F = np.empty_like(u)
     lib().orc_voigt_taylor_batch(int(order), u.size, _d(u), _d(a), _d(H), _d(F))
     return H, F
+
+
+def splitmix64(seed, c):
+    """Output number c (from 0) of the SplitMix64 stream seeded with seed."""
+    return int(lib().orc_splitmix64(seed, c))
+
+
+def restart_uniform(seed, pixel, k, p):
+    return float(lib().orc_restart_uniform(seed, pixel, k, p))
 
 
 def voigt_table_node(i, j):
@@ -202,7 +221,7 @@ def default_init():
     return M
 
 
-def lm_pixel(inst, obs, W, M0=None, opts=None):
+def lm_pixel(inst, obs, W, M0=None, opts=None, pixel=0):
     opts = opts or Options()
     obs = np.ascontiguousarray(obs, dtype=np.float32)
     W = np.ascontiguousarray(W, dtype=np.float32)
@@ -214,7 +233,8 @@ def lm_pixel(inst, obs, W, M0=None, opts=None):
     cnt = _Counters()
     o = opts.c()
     lib().orc_lm_pixel(ctypes.byref(inst.c), ctypes.byref(o), _f(obs), _f(W),
-                       _d(M0c) if M0c is not None else None, _d(M), _d(chi2), _i(it),
+                       _d(M0c) if M0c is not None else None, int(pixel), _d(M), _d(chi2),
+                       _i(it),
                        _i(st), ctypes.byref(cnt))
     return dict(params=M, chi2=float(chi2[0]), iters=int(it[0]), status=int(st[0]),
                 counters=dict(trials=cnt.trials, derivs=cnt.derivs, solves=cnt.solves,

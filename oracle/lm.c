@@ -220,8 +220,114 @@ static double chi2_and_normal(int rows, const float *obs, const float *W, const 
   return chi / dof;
 }
 
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c) {
+  /* state after c + 1 increments by the golden gamma, then the mix */
+  uint64_t z = seed + (c + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double orc_restart_uniform(uint64_t seed, int64_t pixel, int k, int p) {
+  const uint64_t c = ((uint64_t)pixel << 16) | ((uint64_t)(k & 0xFFF) << 4) | (uint64_t)(p & 15);
+  return (double)(orc_splitmix64(seed, c) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Half-widths of the synthetic priors: the scale of restart perturbations. */
+static const double RESTART_HALF[NP] = {1500.0, 90.0, 90.0, 3.0, 15.0, 0.25, 14.5, 0.2, 0.2, 0.4};
+
+/* The paper's scheme (Sect. 4.2): a fixed number of trials; a restart from
+ * the best model seen, its free parameters perturbed by uniform offsets of
+ * up to 0.1 k prior half-widths on restart k (the damping carries over),
+ * when (a) after the first 10 trials chi^2 has not fallen by a
+ * factor 10 from its first value, or (b) 5 trials in a row brought no
+ * improvement (or the damping passed eps_max).  A restart's evaluation is
+ * itself a trial, so every pixel runs exactly fixed_iters trials unless it
+ * stalls with no restart left. */
+static void lm_pixel_fixed(const orc_instrument *inst, const orc_options *opt,
+                           const float *obs, const float *W, const double *M0, int64_t pixel,
+                           double *M_out, double *chi2_out, int32_t *iters_out,
+                           int32_t *status_out, orc_counters *cnt, int rows, double dof) {
+  double M[NP], Mt[NP], Mg[NP], delta[NP], H[NP * NP], g[NP];
+  double *S = (double *)malloc(sizeof(double) * rows);
+  double *J = (double *)malloc(sizeof(double) * rows * NP);
+  if (M0) memcpy(M, M0, sizeof M);
+  else orc_default_init(M);
+  orc_project(M);
+  orc_forward(inst, M, S, J);
+  cnt->derivs++;
+  double chi2 = chi2_and_normal(rows, obs, W, S, J, dof, H, g);
+  const double chi2_first = chi2;
+  memcpy(Mg, M, sizeof M);
+  double chig = chi2;
+  double eps = opt->eps0;
+  int status = ORC_MAX_ITER, it = 0, bad = 0, k = 0, pending = 0;
+  if (!isfinite(chi2)) status = ORC_NONFINITE;
+  while (status != ORC_NONFINITE && it < opt->fixed_iters) {
+    ++it;
+    if (pending) {  /* restart: evaluate the perturbed best model */
+      ++k;
+      for (int p = 0; p < NP; ++p)  /* frozen parameters keep their value */
+        M[p] = ((opt->free_mask >> p) & 1u)
+                   ? Mg[p] + (2.0 * orc_restart_uniform(opt->seed, pixel, k, p) - 1.0) * 0.1 *
+                                 k * RESTART_HALF[p]
+                   : Mg[p];
+      orc_project(M);
+      orc_forward(inst, M, S, J);
+      cnt->derivs++;
+      cnt->trials++;
+      chi2 = chi2_and_normal(rows, obs, W, S, J, dof, H, g);
+      if (isfinite(chi2) && chi2 < chig) {
+        memcpy(Mg, M, sizeof M);
+        chig = chi2;
+      }
+      bad = 0;
+      pending = 0;
+      continue;
+    }
+    const int sres = orc_solve(H, g, eps, opt->free_mask, delta);
+    cnt->solves++;
+    if (sres == 1) cnt->svd_fallbacks++;
+    for (int p = 0; p < NP; ++p) Mt[p] = M[p] + delta[p];
+    orc_project(Mt);
+    orc_forward(inst, Mt, S, NULL);
+    cnt->trials++;
+    const double chi2_t = chi2_and_normal(rows, obs, W, S, NULL, dof, NULL, NULL);
+    if (isfinite(chi2_t) && chi2_t < chi2) {
+      memcpy(M, Mt, sizeof M);
+      chi2 = chi2_t;
+      orc_forward(inst, M, S, J);
+      cnt->derivs++;
+      chi2_and_normal(rows, obs, W, S, J, dof, H, g);
+      eps = orc_eps_decrease(eps);
+      bad = 0;
+      if (chi2 < chig) {
+        memcpy(Mg, M, sizeof M);
+        chig = chi2;
+      }
+    } else {
+      eps = orc_eps_increase(eps);
+      ++bad;
+    }
+    const int stalled = eps > opt->eps_max;
+    if (k < opt->restarts &&
+        ((it == 10 && !(chig <= chi2_first / 10.0)) || bad >= 5 || stalled)) {
+      pending = 1;
+    } else if (stalled) {
+      status = ORC_STALLED;
+      break;
+    }
+  }
+  memcpy(M_out, Mg, sizeof Mg);
+  *chi2_out = chig;
+  *iters_out = it;
+  *status_out = status | (k << 8);
+  free(S);
+  free(J);
+}
+
 void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
-                  const float *obs, const float *W, const double *M0,
+                  const float *obs, const float *W, const double *M0, int64_t pixel,
                   double *M_out, double *chi2_out, int32_t *iters_out,
                   int32_t *status_out, orc_counters *cnt) {
   const int rows = 4 * inst->n_obs;
@@ -234,6 +340,11 @@ void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
       *status_out = ORC_NONFINITE;
       return;
     }
+  if (opt->fixed_iters > 0) {
+    lm_pixel_fixed(inst, opt, obs, W, M0, pixel, M_out, chi2_out, iters_out, status_out, cnt,
+                   rows, dof);
+    return;
+  }
 
   double M[NP], Mt[NP], delta[NP], H[NP * NP], g[NP];
   double *S = (double *)malloc(sizeof(double) * rows);
@@ -327,7 +438,7 @@ static void *invert_worker(void *p) {
     for (int64_t i = start; i < end; ++i) {
       const float *w = jb->W_per_pixel ? jb->W + i * rows : jb->W;
       orc_lm_pixel(jb->inst, jb->opt, jb->stokes + i * rows, w,
-                   jb->init ? jb->init + i * NP : NULL, jb->params + i * NP,
+                   jb->init ? jb->init + i * NP : NULL, i, jb->params + i * NP,
                    &jb->chi2[i], &jb->iters[i], &jb->status[i], cnt);
     }
   }

@@ -57,6 +57,13 @@ typedef struct {
   double eps_max;      /* damping above which the pixel is declared stalled */
   double rel_tol;      /* relative chi^2 decrease that ends the fit */
   uint32_t free_mask;  /* bit p set: parameter p is free */
+  int fixed_iters;     /* > 0: the paper's scheme (Sect. 4.2): exactly this
+                          many trials per pixel, no exit on convergence, the
+                          best model seen is the result */
+  int restarts;        /* with fixed_iters: restarts from a perturbed best
+                          model allowed per pixel (triggers (a) and (b) of
+                          Sect. 4.2) */
+  uint64_t seed;       /* key of the restart perturbations */
 } orc_options;
 
 typedef struct {
@@ -115,11 +122,20 @@ void orc_default_init(double *M);
 
 /* One pixel: Levenberg-Marquardt from M0.
  * obs: [4][n_obs] (float, promoted); W: [4][n_obs] weights w^2/sigma^2.
- * M0 may be NULL (default model). */
+ * M0 may be NULL (default model).  pixel keys the restart perturbations.
+ * In the fixed-iteration mode the status word carries the restarts used in
+ * bits 8..15. */
 void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
-                  const float *obs, const float *W, const double *M0,
+                  const float *obs, const float *W, const double *M0, int64_t pixel,
                   double *M_out, double *chi2_out, int32_t *iters_out,
                   int32_t *status_out, orc_counters *cnt);
+
+/* SplitMix64 (Steele, Lea and Flood 2014) used as a counter-based
+ * generator: the c-th output (c >= 0) of the stream seeded with seed. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t c);
+/* Uniform in [0, 1) for restart k of a pixel and parameter p: output number
+ * (pixel << 16 | k << 4 | p) of the stream, top 53 bits. */
+double orc_restart_uniform(uint64_t seed, int64_t pixel, int k, int p);
 
 /* Batch over pixels with a pool of nthreads (<=0: all hardware threads).
  * stokes: [n][4][n_obs]; W: [4][n_obs] or [n][4][n_obs] if W_per_pixel;
