@@ -118,6 +118,24 @@ typedef struct {
                        /* by the library on first use: a synchronising     */
                        /* allocation) at first or second order.  HMI-shaped */
                        /* instruments only; not in vfisv_invert_batches.     */
+  int fixed_iters;     /* 0 (default): exits on convergence, stall or        */
+                       /* max_iter.  > 0: the paper's scheme (Sect. 4.2):    */
+                       /* exactly fixed_iters trials per pixel (fewer only if */
+                       /* it stalls with no restart left), the best model   */
+                       /* seen is returned, status carries the restarts     */
+                       /* used in bits 8..15.  vfisv_invert only.            */
+  int restarts;        /* with fixed_iters: restarts per pixel (default 0).  */
+                       /* A restart, due when (a) after 10 trials chi^2 is   */
+                       /* not 10x below its first value or (b) 5 trials in a */
+                       /* row failed (or the damping passed eps_max),       */
+                       /* moves each free parameter of the best model by a  */
+                       /* uniform offset of up to 0.1 k prior half-widths   */
+                       /* (restart k; B 1500 G, angles 90, v 3, Doppler     */
+                       /* width 15, a 0.25, eta0 14.5, S0 0.2, S1 0.2,      */
+                       /* alpha 0.4); its evaluation counts as a trial and  */
+                       /* the damping carries over.                          */
+  uint64_t restart_seed; /* offsets: SplitMix64 output (pixel << 16 | k << 4 */
+                       /* | parameter) of the stream seeded with this value */
 } vfisv_options;
 
 /* Result of vfisv_autotune. */

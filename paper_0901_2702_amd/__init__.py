@@ -44,7 +44,8 @@ class _Options(ctypes.Structure):
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
                 ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int),
                 ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int),
-                ("voigt", ctypes.c_int)]
+                ("voigt", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("restart_seed", ctypes.c_uint64)]
 
 
 class _Batch(ctypes.Structure):
@@ -226,10 +227,14 @@ class Options:
     chunk_log2: int = -1
     lanes_per_pixel: int = 1
     voigt: int = 0
+    fixed_iters: int = 0
+    restarts: int = 0
+    restart_seed: int = 0
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
-                        self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt)
+                        self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt,
+                        self.fixed_iters, self.restarts, self.restart_seed)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):

@@ -61,6 +61,10 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   if (o.lanes_per_pixel != 1 && o.lanes_per_pixel != 2)
     return fail(ctx, VFISV_E_INVALID, "options: lanes_per_pixel must be 1 or 2");
   if (o.voigt < 0 || o.voigt > 2) return fail(ctx, VFISV_E_INVALID, "options: voigt must be 0, 1 or 2");
+  if (o.fixed_iters < 0 || o.fixed_iters > 100000)
+    return fail(ctx, VFISV_E_INVALID, "options: fixed_iters outside 0..100000");
+  if (o.restarts < 0 || o.restarts > 4095)
+    return fail(ctx, VFISV_E_INVALID, "options: restarts outside 0..4095");
   if (o.voigt != 0 && inst->kind != KIND_DENSE6)
     return fail(ctx, VFISV_E_UNSUPPORTED, "options: the Taylor table serves HMI-shaped instruments");
   if (o.voigt != 0) {
@@ -112,6 +116,9 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.free_mask = o.free_mask & 0x3FFu;
   const vfisv_ctx::Tuned& t = ctx->tuned[inst->kind];
   a.chunk_log2 = o.chunk_log2 >= 0 ? o.chunk_log2 : (t.valid ? t.chunk_log2 : 8);
+  a.fixed_iters = o.fixed_iters;
+  a.restarts = o.restarts;
+  a.seed = (unsigned long long)o.restart_seed;
 }
 
 static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, int kind) {
@@ -302,6 +309,9 @@ void vfisv_options_default(vfisv_options* o) {
   o->chunk_log2 = -1;
   o->lanes_per_pixel = 1;
   o->voigt = 0;
+  o->fixed_iters = 0;
+  o->restarts = 0;
+  o->restart_seed = 0;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -564,6 +574,8 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
       return fail(ctx, VFISV_E_INVALID, "invert_batches: n must be in 0 .. 2^31 - 1");
     if (o.voigt != 0)
       return fail(ctx, VFISV_E_UNSUPPORTED, "invert_batches: the Taylor table is not served here");
+    if (o.fixed_iters != 0)
+      return fail(ctx, VFISV_E_UNSUPPORTED, "invert_batches: the fixed-iteration scheme is not served here");
     if (b.n > 0 && (!b.stokes || !b.W || !b.params || !b.chi2 || !b.iters))
       return fail(ctx, VFISV_E_INVALID, "invert_batches: NULL buffer");
     fill_lm_args(ctx, b.inst, b.n, nullptr, nullptr, b.stokes, b.W, b.W_per_pixel, b.init, o,

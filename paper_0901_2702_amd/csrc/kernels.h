@@ -48,6 +48,9 @@ struct LMArgs {
   int qbase;       // first of this batch's NQ queue-head slots in work[]
   int lpp_max;     // 2: dense pixels may use a pair of lanes when the grid has
                    // at least two lanes per pixel, else 1
+  int fixed_iters;  // > 0: fixed-iteration scheme with restarts (else 0)
+  int restarts;     // restarts allowed per pixel in that scheme
+  unsigned long long seed;  // key of the restart perturbations
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:

@@ -40,6 +40,26 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
+// SplitMix64 (Steele, Lea and Flood 2014) as a counter-based generator:
+// output number c of the stream seeded with seed.  Restart k of a pixel draws
+// parameter q from output (pixel << 16 | k << 4 | q), top 53 bits.
+__device__ __forceinline__ double restart_uniform(unsigned long long seed, int64_t pix, int k,
+                                                  int q) {
+  const unsigned long long c = ((unsigned long long)pix << 16) |
+                               ((unsigned long long)(k & 0xFFF) << 4) | (unsigned long long)q;
+  unsigned long long z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Scale of restart perturbations: half-widths of the synthetic priors.
+__device__ __forceinline__ double restart_half(int q) {
+  constexpr double h[NPAR] = {1500.0, 90.0, 90.0, 3.0, 15.0, 0.25, 14.5, 0.2, 0.2, 0.4};
+  return h[q];
+}
+
 struct WaveCounters {
   unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0;
 };
@@ -166,7 +186,10 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // the pair's leader (it takes queue positions, writes the results and counts
 // the work), the odd lane mirrors its state: both see the same inputs and
 // the same pair sums, so they take the same decisions.
-template <int NOBS, int LPP, int V = 0>
+// PAPER: the fixed-iteration scheme of Sect. 4.2 (A.fixed_iters trials per
+// pixel, restarts from a perturbed best model, the best model seen is the
+// result); otherwise exits on convergence, stall or A.max_iter.
+template <int NOBS, int LPP, int V = 0, bool PAPER = false>
 __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, int64_t glane,
                                         WaveCounters& wc) {
   static_assert(LPP == 1 || (LPP == 2 && NOBS > 0), "lane pairs serve the dense layout");
@@ -190,6 +213,13 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
   float Mb[NPAR], Mc[NPAR];
   double chib = 0.0, eps = 0.0;
   int it = 0;
+  // fixed-iteration scheme: best model seen, first chi^2, failed trials in
+  // a row, restarts used, restart due / being evaluated
+  float Mg[NPAR];
+  double chig = 0.0, chi_first = 0.0;
+  int bad = 0, kr = 0;
+  bool pending = false, restart_eval = false;
+  const int limit = PAPER ? A.fixed_iters : A.max_iter;
 
   for (;;) {
     // ---- refill lanes whose pixel finished --------------------------------
@@ -256,6 +286,10 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
           fresh = true;
           eps = A.eps0;
           it = 0;
+          bad = 0;
+          kr = 0;
+          pending = false;
+          restart_eval = false;
         }
       }
       nm &= ~__ballot(take);
@@ -276,10 +310,28 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
     if (fresh) {
-      if (!isfinite(chi)) done = 3;
+      if (!isfinite(chi) && !restart_eval) done = 3;
 #pragma unroll
       for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
       chib = chi;
+      if constexpr (PAPER) {
+        if (restart_eval) {  // the restart's evaluation is a trial
+          ++it;
+          if (leader) ++wc.trial;
+          if (isfinite(chi) && chi < chig) {
+#pragma unroll
+            for (int q = 0; q < NPAR; ++q) Mg[q] = Mc[q];
+            chig = chi;
+          }
+          bad = 0;
+          restart_eval = false;
+        } else {
+          chi_first = chi;
+          chig = chi;
+#pragma unroll
+          for (int q = 0; q < NPAR; ++q) Mg[q] = Mc[q];
+        }
+      }
     } else {
       ++it;
       if (leader) ++wc.trial;
@@ -290,25 +342,61 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
         chib = chi;
         eps = eps_down(eps);
         if (leader) ++wc.acc;
-        if (dec < A.rel_tol * (chi + dec)) done = 0;
+        if constexpr (PAPER) {
+          bad = 0;
+          if (chi < chig) {
+#pragma unroll
+            for (int q = 0; q < NPAR; ++q) Mg[q] = Mc[q];
+            chig = chi;
+          }
+        } else {
+          if (dec < A.rel_tol * (chi + dec)) done = 0;
+        }
       } else {
         eps = eps_up(eps);
-        if (eps > A.eps_max) done = 2;
+        if constexpr (PAPER) ++bad;
+        else if (eps > A.eps_max) done = 2;
+      }
+      if constexpr (PAPER) {
+        // restart triggers: (a) after 10 trials chi^2 not down tenfold from
+        // its first value, (b) 5 failed trials in a row, or a stall
+        const bool stalled = eps > A.eps_max;
+        if (kr < A.restarts && ((it == 10 && !(chig <= chi_first / 10.0)) || bad >= 5 || stalled))
+          pending = true;
+        else if (stalled)
+          done = 2;
       }
     }
     fresh = false;
-    if (done < 0 && it >= A.max_iter) done = 1;
+    if (done < 0 && it >= limit) done = 1;
 
     if (done >= 0) {
       if (leader) {
 #pragma unroll
-        for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = Mb[q];
-        A.chi2[pix] = chib;
+        for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = PAPER ? Mg[q] : Mb[q];
+        A.chi2[pix] = PAPER ? chig : chib;
         A.iters[pix] = it;
-        if (A.status) A.status[pix] = done;
+        if (A.status) A.status[pix] = PAPER ? (done | (kr << 8)) : done;
         ++wc.pix;
       }
       live = false;
+    } else if (PAPER && pending) {
+      // ---- restart: the best model's free parameters, perturbed -----------
+      ++kr;
+      double Mt[NPAR];
+#pragma unroll
+      for (int q = 0; q < NPAR; ++q) {
+        const double u = restart_uniform(A.seed, pix, kr, q);
+        Mt[q] = ((A.free_mask >> q) & 1u)
+                    ? (double)Mg[q] + (2.0 * u - 1.0) * 0.1 * kr * restart_half(q)
+                    : (double)Mg[q];
+      }
+      project(Mt);
+#pragma unroll
+      for (int q = 0; q < NPAR; ++q) Mc[q] = (float)Mt[q];
+      fresh = true;
+      restart_eval = true;
+      pending = false;
     } else {
       // ---- damped float64 step from the best model ------------------------
       float H[55], g[NPAR];
@@ -352,7 +440,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
 }
 
 // V: Voigt evaluation (0 Weideman's series, 1/2 Taylor table; dense only).
-template <int NOBS, int V>
+template <int NOBS, int V, bool PAPER>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
   const int lane = threadIdx.x;
@@ -361,11 +449,11 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   if constexpr (NOBS > 0) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
     if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)gridDim.x * 64ull)
-      lm_loop<NOBS, 2, V>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 2, V, PAPER>(A, sHG, lane, glane, wc);
     else
-      lm_loop<NOBS, 1, V>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 1, V, PAPER>(A, sHG, lane, glane, wc);
   } else {
-    lm_loop<NOBS, 1, V>(A, sHG, lane, glane, wc);
+    lm_loop<NOBS, 1, V, PAPER>(A, sHG, lane, glane, wc);
   }
   flush_counters(A.work, wc, lane);
 }
@@ -511,11 +599,17 @@ hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <bool PAPER>
+static void launch_lm_mode(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s) {
+  if (kind != KIND_DENSE6) lm_kernel<0, 0, PAPER><<<grid, 64, 0, s>>>(a);
+  else if (voigt == 1) lm_kernel<NOBS_HMI, 1, PAPER><<<grid, 64, 0, s>>>(a);
+  else if (voigt == 2) lm_kernel<NOBS_HMI, 2, PAPER><<<grid, 64, 0, s>>>(a);
+  else lm_kernel<NOBS_HMI, 0, PAPER><<<grid, 64, 0, s>>>(a);
+}
+
 hipError_t launch_lm(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s) {
-  if (kind != KIND_DENSE6) lm_kernel<0, 0><<<grid, 64, 0, s>>>(a);
-  else if (voigt == 1) lm_kernel<NOBS_HMI, 1><<<grid, 64, 0, s>>>(a);
-  else if (voigt == 2) lm_kernel<NOBS_HMI, 2><<<grid, 64, 0, s>>>(a);
-  else lm_kernel<NOBS_HMI, 0><<<grid, 64, 0, s>>>(a);
+  if (a.fixed_iters > 0) launch_lm_mode<true>(a, kind, voigt, grid, s);
+  else launch_lm_mode<false>(a, kind, voigt, grid, s);
   return hipGetLastError();
 }
 
@@ -550,7 +644,7 @@ hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s) {
 }
 
 hipError_t lm_blocks_per_cu(int* out) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_kernel<NOBS_HMI, 0>, 64, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_kernel<NOBS_HMI, 0, false>, 64, 0);
 }
 
 hipError_t band_blocks_per_cu(int* out) {

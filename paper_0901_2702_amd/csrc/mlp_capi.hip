@@ -416,6 +416,8 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
   double inv_dof;
   rc = check_options(ctx, inst, opt, &o, &inv_dof);
   if (rc) return rc;
+  if (o.fixed_iters != 0)
+    return fail(ctx, VFISV_E_UNSUPPORTED, "invert_learned: the fixed-iteration scheme is not served here");
   if (learned_max_iter < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: learned_max_iter < 0");
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: n < 0");
   if (n == 0) return VFISV_OK;

@@ -390,3 +390,53 @@ def test_taylor_table_follows_the_oracle(ctx, hmi, order):
     assert abs(gi.mean() - ref["iters"].mean()) / ref["iters"].mean() < 0.12
     with pytest.raises(Exception):
         vf.invert(ctx, inst, o, Wd, opts=vf.Options(voigt=3))
+
+
+def test_fixed_iterations_with_restarts_follow_the_oracle(ctx, hmi):
+    """The fixed-iteration scheme with restarts (Sect. 4.2)."""
+    spec, inst, oi = hmi
+    n = 256
+    P, obs = _observations(oi, spec, n, 51)
+    W = wl.weights(spec.n_obs)
+    o, Wd = _dev(ctx, obs), _dev(ctx, W)
+    # restart timing, integer-exact: with nothing free every trial fails
+    for fixed in (5, 6, 11, 17, 40):
+        out = vf.invert(ctx, inst, o, Wd, opts=vf.Options(fixed_iters=fixed, restarts=3,
+                                                          restart_seed=3, free_mask=0))
+        ref = oracle.invert(oi, obs, W, opts=oracle.Options(fixed_iters=fixed, restarts=3, seed=3,
+                                                           free_mask=0))
+        np.testing.assert_array_equal(out["status"].cpu().numpy(), ref["status"])
+        np.testing.assert_array_equal(out["iters"].cpu().numpy(), ref["iters"])
+        c = ctx.counters()
+        assert c["trials"] == ref["iters"].sum() and c["passes"] == c["trials"] + n
+    # without restarts: LM without its convergence exit, bit for bit
+    a = vf.invert(ctx, inst, o, Wd, opts=vf.Options(fixed_iters=30))
+    b = vf.invert(ctx, inst, o, Wd, opts=vf.Options(max_iter=30, rel_tol=0.0))
+    for k in ("params", "chi2", "iters", "status"):
+        assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), k
+    # with restarts from starts near the truth: the oracle's statistics
+    rng = np.random.default_rng(52)
+    near = (P + rng.normal(size=P.shape) * [100, 10, 10, 0.3, 3, 0.05, 2, 0.03, 0.03, 0.05])
+    near = np.array([oracle.project(m) for m in near]).astype(np.float32)
+    opt = vf.Options(fixed_iters=30, restarts=3, restart_seed=5)
+    g1 = vf.invert(ctx, inst, o, Wd, init=_dev(ctx, near), opts=opt)
+    g2 = vf.invert(ctx, inst, o, Wd, init=_dev(ctx, near), opts=opt)
+    for k in g1:
+        assert np.array_equal(g1[k].cpu().numpy(), g2[k].cpu().numpy()), k
+    ref = oracle.invert(oi, obs, W, init=near.astype(np.float64),
+                        opts=oracle.Options(fixed_iters=30, restarts=3, seed=5))
+    gc, gs = g1["chi2"].cpu().numpy(), g1["status"].cpu().numpy()
+    gi = g1["iters"].cpu().numpy()
+    assert ((gi == 30) | ((gs & 255) == 2)).all()
+    a, b = np.median(gc), np.median(ref["chi2"])
+    print("[gpu] fixed 30 + restarts: median chi2 %.4f vs %.4f, restarts used %.2f vs %.2f"
+          % (a, b, (gs >> 8).mean(), (ref["status"] >> 8).mean()), flush=True)
+    assert abs(a - b) / b < 0.05
+    assert abs((gs >> 8).mean() - (ref["status"] >> 8).mean()) < 0.3
+    assert np.mean(np.abs(gc - ref["chi2"]) / ref["chi2"] < 1e-3) > 0.5
+    # another seed moves the restarted pixels only
+    g3 = vf.invert(ctx, inst, o, Wd, init=_dev(ctx, near),
+                   opts=vf.Options(fixed_iters=30, restarts=3, restart_seed=6))
+    restarted = (gs >> 8) > 0
+    assert not np.array_equal(g3["params"].cpu().numpy()[restarted],
+                              g1["params"].cpu().numpy()[restarted])
