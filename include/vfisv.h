@@ -278,6 +278,24 @@ int vfisv_autotune(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                    const vfisv_options *opt, int64_t sample, vfisv_tuning *out,
                    void *stream);
 
+/* Classical initial guess (Sect. 5: magnetograph / weak-field B and gamma,
+ * Jefferies & Mickey 1991; azimuth from the linear polarisation, Auer et
+ * al. 1977; velocity from the line position), per pixel from its observed
+ * samples at the centroids of the instrument's filter rows:
+ *   I_c = max I; v = c * (centre of gravity of I_c - I) / lambda0;
+ *   B_par = -sum V I' / (C_Z sum I'^2); B_perp^2 = 4 sum |Q+iU| |I''| /
+ *   (C_Z^2 sum I''^2); 2 psi = atan2(sum U I'', sum Q I'');
+ * I', I'' finite differences across the samples; B and gamma from
+ * B_par / 0.6 and B_perp / sqrt(0.6) (default filling factor 0.6); Doppler
+ * width, damping, eta0 and alpha from the default model; S0, S1 = 0.3 I_c,
+ * 0.7 I_c; then the box.  A vanishing sum gives 0 for its estimate; a pixel
+ * with non-finite samples gets the default model.
+ *   stokes: dev [n][4][n_obs]; params: dev [n][10] (usable as vfisv_invert's
+ *   init); pol: dev [n] polarisation level max sqrt(Q^2+U^2+V^2) / I_c, or
+ *   NULL.  Needs n_obs >= 3.  Asynchronous on stream. */
+int vfisv_init_classical(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                         const float *stokes, float *params, float *pol, void *stream);
+
 /* Work counters of the most recent vfisv_invert or vfisv_invert_batches
  * (synchronises the context's device). */
 int vfisv_get_counters(vfisv_ctx *ctx, vfisv_counters *out);

@@ -26,6 +26,8 @@ per pixel, on the observed samples:
   S0, S1 = 0.3 I_c, 0.7 I_c; then the box projection.
 * polarisation level: max_k sqrt(Q_k^2 + U_k^2 + V_k^2) / I_c (the paper
   switches between methods at 6%).
+* where a denominator vanishes (no depression, no slope or no curvature of
+  I) the corresponding estimate is 0.
 """
 import numpy as np
 
@@ -65,13 +67,19 @@ def classical_init(obs, x_mA, lambda0_A, cz_mA_per_G, default_model, project):
     x = np.asarray(x_mA, dtype=np.float64)
     Ic = I.max(axis=1)
     d = Ic[:, None] - I
-    lam_cog = (d * x).sum(axis=1) / d.sum(axis=1)
+
+    def ratio(num, den):
+        out = np.zeros_like(num)
+        np.divide(num, den, out=out, where=den != 0.0)
+        return out
+
+    lam_cog = ratio((d * x).sum(axis=1), d.sum(axis=1))
     v = C_KMS * lam_cog / (lambda0_A * 1000.0)
     Ip = _d1(I, x)
     Ipp = _d2(I, x)
-    b_par = -(V * Ip).sum(axis=1) / (cz_mA_per_G * (Ip * Ip).sum(axis=1))
+    b_par = -ratio((V * Ip).sum(axis=1), cz_mA_per_G * (Ip * Ip).sum(axis=1))
     L = np.sqrt(Q * Q + U * U)
-    b_perp2 = 4.0 * (L * np.abs(Ipp)).sum(axis=1) / (cz_mA_per_G ** 2 * (Ipp * Ipp).sum(axis=1))
+    b_perp2 = 4.0 * ratio((L * np.abs(Ipp)).sum(axis=1), cz_mA_per_G ** 2 * (Ipp * Ipp).sum(axis=1))
     b_perp = np.sqrt(np.maximum(b_perp2, 0.0))
     psi = 0.5 * np.degrees(np.arctan2((U * Ipp).sum(axis=1), (Q * Ipp).sum(axis=1)))
     bl = b_par / ALPHA0

@@ -76,7 +76,8 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
-           "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt")
+           "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
+           "vfisv_init_classical")
 
 _LIB = None
 
@@ -111,6 +112,7 @@ def lib():
                                            ctypes.POINTER(ctypes.c_int64), _vp]
         L.vfisv_invert_batches.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.c_int,
                                            ctypes.POINTER(_Options), _vp]
+        L.vfisv_init_classical.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.vfisv_autotune.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
                                      ctypes.POINTER(_Options), ctypes.c_int64,
                                      ctypes.POINTER(_Tuning), _vp]
@@ -314,6 +316,21 @@ def invert_batches(ctx, batches, opts=None):
     ctx._check(lib().vfisv_invert_batches(ctx._h, arr, len(batches), ctypes.byref(o),
                                           _stream(dev)), "vfisv_invert_batches")
     return outs
+
+
+def init_classical(ctx, inst, stokes):
+    """Classical starting models [n, 10] (weak field, azimuth, line
+    position) and polarisation levels [n] for stokes [n, 4, n_obs]."""
+    dev = ctx.device
+    n = stokes.shape[0]
+    params = torch.empty((n, NPAR), device=dev, dtype=torch.float32)
+    pol = torch.empty(n, device=dev, dtype=torch.float32)
+    ctx._check(lib().vfisv_init_classical(ctx._h, inst._h, n,
+                                          _ptr(stokes, torch.float32, dev, name="stokes"),
+                                          _ptr(params, torch.float32, dev),
+                                          _ptr(pol, torch.float32, dev), _stream(dev)),
+               "vfisv_init_classical")
+    return params, pol
 
 
 def autotune(ctx, inst, stokes, W, opts=None, sample=0):

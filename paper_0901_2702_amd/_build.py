@@ -6,8 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvfisv.so")
-SOURCES = ["kernels.hip", "capi.hip", "mlp.hip", "mlp_capi.hip"]
-HEADERS = ["me_device.h", "kernels.h", "mlp.h", "capi_internal.h"]
+SOURCES = ["kernels.hip", "capi.hip", "mlp.hip", "mlp_capi.hip", "classical.hip"]
+HEADERS = ["me_device.h", "kernels.h", "mlp.h", "capi_internal.h", "classical.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

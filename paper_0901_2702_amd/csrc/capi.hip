@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "capi_internal.h"
+#include "classical.h"
 #include "kernels.h"
 #include "vfisv.h"
 
@@ -447,6 +448,24 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     delete inst;
     return hip_fail(ctx, e, "hipSetDevice");
   }
+  // observed wavelength of each sample: the centroid of its filter row
+  std::vector<float> obs_x((size_t)no);
+  for (int i = 0; i < no; ++i) {
+    double sw = 0.0, swx = 0.0;
+    for (int k = 0; k < nf; ++k) {
+      sw += d->filter[(size_t)i * nf + k];
+      swx += d->filter[(size_t)i * nf + k] * d->fine_offset_mA[k];
+    }
+    obs_x[(size_t)i] = sw > 0.0 ? (float)(swx / sw) : 0.f;
+  }
+  e = hipMalloc(&inst->d_obs_x, sizeof(float) * (size_t)no);
+  if (e == hipSuccess)
+    e = hipMemcpy(inst->d_obs_x, obs_x.data(), sizeof(float) * (size_t)no, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (inst->d_obs_x) hipFree(inst->d_obs_x);
+    delete inst;
+    return hip_fail(ctx, e, "instrument_create: sample table");
+  }
   if (inst->kind == KIND_DENSE6) {
     const size_t bytes = sizeof(Point) * (pts.empty() ? 1 : pts.size());
     e = hipMalloc(&inst->d_pts, bytes);
@@ -466,6 +485,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     if (inst->d_pts) hipFree(inst->d_pts);
     if (inst->d_blocks) hipFree(inst->d_blocks);
     if (inst->d_row_sums) hipFree(inst->d_row_sums);
+    hipFree(inst->d_obs_x);
     delete inst;
     return hip_fail(ctx, e, "instrument_create: device tables");
   }
@@ -486,6 +506,7 @@ int vfisv_instrument_destroy(vfisv_instrument* inst) {
   if (inst->d_pts) hipFree(inst->d_pts);
   if (inst->d_blocks) hipFree(inst->d_blocks);
   if (inst->d_row_sums) hipFree(inst->d_row_sums);
+  if (inst->d_obs_x) hipFree(inst->d_obs_x);
   delete inst;
   return VFISV_OK;
 }
@@ -677,6 +698,34 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   t.grid_waves = best.grid_waves;
   t.chunk_log2 = best.chunk_log2;
   if (out) *out = best;
+  return VFISV_OK;
+}
+
+int vfisv_init_classical(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                         const float* stokes, float* params, float* pol, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "init_classical: ctx is NULL");
+  int rc = check_inst(ctx, inst, "init_classical");
+  if (rc) return rc;
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "init_classical: n < 0");
+  if (inst->C.n_obs < 3)
+    return fail(ctx, VFISV_E_UNSUPPORTED, "init_classical: needs at least 3 observed samples");
+  if (n == 0) return VFISV_OK;
+  if (!stokes || !params) return fail(ctx, VFISV_E_INVALID, "init_classical: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  ClassicalArgs a;
+  a.stokes = stokes;
+  a.x = inst->d_obs_x;
+  a.n_obs = inst->C.n_obs;
+  a.n = n;
+  a.cz = inst->C.cz;
+  a.lam0_mA = inst->C.lam_over_c * (float)C_KMS;
+  a.params = params;
+  a.pol = pol;
+  const int64_t blocks = (n + 255) / 256;
+  const int64_t cap = (int64_t)ctx->num_cus * 16;
+  e = launch_classical(a, (int)(blocks < cap ? blocks : cap), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "init_classical launch");
   return VFISV_OK;
 }
 

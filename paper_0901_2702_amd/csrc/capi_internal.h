@@ -38,6 +38,7 @@ struct vfisv_instrument {
   vfisv::Point* d_pts = nullptr;       // KIND_DENSE6
   vfisv::Block* d_blocks = nullptr;    // KIND_BAND
   float* d_row_sums = nullptr;         // KIND_BAND
+  float* d_obs_x = nullptr;            // [n_obs] observed wavelength of each sample
   vfisv::Consts C;
   vfisv_instrument_info info;
 };

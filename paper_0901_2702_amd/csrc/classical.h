@@ -1,0 +1,23 @@
+// Classical initial guess (declarations shared by classical.hip and the
+// C-ABI layer).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vfisv {
+
+struct ClassicalArgs {
+  const float* stokes;  // [n][4][n_obs]
+  const float* x;       // [n_obs] observed wavelength of each sample [mA]
+  int n_obs;
+  int64_t n;
+  float cz;             // Eq. 7 constant [mA/G]
+  float lam0_mA;
+  float* params;        // [n][10]
+  float* pol;           // [n] polarisation level, or NULL
+};
+
+hipError_t launch_classical(const ClassicalArgs& a, int grid, hipStream_t s);
+
+}  // namespace vfisv

@@ -62,6 +62,7 @@ def test_null_arguments_are_rejected():
     assert L.vfisv_solve(None, 0, None, None, None, 0, None, None, None) == -1
     assert L.vfisv_iter_histogram(None, 0, None, 1, None, None) == -1
     assert L.vfisv_autotune(None, None, 0, None, None, 0, None, 0, None, None) == -1
+    assert L.vfisv_init_classical(None, None, 0, None, None, None, None) == -1
     assert L.vfisv_instrument_info_get(None, None) == -1
 
 
