@@ -14,8 +14,12 @@ per pixel, on the observed samples:
   solved by least squares over the samples;
 * weak field, transverse: |Q + iU| = (C_Z B_perp)^2 / 4 |d2I/dlambda2|,
   least squares for B_perp^2 (set to 0 if negative);
-* azimuth: 2 psi = atan2(sum U_k w_k, sum Q_k w_k) with w_k = d2I/dlambda2
-  at the samples (the sign of the transverse Zeeman signal);
+* azimuth: 2 psi = atan2(sum_k U_k, sum_k Q_k), the linear polarisation
+  integrated over the observed samples (the paper cites Auer et al. 1977
+  and calls it more reliable than half the arctangent of U/Q, without
+  printing it; read here as the line-integrated ratio, which is exact for
+  transverse fields and insensitive to the sign change of Q between the
+  line core and the sigma components of strong fields);
 * derivatives of I by finite differences on the (non-uniform) sample grid:
   central first differences, three-point second differences, the end
   samples taking their neighbour's second difference;
@@ -25,9 +29,15 @@ per pixel, on the observed samples:
   gamma); Doppler width, damping, eta0 and alpha from the default model;
   S0, S1 = 0.3 I_c, 0.7 I_c; then the box projection.
 * polarisation level: max_k sqrt(Q_k^2 + U_k^2 + V_k^2) / I_c (the paper
-  switches between methods at 6%).
+  switches between methods at 6%), undefined (NaN) when I_c <= 0.
 * where a denominator vanishes (no depression, no slope or no curvature of
   I) the corresponding estimate is 0.
+
+combined_init puts the two initialisations of Sect. 5 together: a model
+from elsewhere (the network's) keeps everything but the azimuth, which is
+always the classical one, and B and gamma, which are the classical ones
+where the polarisation level is below the threshold (a NaN level keeps the
+base's); a pixel with non-finite samples keeps the base model.
 """
 import numpy as np
 
@@ -81,7 +91,7 @@ def classical_init(obs, x_mA, lambda0_A, cz_mA_per_G, default_model, project):
     L = np.sqrt(Q * Q + U * U)
     b_perp2 = 4.0 * ratio((L * np.abs(Ipp)).sum(axis=1), cz_mA_per_G ** 2 * (Ipp * Ipp).sum(axis=1))
     b_perp = np.sqrt(np.maximum(b_perp2, 0.0))
-    psi = 0.5 * np.degrees(np.arctan2((U * Ipp).sum(axis=1), (Q * Ipp).sum(axis=1)))
+    psi = 0.5 * np.degrees(np.arctan2(U.sum(axis=1), Q.sum(axis=1)))
     bl = b_par / ALPHA0
     bt = b_perp / np.sqrt(ALPHA0)
     M = np.tile(np.asarray(default_model, dtype=np.float64), (S.shape[0], 1))
@@ -92,5 +102,26 @@ def classical_init(obs, x_mA, lambda0_A, cz_mA_per_G, default_model, project):
     M[:, 7] = 0.3 * Ic
     M[:, 8] = 0.7 * Ic
     M = np.array([project(m) for m in M])
-    pol = np.sqrt(Q * Q + U * U + V * V).max(axis=1) / Ic
+    pmax = np.sqrt(Q * Q + U * U + V * V).max(axis=1)
+    pol = np.full_like(Ic, np.nan)
+    np.divide(pmax, Ic, out=pol, where=Ic > 0.0)
     return M, pol
+
+
+def combined_init(obs, base, pol_threshold, x_mA, lambda0_A, cz_mA_per_G, default_model,
+                  project):
+    """obs [n, 4, n_obs], base [n, 10] -> (starting models [n, 10], polarisation
+    level [n])."""
+    S = np.asarray(obs, dtype=np.float64)
+    finite = np.isfinite(S).all(axis=(1, 2))
+    M = np.array(base, dtype=np.float64)
+    pol = np.full(S.shape[0], np.nan)
+    if finite.any():
+        Mc, pc = classical_init(S[finite], x_mA, lambda0_A, cz_mA_per_G, default_model, project)
+        pol[finite] = pc
+        sub = M[finite]
+        sub[:, 2] = Mc[:, 2]
+        low = pc < pol_threshold  # False for a NaN level
+        sub[low, 0:2] = Mc[low, 0:2]
+        M[finite] = sub
+    return np.array([project(m) for m in M]), pol
