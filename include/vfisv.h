@@ -284,7 +284,8 @@ int vfisv_autotune(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
  * samples at the centroids of the instrument's filter rows:
  *   I_c = max I; v = c * (centre of gravity of I_c - I) / lambda0;
  *   B_par = -sum V I' / (C_Z sum I'^2); B_perp^2 = 4 sum |Q+iU| |I''| /
- *   (C_Z^2 sum I''^2); 2 psi = atan2(sum U I'', sum Q I'');
+ *   (C_Z^2 sum I''^2); 2 psi = atan2(sum U, sum Q) (the linear polarisation
+ *   integrated over the samples);
  * I', I'' finite differences across the samples; B and gamma from
  * B_par / 0.6 and B_perp / sqrt(0.6) (default filling factor 0.6); Doppler
  * width, damping, eta0 and alpha from the default model; S0, S1 = 0.3 I_c,
@@ -295,6 +296,22 @@ int vfisv_autotune(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
  *   NULL.  Needs n_obs >= 3.  Asynchronous on stream. */
 int vfisv_init_classical(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                          const float *stokes, float *params, float *pol, void *stream);
+
+/* The two initialisations of Sect. 5 combined: a starting model from
+ * elsewhere (normally the network's, vfisv_mlp_forward) keeps all its
+ * parameters except that the azimuth is always replaced by the classical
+ * one, and B and gamma by the classical ones where the polarisation level
+ * is below pol_threshold (0.06 in the paper).  The classical estimates are
+ * those of vfisv_init_classical; a pixel with non-finite samples keeps base
+ * unchanged.  The result goes through the box.
+ *   base: dev [n][10] finite float32; params: dev [n][10] output, may be
+ *   the same buffer as base (each pixel reads its row before writing it);
+ *   pol: dev [n] or NULL, as for vfisv_init_classical; pol_threshold >= 0
+ *   (+inf gives classical B, gamma and azimuth everywhere, 0 only the
+ *   azimuth).  Needs n_obs >= 3.  Asynchronous on stream. */
+int vfisv_init_combined(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                        const float *stokes, const float *base, float pol_threshold,
+                        float *params, float *pol, void *stream);
 
 /* Work counters of the most recent vfisv_invert or vfisv_invert_batches
  * (synchronises the context's device). */
@@ -352,6 +369,10 @@ int vfisv_mlp_destroy(vfisv_mlp *mlp);
  * W4 [256][32], b4 [32], K0 = n_in rounded up to 32; -1 if mlp is NULL). */
 int64_t vfisv_mlp_num_params(const vfisv_mlp *mlp);
 
+/* Number of network inputs n_in (the row length of the stokes arrays the
+ * network functions read); -1 if mlp is NULL. */
+int vfisv_mlp_num_inputs(const vfisv_mlp *mlp);
+
 /* Copy the float32 parameters to / from host memory (synchronising).
  * set_params also clears the Adam state. n must equal num_params. */
 int vfisv_mlp_get_params(vfisv_mlp *mlp, float *host, int64_t n);
@@ -371,8 +392,9 @@ int vfisv_mlp_gradient(vfisv_ctx *ctx, vfisv_mlp *mlp, int64_t n, const float *s
                        const float *targets, float *grad, double *loss, void *stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch of rows
- * `rows` (dev int32 [batch], indices into stokes [.][4*n_obs] and targets
- * [.][10]); batch a positive multiple of 32.  The summed squared error
+ * `rows` (dev int32 [batch], indices into stokes [.][n_in] and targets
+ * [.][10]; every index must address a row of both, which is not checked);
+ * batch a positive multiple of 32.  The summed squared error
  * accumulates until vfisv_mlp_take_loss. */
 int vfisv_mlp_train_step(vfisv_ctx *ctx, vfisv_mlp *mlp, const float *stokes,
                          const float *targets, const int32_t *rows, int batch, float lr,

@@ -72,12 +72,12 @@ class _Counters(ctypes.Structure):
 EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_instrument_create", "vfisv_instrument_info_get", "vfisv_instrument_destroy",
            "vfisv_options_default", "vfisv_synthesize", "vfisv_invert", "vfisv_get_counters",
-           "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params",
+           "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params", "vfisv_mlp_num_inputs",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
            "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
-           "vfisv_init_classical")
+           "vfisv_init_classical", "vfisv_init_combined")
 
 _LIB = None
 
@@ -113,6 +113,8 @@ def lib():
         L.vfisv_invert_batches.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.c_int,
                                            ctypes.POINTER(_Options), _vp]
         L.vfisv_init_classical.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.vfisv_init_combined.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float,
+                                          _vp, _vp, _vp]
         L.vfisv_autotune.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
                                      ctypes.POINTER(_Options), ctypes.c_int64,
                                      ctypes.POINTER(_Tuning), _vp]
@@ -124,7 +126,10 @@ def version():
     return lib().vfisv_version().decode()
 
 
-def _ptr(t, dtype, device, shape_last=None, name="tensor"):
+def _ptr(t, dtype, device, numel=None, name="tensor"):
+    """Device address of a contiguous tensor, after checking its dtype,
+    device and (when given) element count: the library takes bare pointers
+    and reads or writes exactly the sizes its arguments imply."""
     if t is None:
         return None
     if not isinstance(t, torch.Tensor):
@@ -135,7 +140,19 @@ def _ptr(t, dtype, device, shape_last=None, name="tensor"):
         raise ValueError("%s must live on %s, got %s" % (name, device, t.device))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must hold %d elements, got shape %s" % (name, numel, tuple(t.shape)))
     return t.data_ptr()
+
+
+def _rows(t, name="stokes"):
+    if not isinstance(t, torch.Tensor) or t.dim() < 1:
+        raise TypeError("%s must be a torch tensor with a leading pixel dimension" % name)
+    return t.shape[0]
+
+
+def _w_numel(W, n, n_obs):
+    return (n if W.dim() == 3 else 1) * 4 * n_obs
 
 
 def _stream(device):
@@ -244,15 +261,17 @@ def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):
     of the models ``params`` [n, 10] (float32, on the context's device);
     ``voigt`` selects the H/F evaluation as Options.voigt does."""
     dev = ctx.device
-    n = params.shape[0]
-    p = _ptr(params, torch.float32, dev, name="params")
+    n = _rows(params, "params")
+    m = n * 4 * inst.n_obs
+    p = _ptr(params, torch.float32, dev, n * NPAR, name="params")
     stokes = out if out is not None else torch.empty((n, 4, inst.n_obs), device=dev,
                                                      dtype=torch.float32)
     J = torch.empty((n, 4, inst.n_obs, NPAR), device=dev, dtype=torch.float32) if jac else None
     ctx._check(lib().vfisv_synthesize_voigt(ctx._h, inst._h, n, p,
-                                            _ptr(noise, torch.float32, dev, name="noise"),
-                                            _ptr(stokes, torch.float32, dev, name="out"),
-                                            _ptr(J, torch.float32, dev, name="jac"), int(voigt),
+                                            _ptr(noise, torch.float32, dev, m, name="noise"),
+                                            _ptr(stokes, torch.float32, dev, m, name="out"),
+                                            _ptr(J, torch.float32, dev, m * NPAR, name="jac"),
+                                            int(voigt),
                                             _stream(dev)),
                "vfisv_synthesize_voigt")
     return (stokes, J) if jac else stokes
@@ -264,22 +283,16 @@ def invert(ctx, inst, stokes, W, init=None, opts=None, out=None):
     device tensors params [n, 10], chi2 [n] (float64), iters [n], status [n]."""
     dev = ctx.device
     opts = opts or Options()
-    n = stokes.shape[0]
+    n = _rows(stokes)
     if out is None:
-        out = dict(params=torch.empty((n, NPAR), device=dev, dtype=torch.float32),
-                   chi2=torch.empty(n, device=dev, dtype=torch.float64),
-                   iters=torch.empty(n, device=dev, dtype=torch.int32),
-                   status=torch.empty(n, device=dev, dtype=torch.int32))
+        out = _alloc_out(n, dev)
     per_pixel = 1 if W.dim() == 3 else 0
     o = opts.c()
     ctx._check(lib().vfisv_invert(
-        ctx._h, inst._h, n, _ptr(stokes, torch.float32, dev, name="stokes"),
-        _ptr(W, torch.float32, dev, name="W"), per_pixel,
-        _ptr(init, torch.float32, dev, name="init"), ctypes.byref(o),
-        _ptr(out["params"], torch.float32, dev, name="params"),
-        _ptr(out["chi2"], torch.float64, dev, name="chi2"),
-        _ptr(out["iters"], torch.int32, dev, name="iters"),
-        _ptr(out["status"], torch.int32, dev, name="status"), _stream(dev)), "vfisv_invert")
+        ctx._h, inst._h, n, _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
+        _ptr(W, torch.float32, dev, _w_numel(W, n, inst.n_obs), name="W"), per_pixel,
+        _ptr(init, torch.float32, dev, n * NPAR, name="init"), ctypes.byref(o),
+        *_out_ptrs(out, n, dev), _stream(dev)), "vfisv_invert")
     return out
 
 
@@ -288,6 +301,13 @@ def _alloc_out(n, dev):
                 chi2=torch.empty(n, device=dev, dtype=torch.float64),
                 iters=torch.empty(n, device=dev, dtype=torch.int32),
                 status=torch.empty(n, device=dev, dtype=torch.int32))
+
+
+def _out_ptrs(out, n, dev):
+    return (_ptr(out["params"], torch.float32, dev, n * NPAR, name="params"),
+            _ptr(out["chi2"], torch.float64, dev, n, name="chi2"),
+            _ptr(out["iters"], torch.int32, dev, n, name="iters"),
+            _ptr(out["status"], torch.int32, dev, n, name="status"))
 
 
 def invert_batches(ctx, batches, opts=None):
@@ -300,18 +320,18 @@ def invert_batches(ctx, batches, opts=None):
     arr = (_Batch * len(batches))()
     outs = []
     for i, b in enumerate(batches):
-        n = b["stokes"].shape[0]
+        n = _rows(b["stokes"])
         out = b.get("out") or _alloc_out(n, dev)
         outs.append(out)
         W = b["W"]
-        h = b["inst"]._h
-        arr[i] = _Batch(h.value if isinstance(h, ctypes.c_void_p) else h, n, _ptr(b["stokes"], torch.float32, dev, name="stokes"),
-                        _ptr(W, torch.float32, dev, name="W"), 1 if W.dim() == 3 else 0,
-                        _ptr(b.get("init"), torch.float32, dev, name="init"),
-                        _ptr(out["params"], torch.float32, dev, name="params"),
-                        _ptr(out["chi2"], torch.float64, dev, name="chi2"),
-                        _ptr(out["iters"], torch.int32, dev, name="iters"),
-                        _ptr(out["status"], torch.int32, dev, name="status"))
+        inst = b["inst"]
+        h = inst._h
+        arr[i] = _Batch(h.value if isinstance(h, ctypes.c_void_p) else h, n,
+                        _ptr(b["stokes"], torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
+                        _ptr(W, torch.float32, dev, _w_numel(W, n, inst.n_obs), name="W"),
+                        1 if W.dim() == 3 else 0,
+                        _ptr(b.get("init"), torch.float32, dev, n * NPAR, name="init"),
+                        *_out_ptrs(out, n, dev))
     o = opts.c()
     ctx._check(lib().vfisv_invert_batches(ctx._h, arr, len(batches), ctypes.byref(o),
                                           _stream(dev)), "vfisv_invert_batches")
@@ -322,14 +342,36 @@ def init_classical(ctx, inst, stokes):
     """Classical starting models [n, 10] (weak field, azimuth, line
     position) and polarisation levels [n] for stokes [n, 4, n_obs]."""
     dev = ctx.device
-    n = stokes.shape[0]
+    n = _rows(stokes)
     params = torch.empty((n, NPAR), device=dev, dtype=torch.float32)
     pol = torch.empty(n, device=dev, dtype=torch.float32)
     ctx._check(lib().vfisv_init_classical(ctx._h, inst._h, n,
-                                          _ptr(stokes, torch.float32, dev, name="stokes"),
+                                          _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs,
+                                               name="stokes"),
                                           _ptr(params, torch.float32, dev),
                                           _ptr(pol, torch.float32, dev), _stream(dev)),
                "vfisv_init_classical")
+    return params, pol
+
+
+def init_combined(ctx, inst, stokes, base, pol_threshold=0.06, out=None):
+    """Starting models [n, 10] combining base (e.g. the network's) with the
+    classical azimuth everywhere and the classical B, gamma below
+    pol_threshold; also returns the polarisation levels [n].  out may be
+    base (in place)."""
+    dev = ctx.device
+    n = _rows(stokes)
+    params = out if out is not None else torch.empty((n, NPAR), device=dev,
+                                                     dtype=torch.float32)
+    pol = torch.empty(n, device=dev, dtype=torch.float32)
+    ctx._check(lib().vfisv_init_combined(ctx._h, inst._h, n,
+                                         _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs,
+                                              name="stokes"),
+                                         _ptr(base, torch.float32, dev, n * NPAR, name="base"),
+                                         float(pol_threshold),
+                                         _ptr(params, torch.float32, dev, n * NPAR, name="out"),
+                                         _ptr(pol, torch.float32, dev), _stream(dev)),
+               "vfisv_init_combined")
     return params, pol
 
 
@@ -340,9 +382,11 @@ def autotune(ctx, inst, stokes, W, opts=None, sample=0):
     dev = ctx.device
     o = (opts or Options()).c()
     t = _Tuning()
+    n = _rows(stokes)
     ctx._check(lib().vfisv_autotune(
-        ctx._h, inst._h, stokes.shape[0], _ptr(stokes, torch.float32, dev, name="stokes"),
-        _ptr(W, torch.float32, dev, name="W"), 1 if W.dim() == 3 else 0, ctypes.byref(o),
+        ctx._h, inst._h, n, _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
+        _ptr(W, torch.float32, dev, _w_numel(W, n, inst.n_obs), name="W"),
+        1 if W.dim() == 3 else 0, ctypes.byref(o),
         int(sample), ctypes.byref(t), _stream(dev)), "vfisv_autotune")
     return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
@@ -353,8 +397,9 @@ def iter_histogram(ctx, iters, n_bins=51):
     import numpy as np
     dev = ctx.device
     hist = np.zeros(n_bins, dtype=np.int64)
+    n = _rows(iters, "iters")
     ctx._check(lib().vfisv_iter_histogram(
-        ctx._h, iters.shape[0], _ptr(iters, torch.int32, dev, name="iters"), int(n_bins),
+        ctx._h, n, _ptr(iters, torch.int32, dev, n, name="iters"), int(n_bins),
         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(dev)),
         "vfisv_iter_histogram")
     return hist
@@ -364,12 +409,12 @@ def solve(ctx, H, g, eps, free_mask=0x3FF):
     """Damped solves: H [n, 55] float32 packed lower triangle, g [n, 10]
     float32, eps [n] float64 -> (delta [n, 10] float64, code [n] int32)."""
     dev = ctx.device
-    n = H.shape[0]
+    n = _rows(H, "H")
     delta = torch.empty((n, NPAR), device=dev, dtype=torch.float64)
     code = torch.empty(n, device=dev, dtype=torch.int32)
-    ctx._check(lib().vfisv_solve(ctx._h, n, _ptr(H, torch.float32, dev, name="H"),
-                                 _ptr(g, torch.float32, dev, name="g"),
-                                 _ptr(eps, torch.float64, dev, name="eps"), free_mask,
+    ctx._check(lib().vfisv_solve(ctx._h, n, _ptr(H, torch.float32, dev, n * 55, name="H"),
+                                 _ptr(g, torch.float32, dev, n * NPAR, name="g"),
+                                 _ptr(eps, torch.float64, dev, n, name="eps"), free_mask,
                                  _ptr(delta, torch.float64, dev, name="delta"),
                                  _ptr(code, torch.int32, dev, name="code"), _stream(dev)),
                "vfisv_solve")

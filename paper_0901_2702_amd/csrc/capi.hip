@@ -701,16 +701,21 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   return VFISV_OK;
 }
 
-int vfisv_init_classical(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
-                         const float* stokes, float* params, float* pol, void* stream) {
-  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "init_classical: ctx is NULL");
-  int rc = check_inst(ctx, inst, "init_classical");
+namespace {
+
+int init_start(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const float* stokes,
+               const float* base, float pol_threshold, float* params, float* pol,
+               void* stream, const char* what) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, std::string(what) + ": ctx is NULL");
+  int rc = check_inst(ctx, inst, what);
   if (rc) return rc;
-  if (n < 0) return fail(ctx, VFISV_E_INVALID, "init_classical: n < 0");
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, std::string(what) + ": n < 0");
   if (inst->C.n_obs < 3)
-    return fail(ctx, VFISV_E_UNSUPPORTED, "init_classical: needs at least 3 observed samples");
+    return fail(ctx, VFISV_E_UNSUPPORTED, std::string(what) + ": needs at least 3 observed samples");
+  if (!(pol_threshold >= 0.f))
+    return fail(ctx, VFISV_E_INVALID, std::string(what) + ": pol_threshold must be >= 0");
   if (n == 0) return VFISV_OK;
-  if (!stokes || !params) return fail(ctx, VFISV_E_INVALID, "init_classical: NULL buffer");
+  if (!stokes || !params) return fail(ctx, VFISV_E_INVALID, std::string(what) + ": NULL buffer");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   ClassicalArgs a;
@@ -722,11 +727,28 @@ int vfisv_init_classical(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.lam0_mA = inst->C.lam_over_c * (float)C_KMS;
   a.params = params;
   a.pol = pol;
+  a.base = base;
+  a.pol_threshold = pol_threshold;
   const int64_t blocks = (n + 255) / 256;
   const int64_t cap = (int64_t)ctx->num_cus * 16;
   e = launch_classical(a, (int)(blocks < cap ? blocks : cap), (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "init_classical launch");
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
   return VFISV_OK;
+}
+
+}  // namespace
+
+int vfisv_init_classical(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                         const float* stokes, float* params, float* pol, void* stream) {
+  return init_start(ctx, inst, n, stokes, nullptr, 0.f, params, pol, stream, "init_classical");
+}
+
+int vfisv_init_combined(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                        const float* stokes, const float* base, float pol_threshold,
+                        float* params, float* pol, void* stream) {
+  if (n > 0 && !base && ctx) return fail(ctx, VFISV_E_INVALID, "init_combined: base is NULL");
+  return init_start(ctx, inst, n, stokes, base, pol_threshold, params, pol, stream,
+                    "init_combined");
 }
 
 int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {

@@ -16,6 +16,8 @@ struct ClassicalArgs {
   float lam0_mA;
   float* params;        // [n][10]
   float* pol;           // [n] polarisation level, or NULL
+  const float* base;    // [n][10] model to combine with, or NULL (classical only)
+  float pol_threshold;  // with base: classical B and gamma below this level
 };
 
 hipError_t launch_classical(const ClassicalArgs& a, int grid, hipStream_t s);

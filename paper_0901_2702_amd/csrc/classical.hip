@@ -5,12 +5,18 @@
 //   I_c = max_k I_k; v = c * cog(I_c - I_k) / lambda0;
 //   B_par = -sum V_k I'_k / (C_Z sum I'_k^2)      (V = -C_Z B_par dI/dl);
 //   B_perp^2 = 4 sum |Q + iU|_k |I''_k| / (C_Z^2 sum I''_k^2);
-//   2 psi = atan2(sum U_k I''_k, sum Q_k I''_k);
+//   2 psi = atan2(sum U_k, sum Q_k)   (linear polarisation over the line);
 // with I' and I'' finite differences across the (non-uniform) samples; the
 // weak-field signals scale with the filling factor, taken at its default
 // 0.6 (B_par / 0.6, B_perp / sqrt(0.6)); the other parameters come from the
 // default model, S0 and S1 scaled to I_c.  A vanishing denominator gives 0.
-// One pixel per lane; the loops run over the observed samples.
+// With a base model (the network's start) the two are combined as the
+// paper's initialisation does: the azimuth always classical, B and gamma
+// classical only below a polarisation level, everything else from the base.
+// One pixel per lane; the loops run over the observed samples.  For six
+// samples (the filtergram case) a lane loads its pixel's 24 values with six
+// 16-byte loads up front and the loops unroll over registers; other sample
+// counts read the values from memory as they go.
 #include <hip/hip_runtime.h>
 
 #include "classical.h"
@@ -18,43 +24,73 @@
 
 namespace vfisv {
 
+// NO > 0: exactly NO samples, the pixel's rows 16-byte aligned; NO == 0: any.
+template <int NO>
 __global__ __launch_bounds__(256) void classical_init_kernel(const ClassicalArgs A) {
-  const int no = A.n_obs;
+  const int no = NO > 0 ? NO : A.n_obs;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const float* S = A.stokes + i * (int64_t)(4 * no);
-    const float* I = S;
-    const float* Q = S + no;
-    const float* U = S + 2 * no;
-    const float* V = S + 3 * no;
+    const float* G = A.stokes + i * (int64_t)(4 * no);
+    float R[NO > 0 ? 4 * NO : 1];
+    if constexpr (NO > 0) {
+      const float4* g4 = reinterpret_cast<const float4*>(G);
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        const float4 t = g4[j];
+        R[4 * j] = t.x;
+        R[4 * j + 1] = t.y;
+        R[4 * j + 2] = t.z;
+        R[4 * j + 3] = t.w;
+      }
+    }
+    // sample k of Stokes parameter s (0 I, 1 Q, 2 U, 3 V)
+    auto at = [&](int s, int k) -> float {
+      if constexpr (NO > 0)
+        return R[s * NO + k];
+      else
+        return G[s * no + k];
+    };
     bool finite = true;
     float Ic = -INFINITY;
-    for (int k = 0; k < 4 * no; ++k) finite = finite && isfinite(S[k]);
-    for (int k = 0; k < no; ++k) Ic = fmaxf(Ic, I[k]);
-    float sd = 0.f, sdx = 0.f, sVI = 0.f, sII = 0.f, sLI = 0.f, sI2 = 0.f, sUI = 0.f, sQI = 0.f,
+#pragma unroll
+    for (int k = 0; k < no; ++k)
+      finite = finite && isfinite(at(0, k)) && isfinite(at(1, k)) && isfinite(at(2, k)) &&
+               isfinite(at(3, k));
+#pragma unroll
+    for (int k = 0; k < no; ++k) Ic = fmaxf(Ic, at(0, k));
+    float sd = 0.f, sdx = 0.f, sVI = 0.f, sII = 0.f, sLI = 0.f, sI2 = 0.f, sU = 0.f, sQ = 0.f,
           pol = 0.f;
+#pragma unroll
     for (int k = 0; k < no; ++k) {
-      const float d = Ic - I[k];
+      const float d = Ic - at(0, k);
       sd += d;
       sdx = fmaf(d, A.x[k], sdx);
       // first difference: central inside, one-sided at the ends
       const int a = k > 0 ? k - 1 : 0, b = k < no - 1 ? k + 1 : no - 1;
-      const float Ip = (I[b] - I[a]) / (A.x[b] - A.x[a]);
+      const float Ip = (at(0, b) - at(0, a)) / (A.x[b] - A.x[a]);
       // second difference: three-point at the interior sample c nearest k
       const int c = k < 1 ? 1 : (k > no - 2 ? no - 2 : k);
       const float h0 = A.x[c] - A.x[c - 1], h1 = A.x[c + 1] - A.x[c];
-      const float Ipp =
-          2.f * (h0 * I[c + 1] - (h0 + h1) * I[c] + h1 * I[c - 1]) / (h0 * h1 * (h0 + h1));
-      const float L = sqrtf(fmaf(Q[k], Q[k], U[k] * U[k]));
-      sVI = fmaf(V[k], Ip, sVI);
+      const float Ipp = 2.f * (h0 * at(0, c + 1) - (h0 + h1) * at(0, c) + h1 * at(0, c - 1)) /
+                        (h0 * h1 * (h0 + h1));
+      const float Qk = at(1, k), Uk = at(2, k), Vk = at(3, k);
+      const float L = sqrtf(fmaf(Qk, Qk, Uk * Uk));
+      sVI = fmaf(Vk, Ip, sVI);
       sII = fmaf(Ip, Ip, sII);
       sLI = fmaf(L, fabsf(Ipp), sLI);
       sI2 = fmaf(Ipp, Ipp, sI2);
-      sUI = fmaf(U[k], Ipp, sUI);
-      sQI = fmaf(Q[k], Ipp, sQI);
-      pol = fmaxf(pol, sqrtf(fmaf(L, L, V[k] * V[k])));
+      sU += Uk;
+      sQ += Qk;
+      pol = fmaxf(pol, sqrtf(fmaf(L, L, Vk * Vk)));
+    }
+    // base rows are read before params rows are written (they may alias)
+    double Mb[NPAR];
+    if (A.base) {
+#pragma unroll
+      for (int q = 0; q < NPAR; ++q) Mb[q] = A.base[i * NPAR + q];
     }
     double M[NPAR] = {1500.0, 90.0, 90.0, 0.0, 35.0, 0.25, 15.5, 0.3, 0.7, 0.6};
+    const float level = (finite && Ic > 0.f) ? pol / Ic : __builtin_nanf("");
     if (finite && no >= 3) {
       const double lam_cog = sd != 0.f ? (double)sdx / (double)sd : 0.0;
       const double b_par = sII != 0.f ? -(double)sVI / ((double)A.cz * (double)sII) : 0.0;
@@ -63,20 +99,34 @@ __global__ __launch_bounds__(256) void classical_init_kernel(const ClassicalArgs
       const double bl = b_par / 0.6, bt = sqrt(fmax(bp2, 0.0)) / sqrt(0.6);
       M[0] = sqrt(bl * bl + bt * bt);
       M[1] = atan2(bt, bl) * (180.0 / 3.14159265358979323846);
-      M[2] = 0.5 * atan2((double)sUI, (double)sQI) * (180.0 / 3.14159265358979323846);
+      M[2] = 0.5 * atan2((double)sU, (double)sQ) * (180.0 / 3.14159265358979323846);
       M[3] = C_KMS * lam_cog / (double)A.lam0_mA;
       M[7] = 0.3 * (double)Ic;
       M[8] = 0.7 * (double)Ic;
     }
+    if (A.base) {
+      if (finite) {
+        Mb[2] = M[2];
+        if (level < A.pol_threshold) {  // false for a NaN level
+          Mb[0] = M[0];
+          Mb[1] = M[1];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NPAR; ++q) M[q] = Mb[q];
+    }
     project(M);
 #pragma unroll
     for (int q = 0; q < NPAR; ++q) A.params[i * NPAR + q] = (float)M[q];
-    if (A.pol) A.pol[i] = (finite && Ic > 0.f) ? pol / Ic : __builtin_nanf("");
+    if (A.pol) A.pol[i] = level;
   }
 }
 
 hipError_t launch_classical(const ClassicalArgs& a, int grid, hipStream_t s) {
-  classical_init_kernel<<<grid, 256, 0, s>>>(a);
+  if (a.n_obs == 6 && reinterpret_cast<uintptr_t>(a.stokes) % 16 == 0)
+    classical_init_kernel<6><<<grid, 256, 0, s>>>(a);
+  else
+    classical_init_kernel<0><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -230,6 +230,8 @@ int vfisv_mlp_destroy(vfisv_mlp* m) {
 
 int64_t vfisv_mlp_num_params(const vfisv_mlp* m) { return m ? m->dev.L.total : -1; }
 
+int vfisv_mlp_num_inputs(const vfisv_mlp* m) { return m ? m->dev.L.n_in : -1; }
+
 int vfisv_mlp_get_params(vfisv_mlp* m, float* host, int64_t n) {
   if (!m || !host) return VFISV_E_INVALID;
   if (n != m->dev.L.total) return fail(m->ctx, VFISV_E_INVALID, "mlp_get_params: size mismatch");

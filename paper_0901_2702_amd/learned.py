@@ -14,8 +14,8 @@ import time
 import numpy as np
 import torch
 
-from . import (NPAR, Context, Instrument, Options, VfisvError, _Options, _ptr, _stream, _vp,
-               lib, synthesize)
+from . import (NPAR, Context, Instrument, Options, VfisvError, _alloc_out, _Options, _out_ptrs,
+               _ptr, _rows, _stream, _vp, _w_numel, lib, synthesize)
 
 NCODE = 10
 
@@ -29,6 +29,8 @@ def _L():
         L.vfisv_mlp_destroy.argtypes = [_vp]
         L.vfisv_mlp_num_params.argtypes = [_vp]
         L.vfisv_mlp_num_params.restype = ctypes.c_int64
+        L.vfisv_mlp_num_inputs.argtypes = [_vp]
+        L.vfisv_mlp_num_inputs.restype = ctypes.c_int
         L.vfisv_mlp_get_params.argtypes = [_vp, fp, ctypes.c_int64]
         L.vfisv_mlp_set_params.argtypes = [_vp, fp, ctypes.c_int64]
         L.vfisv_mlp_forward.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
@@ -91,6 +93,17 @@ class Mlp:
     def num_params(self):
         return int(_L().vfisv_mlp_num_params(self._h))
 
+    @property
+    def n_in(self):
+        return int(_L().vfisv_mlp_num_inputs(self._h))
+
+    def _input_rows(self, stokes):
+        n = _rows(stokes)
+        if stokes.numel() != n * self.n_in:
+            raise ValueError("stokes must be [n, %d] for this network, got shape %s"
+                             % (self.n_in, tuple(stokes.shape)))
+        return n
+
     def get_params(self):
         a = np.empty(self.num_params, np.float32)
         self.ctx._check(_L().vfisv_mlp_get_params(
@@ -103,7 +116,7 @@ class Mlp:
 
     def forward(self, stokes, codes=True, params=True):
         dev = self.ctx.device
-        n = stokes.shape[0]
+        n = self._input_rows(stokes)
         c = torch.empty((n, NCODE), device=dev, dtype=torch.float32) if codes else None
         p = torch.empty((n, NPAR), device=dev, dtype=torch.float32) if params else None
         self.ctx._check(_L().vfisv_mlp_forward(
@@ -114,19 +127,29 @@ class Mlp:
 
     def gradient(self, stokes, targets):
         dev = self.ctx.device
+        n = self._input_rows(stokes)
         g = torch.empty(self.num_params, device=dev, dtype=torch.float32)
         loss = torch.empty(1, device=dev, dtype=torch.float64)
         self.ctx._check(_L().vfisv_mlp_gradient(
-            self.ctx._h, self._h, stokes.shape[0], _ptr(stokes, torch.float32, dev, name="stokes"),
-            _ptr(targets, torch.float32, dev, name="targets"), _ptr(g, torch.float32, dev),
+            self.ctx._h, self._h, n, _ptr(stokes, torch.float32, dev, name="stokes"),
+            _ptr(targets, torch.float32, dev, n * NCODE, name="targets"),
+            _ptr(g, torch.float32, dev),
             _ptr(loss, torch.float64, dev), _stream(dev)), "vfisv_mlp_gradient")
         return g, loss
 
-    def train_step(self, stokes, targets, rows, lr):
+    def train_step(self, stokes, targets, rows, lr, check_rows=True):
+        """One Adam step on stokes[rows], targets[rows].  The library does not
+        bound-check the indices; check_rows (one host synchronisation) does,
+        for callers whose rows are not in range by construction."""
         dev = self.ctx.device
+        n = self._input_rows(stokes)
+        if rows.dim() != 1:
+            raise ValueError("rows must be one-dimensional")
+        if check_rows and rows.numel() and (int(rows.min()) < 0 or int(rows.max()) >= n):
+            raise ValueError("rows must index the %d rows of stokes" % n)
         self.ctx._check(_L().vfisv_mlp_train_step(
             self.ctx._h, self._h, _ptr(stokes, torch.float32, dev, name="stokes"),
-            _ptr(targets, torch.float32, dev, name="targets"),
+            _ptr(targets, torch.float32, dev, n * NCODE, name="targets"),
             _ptr(rows, torch.int32, dev, name="rows"), rows.shape[0], float(lr), _stream(dev)),
             "vfisv_mlp_train_step")
 
@@ -141,20 +164,16 @@ def invert_learned(ctx, inst, mlp, stokes, W, opts=None, learned_max_iter=15, ch
     """Learned start + at most learned_max_iter LM trials, plain-LM fallback."""
     dev = ctx.device
     opts = opts or Options()
-    n = stokes.shape[0]
+    n = _rows(stokes)
     if out is None:
-        out = dict(params=torch.empty((n, NPAR), device=dev, dtype=torch.float32),
-                   chi2=torch.empty(n, device=dev, dtype=torch.float64),
-                   iters=torch.empty(n, device=dev, dtype=torch.int32),
-                   status=torch.empty(n, device=dev, dtype=torch.int32))
+        out = _alloc_out(n, dev)
     o = opts.c()
     ctx._check(_L().vfisv_invert_learned(
-        ctx._h, inst._h, mlp._h, n, _ptr(stokes, torch.float32, dev, name="stokes"),
-        _ptr(W, torch.float32, dev, name="W"), 1 if W.dim() == 3 else 0, ctypes.byref(o),
-        int(learned_max_iter), float(chi2_accept),
-        _ptr(out["params"], torch.float32, dev), _ptr(out["chi2"], torch.float64, dev),
-        _ptr(out["iters"], torch.int32, dev), _ptr(out["status"], torch.int32, dev),
-        _stream(dev)), "vfisv_invert_learned")
+        ctx._h, inst._h, mlp._h, n,
+        _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
+        _ptr(W, torch.float32, dev, _w_numel(W, n, inst.n_obs), name="W"),
+        1 if W.dim() == 3 else 0, ctypes.byref(o), int(learned_max_iter), float(chi2_accept),
+        *_out_ptrs(out, n, dev), _stream(dev)), "vfisv_invert_learned")
     return out
 
 
@@ -224,7 +243,8 @@ def train(ctx, inst, train_stokes, train_P, control_stokes, control_P, epochs=20
         for b in range(steps_per_epoch):
             frac = step / max(total - 1, 1)
             cur = lr * (min_lr_frac + (1 - min_lr_frac) * 0.5 * (1 + math.cos(math.pi * frac)))
-            mlp.train_step(S, T_train, perm[b * batch:(b + 1) * batch], cur)
+            # a permutation of range(n): in range by construction
+            mlp.train_step(S, T_train, perm[b * batch:(b + 1) * batch], cur, check_rows=False)
             step += 1
         train_mse = mlp.take_loss() / (steps_per_epoch * batch * NCODE)
         c, _ = mlp.forward(control_stokes, codes=True, params=False)

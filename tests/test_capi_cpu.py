@@ -75,3 +75,20 @@ def test_no_cpu_fallback():
     vf, _ = _lib()
     with pytest.raises(vf.VfisvError):
         vf.Context(0)
+
+
+def test_binding_checks_sizes_before_any_call():
+    """The library takes bare pointers; the binding refuses tensors whose
+    element count, dtype or layout does not match what the call implies."""
+    import torch
+    from paper_0901_2702_amd import _ptr
+    cpu = torch.device("cpu")
+    t = torch.zeros((4, 10), dtype=torch.float32)
+    assert _ptr(t, torch.float32, cpu, 40) == t.data_ptr()
+    with pytest.raises(ValueError):
+        _ptr(t, torch.float32, cpu, 41)
+    with pytest.raises(TypeError):
+        _ptr(t, torch.float64, cpu, 40)
+    with pytest.raises(ValueError):
+        _ptr(t.t(), torch.float32, cpu, 40)
+    assert _ptr(None, torch.float32, cpu, 40) is None
