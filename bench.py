@@ -97,13 +97,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
-    ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity"),
+    ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity",
+                                           "init-compare"),
                     default="learned",
                     help="learned: the learned-start vs plain LM line (default); full-disk: "
                          "plain LM over the 13.2M-pixel disk with clustered active regions; "
                          "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch; "
                          "parity: per-parameter differences from the FP64 oracle on the "
-                         "262,144-pixel HMI set")
+                         "262,144-pixel HMI set; init-compare: default / classical / network "
+                         "starts")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -146,6 +148,8 @@ def main():
         return fine_mixed(args, ctx, inst, spec, log)
     if args.workload == "parity":
         return parity(args, ctx, inst, spec, log)
+    if args.workload == "init-compare":
+        return init_compare(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -629,6 +633,114 @@ def parity(args, ctx, inst, spec, log):
                                              "frac_below_1e-4": float(np.mean(dchi[both] < 1e-4))},
             "abs_diff_on_same_minimum": per}
         log("%s start: converged both %.3f, same minimum %.3f" % (start, both.mean(), same.mean()))
+    print(json.dumps(result), flush=True)
+
+
+def init_compare(args, ctx, inst, spec, log):
+    """Starting models for the same LM on the 1M held-out pixels: the default
+    model, the classical estimate (weak field, azimuth, line position), the
+    network's proposal, and the paper's combination of the last two (the
+    network, with the classical azimuth and, below 6 % polarisation, the
+    classical B and gamma).  As in the paper's Fig. 7, the spread between
+    each start and the final fit against the polarisation level; the
+    synthetic truth is known here too, so the spread about it is given."""
+    import numpy as np
+    import torch
+
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    from paper_0901_2702_amd import learned
+    dev = ctx.device
+    stream = torch.cuda.current_stream(dev)
+    n_obs = spec.n_obs
+    S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
+                                           wl.CONFIGS["cfg3_train"]["seed"], wl.draw_params,
+                                           wl.draw_noise)
+    S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
+                                           wl.CONFIGS["cfg3_control"]["seed"], wl.draw_params,
+                                           wl.draw_noise)
+    net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
+                               batch=4096, lr=2e-3, log=log)
+    del S_tr
+    torch.cuda.empty_cache()
+    n = args.n
+    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    P = wl.draw_params(n, seed)
+    noise = wl.draw_noise(n, n_obs, seed)
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                        noise=torch.tensor(noise.astype(np.float32), device=dev))
+    W = torch.tensor(wl.weights(n_obs), device=dev)
+    x = obs.view(n, 4 * n_obs)
+
+    def ev_time(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    net_start = net.forward(x, codes=False)[1]
+    starts = {"default": None}
+    start_ms = {"default": 0.0}
+    start_ms["classical"] = ev_time(lambda: vf.init_classical(ctx, inst, obs))
+    starts["classical"], pol = vf.init_classical(ctx, inst, obs)
+    start_ms["network"] = ev_time(lambda: net.forward(x, codes=False))
+    starts["network"] = net_start
+    comb = torch.empty_like(net_start)
+    start_ms["combined"] = start_ms["network"] + ev_time(
+        lambda: vf.init_combined(ctx, inst, obs, net_start, 0.06, out=comb))
+    starts["combined"] = vf.init_combined(ctx, inst, obs, net_start, 0.06)[0]
+    pol = pol.cpu().numpy()
+    fits, result_starts = {}, {}
+    for name, init in starts.items():
+        out = vf.invert(ctx, inst, obs, W, init=init)
+        ms = ev_time(lambda: vf.invert(ctx, inst, obs, W, init=init, out=out), reps=3)
+        fits[name] = {k: v.cpu().numpy() for k, v in out.items()}
+        ch, it = fits[name]["chi2"], fits[name]["iters"]
+        result_starts[name] = {
+            "start_ms": round(start_ms[name], 3), "lm_ms": round(ms, 3),
+            "mean_iters": float(it.mean()), "median_chi2": float(np.median(ch)),
+            "frac_chi2_below_2.08": float(np.mean(ch < 2.08)),
+            "status_counts": np.bincount(fits[name]["status"] & 255, minlength=4).tolist()}
+        log("%s: %s" % (name, result_starts[name]))
+    # final fit per pixel: the lowest chi^2 of the runs
+    names = list(starts)
+    chis = np.stack([fits[k]["chi2"] for k in names])
+    best = np.argmin(chis, axis=0)
+    final = np.stack([fits[k]["params"] for k in names])[best, np.arange(n)]
+    edges = [0.0, 0.01, 0.02, 0.04, 0.06, 0.1, 0.2, np.inf]
+    bins = [(pol >= edges[i]) & (pol < edges[i + 1]) for i in range(len(edges) - 1)]
+
+    def spread(a, b, col):
+        d = a[:, col] - b[:, col]
+        if col == 2:  # azimuth: 180 == 0
+            d = (d + 90.0) % 180.0 - 90.0
+        return [round(float(np.std(d[m])), 2) if m.any() else None for m in bins]
+
+    fig7 = {"polarisation_bins": [[edges[i], edges[i + 1]] for i in range(len(edges) - 1)],
+            "pixels_per_bin": [int(m.sum()) for m in bins]}
+    for name in ("classical", "network", "combined"):
+        init = starts[name].cpu().numpy()
+        fig7[name] = {"vs_final": {k: spread(init, final, c) for k, c in
+                                   (("sigma_B_G", 0), ("sigma_gamma_deg", 1),
+                                    ("sigma_psi_deg", 2))},
+                      "vs_truth": {k: spread(init, P, c) for k, c in
+                                   (("sigma_B_G", 0), ("sigma_gamma_deg", 1),
+                                    ("sigma_psi_deg", 2))}}
+    fig7["final_vs_truth"] = {k: spread(final, P, c) for k, c in
+                              (("sigma_B_G", 0), ("sigma_gamma_deg", 1), ("sigma_psi_deg", 2))}
+    result = {"metric": "starting models for the same LM: default / classical / network / "
+                        "combined",
+              "config": {"workload": "1M held-out HMI-shaped pixels (cfg0 priors, seed %d, "
+                                     "noise 1e-3); plain LM (convergence exits, <= 50 trials) "
+                                     "from each start; network trained on %d pixels"
+                                     % (seed, args.train_samples)},
+              "starts": result_starts, "fig7_spread_vs_polarisation": fig7,
+              "training_seconds": round(tinfo["seconds"], 2)}
     print(json.dumps(result), flush=True)
 
 
