@@ -45,3 +45,12 @@ def test_full_disk_split_ranges_and_clustering():
     c = wl.full_disk(grid=256, seed=10)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert not np.array_equal(a[1], c[1])
+
+
+def test_disk_mu():
+    mu = wl.disk_mu(64)
+    assert mu.shape == (int(wl.disk_mask(64).sum()),)
+    assert 0.0 <= mu.min() < 0.2 and 0.99 < mu.max() <= 1.0
+    # the pixels with mu above m fill the disk area inside rho = sqrt(1 - m^2)
+    m = 0.6
+    assert abs(np.mean(mu > m) - (1 - m * m)) < 0.02

@@ -134,6 +134,16 @@ def disk_mask(grid=4096):
     return (x - c) ** 2 + (y - c) ** 2 <= (grid / 2.0) ** 2
 
 
+def disk_mu(grid=4096):
+    """mu = cos(heliocentric angle) of each disk pixel, in the disk's
+    row-major order: sqrt(1 - rho^2), rho the distance from the centre over
+    the radius grid/2."""
+    c = (grid - 1) / 2.0
+    y, x = np.mgrid[0:grid, 0:grid]
+    rho2 = ((x - c) ** 2 + (y - c) ** 2) / (grid / 2.0) ** 2
+    return np.sqrt(np.clip(1.0 - rho2[disk_mask(grid)], 0.0, 1.0))
+
+
 def full_disk(grid=4096, seed=1002, clustered=True, active_frac=0.2, r_range=(16.0, 128.0)):
     """Config-2 parameters.  Returns (P [n, 10] float64 in disk row-major
     order, active [n] bool, mask [grid, grid] bool).
