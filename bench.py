@@ -341,16 +341,16 @@ def full_disk(args, ctx, inst, spec, log):
         torch.cuda.synchronize()
         return P, active, noise, obs
 
-    def timed(obs, out, opts, steps):
+    def timed(obs, out, opts, steps, Wt=W):
         for _ in range(args.warmup):
-            vf.invert(ctx, inst, obs, W, opts=opts, out=out)
+            vf.invert(ctx, inst, obs, Wt, opts=opts, out=out)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
         t = time.perf_counter()
         for a, b in ev:
             a.record(stream)
-            vf.invert(ctx, inst, obs, W, opts=opts, out=out)
+            vf.invert(ctx, inst, obs, Wt, opts=opts, out=out)
             b.record(stream)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) * 1e3 / steps
@@ -385,6 +385,28 @@ def full_disk(args, ctx, inst, spec, log):
     alg = c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
     achieved = alg / (ev_ms * 1e-3) / 1e12
 
+    # the same disk with the per-pixel weights of Eqs. 14-15 (mu from the
+    # disk geometry)
+    mu = torch.tensor(wl.disk_mu().astype(np.float32), device=dev)
+    Wpp = vf.stokes_weights(ctx, inst, obs, mu)
+    a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a_ev.record(stream)
+    for _ in range(5):
+        vf.stokes_weights(ctx, inst, obs, mu, out=Wpp)
+    b_ev.record(stream)
+    torch.cuda.synchronize()
+    w_ms = a_ev.elapsed_time(b_ev) / 5
+    ms_w, _ = timed(obs, out, opts, 2, Wt=Wpp)
+    iters_w = out["iters"].cpu().numpy()
+    chi2_w = out["chi2"].cpu().numpy()
+    wI = Wpp[:, 0, 0].cpu().numpy() * 1e-6
+    eq14 = {"weights_ms": round(w_ms, 3), "lm_ms_per_step": round(ms_w, 3),
+            "mean_iters": float(iters_w.mean()), "median_chi2": float(np.median(chi2_w)),
+            "w_I_quantiles_5_50_95": [round(float(np.sqrt(q)), 4)
+                                      for q in np.quantile(wI, [0.05, 0.5, 0.95])]}
+    log("Eq. 14-15 weights: %s" % eq14)
+    del Wpp, mu
+
     del obs
     torch.cuda.empty_cache()
     P_iid, active_iid, _, obs_iid = make(False)
@@ -415,6 +437,7 @@ def full_disk(args, ctx, inst, spec, log):
             "median_chi2": float(np.median(chi2)),
             "frac_chi2_below_2": float(np.mean(chi2 < 2.0)),
         },
+        "eq14_weights": eq14,
         "iid_variant": {"ms_per_step": round(ms_iid, 3),
                         "value": round(n / (ms_iid * 1e-3), 1),
                         "active_fraction": round(float(active_iid.mean()), 5),

@@ -313,6 +313,24 @@ int vfisv_init_combined(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                         const float *stokes, const float *base, float pol_threshold,
                         float *params, float *pol, void *stream);
 
+/* Per-pixel weights of Sect. 4.3 (Eqs. 1, 14, 15) for vfisv_invert with
+ * W_per_pixel = 1: W = w^2 / sigma^2 with w_Q = w_U = w_V = 1 and
+ *   w_I = 0.7778 |I_c(mu) - I_c| + 0.3                              (Eq. 14)
+ *   I_c(mu) = 0.33644 + 1.30590 mu - 1.79238 mu^2 + 2.45050 mu^3
+ *             - 1.89979 mu^4 + 0.59943 mu^5                         (Eq. 15)
+ * where I_c is the pixel's largest observed intensity, in units of the
+ * disk-centre quiet-Sun continuum, and mu (cosine of the heliocentric
+ * angle) is clamped to [0, 1].
+ *   stokes: dev [n][4][n_obs]; mu: dev [n]; sigma: host [4] noise level
+ *   per Stokes parameter (finite, > 0), the same at every sample;
+ *   W: dev [n][4][n_obs] output.
+ * A pixel with non-finite mu or Stokes-I samples gets NaN weights for I
+ * (its inversion then ends with status VFISV_NONFINITE).  Asynchronous on
+ * stream. */
+int vfisv_stokes_weights(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
+                         const float *stokes, const float *mu, const float *sigma, float *W,
+                         void *stream);
+
 /* Work counters of the most recent vfisv_invert or vfisv_invert_batches
  * (synchronises the context's device). */
 int vfisv_get_counters(vfisv_ctx *ctx, vfisv_counters *out);

@@ -77,7 +77,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
            "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
-           "vfisv_init_classical", "vfisv_init_combined")
+           "vfisv_init_classical", "vfisv_init_combined", "vfisv_stokes_weights")
 
 _LIB = None
 
@@ -113,6 +113,8 @@ def lib():
         L.vfisv_invert_batches.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.c_int,
                                            ctypes.POINTER(_Options), _vp]
         L.vfisv_init_classical.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.vfisv_stokes_weights.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp,
+                                           ctypes.POINTER(ctypes.c_float), _vp, _vp]
         L.vfisv_init_combined.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float,
                                           _vp, _vp, _vp]
         L.vfisv_autotune.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
@@ -389,6 +391,24 @@ def autotune(ctx, inst, stokes, W, opts=None, sample=0):
         1 if W.dim() == 3 else 0, ctypes.byref(o),
         int(sample), ctypes.byref(t), _stream(dev)), "vfisv_autotune")
     return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+
+def stokes_weights(ctx, inst, stokes, mu, sigma=(1e-3, 1e-3, 1e-3, 1e-3), out=None):
+    """Per-pixel weights W [n, 4, n_obs] of Eqs. 14-15 (w_I from the
+    pixel's continuum against the centre-to-limb curve at mu [n]; Q, U, V
+    weight one) divided by sigma^2 per Stokes parameter; pass the result to
+    ``invert`` as W."""
+    dev = ctx.device
+    n = _rows(stokes)
+    W = out if out is not None else torch.empty((n, 4, inst.n_obs), device=dev,
+                                                dtype=torch.float32)
+    sig = (ctypes.c_float * 4)(*[float(x) for x in sigma])
+    ctx._check(lib().vfisv_stokes_weights(
+        ctx._h, inst._h, n, _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
+        _ptr(mu, torch.float32, dev, n, name="mu"), sig,
+        _ptr(W, torch.float32, dev, n * 4 * inst.n_obs, name="out"), _stream(dev)),
+        "vfisv_stokes_weights")
+    return W
 
 
 def iter_histogram(ctx, iters, n_bins=51):

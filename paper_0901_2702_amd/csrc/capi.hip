@@ -751,6 +751,36 @@ int vfisv_init_combined(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                     "init_combined");
 }
 
+int vfisv_stokes_weights(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
+                         const float* stokes, const float* mu, const float* sigma, float* W,
+                         void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "stokes_weights: ctx is NULL");
+  int rc = check_inst(ctx, inst, "stokes_weights");
+  if (rc) return rc;
+  if (n < 0) return fail(ctx, VFISV_E_INVALID, "stokes_weights: n < 0");
+  if (!sigma) return fail(ctx, VFISV_E_INVALID, "stokes_weights: sigma is NULL");
+  WeightsArgs a;
+  for (int s = 0; s < 4; ++s) {
+    if (!(sigma[s] > 0.f) || !std::isfinite(sigma[s]))
+      return fail(ctx, VFISV_E_INVALID, "stokes_weights: sigma must be finite and > 0");
+    a.inv_var[s] = 1.0 / ((double)sigma[s] * (double)sigma[s]);
+  }
+  if (n == 0) return VFISV_OK;
+  if (!stokes || !mu || !W) return fail(ctx, VFISV_E_INVALID, "stokes_weights: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  a.stokes = stokes;
+  a.mu = mu;
+  a.n_obs = inst->C.n_obs;
+  a.n = n;
+  a.W = W;
+  const int64_t blocks = (n + 255) / 256;
+  const int64_t cap = (int64_t)ctx->num_cus * 16;
+  e = launch_weights(a, (int)(blocks < cap ? blocks : cap), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stokes_weights launch");
+  return VFISV_OK;
+}
+
 int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "get_counters: ctx is NULL");
   if (!out) return fail(ctx, VFISV_E_INVALID, "get_counters: out is NULL");

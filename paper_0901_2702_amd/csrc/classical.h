@@ -1,5 +1,5 @@
-// Classical initial guess (declarations shared by classical.hip and the
-// C-ABI layer).
+// Per-pixel preparatory kernels: the classical initial guess and the
+// Stokes weights (declarations shared by classical.hip and the C-ABI layer).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,5 +21,16 @@ struct ClassicalArgs {
 };
 
 hipError_t launch_classical(const ClassicalArgs& a, int grid, hipStream_t s);
+
+struct WeightsArgs {
+  const float* stokes;  // [n][4][n_obs]
+  const float* mu;      // [n]
+  int n_obs;
+  int64_t n;
+  double inv_var[4];    // 1 / sigma^2 per Stokes parameter
+  float* W;             // [n][4][n_obs]
+};
+
+hipError_t launch_weights(const WeightsArgs& a, int grid, hipStream_t s);
 
 }  // namespace vfisv

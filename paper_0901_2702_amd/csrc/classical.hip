@@ -122,6 +122,73 @@ __global__ __launch_bounds__(256) void classical_init_kernel(const ClassicalArgs
   }
 }
 
+// Per-pixel weights of Sect. 4.3 (Eqs. 1, 14, 15): W = w^2 / sigma^2 with
+// w_Q = w_U = w_V = 1 and w_I = 0.7778 |I_c(mu) - I_c| + 0.3, where I_c is
+// the pixel's largest observed intensity and I_c(mu) the continuum
+// centre-to-limb polynomial (Neckel & Labs 1994) at mu clamped to [0, 1].
+// Non-finite mu or Stokes-I samples give NaN for the I weights.
+template <int NO>
+__global__ __launch_bounds__(256) void weights_kernel(const WeightsArgs A) {
+  const int no = NO > 0 ? NO : A.n_obs;
+  const float wq = (float)A.inv_var[1], wu = (float)A.inv_var[2], wv = (float)A.inv_var[3];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float* G = A.stokes + i * (int64_t)(4 * no);
+    float Ic = -INFINITY;
+    bool finite = true;
+    if constexpr (NO == 6) {
+      const float4 a = *reinterpret_cast<const float4*>(G);
+      const float2 b = *reinterpret_cast<const float2*>(G + 4);
+      const float v[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        finite = finite && isfinite(v[k]);
+        Ic = fmaxf(Ic, v[k]);
+      }
+    } else {
+      for (int k = 0; k < no; ++k) {
+        finite = finite && isfinite(G[k]);
+        Ic = fmaxf(Ic, G[k]);
+      }
+    }
+    double m = (double)A.mu[i];
+    finite = finite && isfinite(m);
+    m = fmin(fmax(m, 0.0), 1.0);
+    // Eq. 15 by Horner's rule
+    const double icm =
+        0.33644 +
+        m * (1.30590 + m * (-1.79238 + m * (2.45050 + m * (-1.89979 + m * 0.59943))));
+    const double wI = 0.7778 * fabs(icm - (double)Ic) + 0.3;
+    const float WI = finite ? (float)(wI * wI * A.inv_var[0]) : __builtin_nanf("");
+    float* out = A.W + i * (int64_t)(4 * no);
+    if constexpr (NO == 6) {
+      float4* o4 = reinterpret_cast<float4*>(out);
+      o4[0] = make_float4(WI, WI, WI, WI);
+      o4[1] = make_float4(WI, WI, wq, wq);
+      o4[2] = make_float4(wq, wq, wq, wq);
+      o4[3] = make_float4(wu, wu, wu, wu);
+      o4[4] = make_float4(wu, wu, wv, wv);
+      o4[5] = make_float4(wv, wv, wv, wv);
+    } else {
+      for (int k = 0; k < no; ++k) {
+        out[k] = WI;
+        out[no + k] = wq;
+        out[2 * no + k] = wu;
+        out[3 * no + k] = wv;
+      }
+    }
+  }
+}
+
+hipError_t launch_weights(const WeightsArgs& a, int grid, hipStream_t s) {
+  if (a.n_obs == 6 && reinterpret_cast<uintptr_t>(a.stokes) % 16 == 0 &&
+      reinterpret_cast<uintptr_t>(a.W) % 16 == 0)
+    weights_kernel<6><<<grid, 256, 0, s>>>(a);
+  else
+    weights_kernel<0><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_classical(const ClassicalArgs& a, int grid, hipStream_t s) {
   if (a.n_obs == 6 && reinterpret_cast<uintptr_t>(a.stokes) % 16 == 0)
     classical_init_kernel<6><<<grid, 256, 0, s>>>(a);
