@@ -31,12 +31,14 @@ class _Options(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("eps0", ctypes.c_double),
                 ("eps_max", ctypes.c_double), ("rel_tol", ctypes.c_double),
                 ("free_mask", ctypes.c_uint32), ("fixed_iters", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("restarts", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("hess_reuse", ctypes.c_double)]
 
 
 class _Counters(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int64), ("derivs", ctypes.c_int64),
-                ("solves", ctypes.c_int64), ("svd_fallbacks", ctypes.c_int64)]
+                ("solves", ctypes.c_int64), ("svd_fallbacks", ctypes.c_int64),
+                ("hessians", ctypes.c_int64)]
 
 
 _LIB = None
@@ -126,10 +128,11 @@ class Options:
     fixed_iters: int = 0
     restarts: int = 0
     seed: int = 0
+    hess_reuse: float = 0.0
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
-                        self.fixed_iters, self.restarts, self.seed)
+                        self.fixed_iters, self.restarts, self.seed, self.hess_reuse)
 
 
 def faddeeva(u, a):
@@ -238,7 +241,7 @@ def lm_pixel(inst, obs, W, M0=None, opts=None, pixel=0):
                        _i(st), ctypes.byref(cnt))
     return dict(params=M, chi2=float(chi2[0]), iters=int(it[0]), status=int(st[0]),
                 counters=dict(trials=cnt.trials, derivs=cnt.derivs, solves=cnt.solves,
-                              svd_fallbacks=cnt.svd_fallbacks))
+                              svd_fallbacks=cnt.svd_fallbacks, hessians=cnt.hessians))
 
 
 def invert(inst, stokes, W, init=None, opts=None, nthreads=0):
@@ -262,4 +265,4 @@ def invert(inst, stokes, W, init=None, opts=None, nthreads=0):
                             nthreads)
     return dict(params=params, chi2=chi2, iters=iters, status=status, threads=used,
                 counters=dict(trials=cnt.trials, derivs=cnt.derivs, solves=cnt.solves,
-                              svd_fallbacks=cnt.svd_fallbacks))
+                              svd_fallbacks=cnt.svd_fallbacks, hessians=cnt.hessians))

@@ -197,12 +197,12 @@ static int popcount10(uint32_t m) {
 }
 
 /* chi^2 of Eq. 1 and, with J, the normal equations H = J^T W J and
- * g = J^T W r, r = obs - syn. */
+ * g = J^T W r, r = obs - syn (H NULL: the gradient only). */
 static double chi2_and_normal(int rows, const float *obs, const float *W, const double *S,
                               const double *J, double dof, double *H, double *g) {
   double chi = 0.0;
   if (J) {
-    memset(H, 0, sizeof(double) * NP * NP);
+    if (H) memset(H, 0, sizeof(double) * NP * NP);
     memset(g, 0, sizeof(double) * NP);
   }
   for (int r = 0; r < rows; ++r) {
@@ -213,7 +213,8 @@ static double chi2_and_normal(int rows, const float *obs, const float *W, const 
       const double *j = J + (size_t)r * NP;
       for (int p = 0; p < NP; ++p) {
         g[p] += w * res * j[p];
-        for (int q = 0; q < NP; ++q) H[p * NP + q] += w * j[p] * j[q];
+        if (H)
+          for (int q = 0; q < NP; ++q) H[p * NP + q] += w * j[p] * j[q];
       }
     }
   }
@@ -256,6 +257,7 @@ static void lm_pixel_fixed(const orc_instrument *inst, const orc_options *opt,
   orc_project(M);
   orc_forward(inst, M, S, J);
   cnt->derivs++;
+  cnt->hessians++;
   double chi2 = chi2_and_normal(rows, obs, W, S, J, dof, H, g);
   const double chi2_first = chi2;
   memcpy(Mg, M, sizeof M);
@@ -275,6 +277,7 @@ static void lm_pixel_fixed(const orc_instrument *inst, const orc_options *opt,
       orc_project(M);
       orc_forward(inst, M, S, J);
       cnt->derivs++;
+      cnt->hessians++;
       cnt->trials++;
       chi2 = chi2_and_normal(rows, obs, W, S, J, dof, H, g);
       if (isfinite(chi2) && chi2 < chig) {
@@ -294,11 +297,14 @@ static void lm_pixel_fixed(const orc_instrument *inst, const orc_options *opt,
     cnt->trials++;
     const double chi2_t = chi2_and_normal(rows, obs, W, S, NULL, dof, NULL, NULL);
     if (isfinite(chi2_t) && chi2_t < chi2) {
+      /* near the minimum the curvature barely changes: keep H (Sect. 4.4) */
+      const int keep_h = chi2 < opt->hess_reuse;
       memcpy(M, Mt, sizeof M);
       chi2 = chi2_t;
       orc_forward(inst, M, S, J);
       cnt->derivs++;
-      chi2_and_normal(rows, obs, W, S, J, dof, H, g);
+      if (!keep_h) cnt->hessians++;
+      chi2_and_normal(rows, obs, W, S, J, dof, keep_h ? NULL : H, g);
       eps = orc_eps_decrease(eps);
       bad = 0;
       if (chi2 < chig) {
@@ -356,6 +362,7 @@ void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
   /* initial model: synthesis with derivatives */
   orc_forward(inst, M, S, J);
   cnt->derivs++;
+  cnt->hessians++;
   double chi2 = chi2_and_normal(rows, obs, W, S, J, dof, H, g);
   double eps = opt->eps0;
   int status = ORC_MAX_ITER, it = 0;
@@ -375,12 +382,17 @@ void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
       const double chi2_t = chi2_and_normal(rows, obs, W, S, NULL, dof, NULL, NULL);
       if (isfinite(chi2_t) && chi2_t < chi2) {
         const double dec = chi2 - chi2_t;
+        /* Sect. 4.4: when the model the step started from was already near
+         * the minimum (chi^2 below hess_reuse), the Hessian is kept and
+         * only the gradient is rebuilt */
+        const int keep_h = chi2 < opt->hess_reuse;
         memcpy(M, Mt, sizeof M);
         chi2 = chi2_t;
         /* success: derivatives at the new best model */
         orc_forward(inst, M, S, J);
         cnt->derivs++;
-        chi2_and_normal(rows, obs, W, S, J, dof, H, g);
+        if (!keep_h) cnt->hessians++;
+        chi2_and_normal(rows, obs, W, S, J, dof, keep_h ? NULL : H, g);
         eps = orc_eps_decrease(eps);
         if (dec < opt->rel_tol * (chi2 + dec)) {
           status = ORC_CONVERGED;
@@ -506,6 +518,7 @@ int orc_invert(const orc_instrument *inst, const orc_options *opt, int64_t n,
       cnt->derivs += job->cnt[t].derivs;
       cnt->solves += job->cnt[t].solves;
       cnt->svd_fallbacks += job->cnt[t].svd_fallbacks;
+      cnt->hessians += job->cnt[t].hessians;
     }
   }
   free(job);

@@ -64,6 +64,9 @@ typedef struct {
                           model allowed per pixel (triggers (a) and (b) of
                           Sect. 4.2) */
   uint64_t seed;       /* key of the restart perturbations */
+  double hess_reuse;   /* Sect. 4.4: an accepted step from a model whose chi^2
+                          is below this keeps the previous J^T W J and only
+                          rebuilds the gradient; 0 rebuilds every time */
 } orc_options;
 
 typedef struct {
@@ -71,6 +74,8 @@ typedef struct {
   int64_t derivs;       /* syntheses with derivatives (initial + accepted) */
   int64_t solves;       /* damped normal-equation solves */
   int64_t svd_fallbacks;/* solves that needed the eigen/SVD fallback */
+  int64_t hessians;     /* J^T W J built (initial, restarts, accepted steps
+                           not covered by hess_reuse) */
 } orc_counters;
 
 /* Faddeeva function w(u + i a) = H + i F for a >= 0 (Sect. 3.2). */
