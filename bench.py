@@ -98,14 +98,14 @@ def main():
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
     ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity",
-                                           "init-compare"),
+                                           "init-compare", "hess-reuse"),
                     default="learned",
                     help="learned: the learned-start vs plain LM line (default); full-disk: "
                          "plain LM over the 13.2M-pixel disk with clustered active regions; "
                          "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch; "
                          "parity: per-parameter differences from the FP64 oracle on the "
                          "262,144-pixel HMI set; init-compare: default / classical / network "
-                         "starts")
+                         "starts; hess-reuse: plain LM with the Hessian kept near the minimum")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -150,6 +150,8 @@ def main():
         return parity(args, ctx, inst, spec, log)
     if args.workload == "init-compare":
         return init_compare(args, ctx, inst, spec, log)
+    if args.workload == "hess-reuse":
+        return hess_reuse(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
@@ -764,6 +766,53 @@ def init_compare(args, ctx, inst, spec, log):
                                      % (seed, args.train_samples)},
               "starts": result_starts, "fig7_spread_vs_polarisation": fig7,
               "training_seconds": round(tinfo["seconds"], 2)}
+    print(json.dumps(result), flush=True)
+
+
+def hess_reuse(args, ctx, inst, spec, log):
+    """Plain LM with the Hessian kept for steps from models below a chi^2
+    threshold (0 = off), on the 1M held-out HMI pixels and on 100k
+    fine-spectrum pixels: time, work and the fits reached."""
+    import numpy as np
+    import torch
+
+    import paper_0901_2702_amd as vf
+    import workloads as wl
+    dev = ctx.device
+    stream = torch.cuda.current_stream(dev)
+    result = {"metric": "plain LM with the Hessian kept near the minimum", "cases": {}}
+    for name, sp, n, seed in (("hmi", spec, args.n, wl.CONFIGS["cfg3_heldout"]["seed"]),
+                              ("fine", wl.fine_instrument(), 100_000,
+                               wl.CONFIGS["cfg4_fine"]["seed"])):
+        ins = inst if name == "hmi" else vf.Instrument.from_spec(ctx, sp)
+        P = wl.draw_params(n, seed)
+        noise = wl.draw_noise(n, sp.n_obs, seed)
+        obs = vf.synthesize(ctx, ins, torch.tensor(P.astype(np.float32), device=dev),
+                            noise=torch.tensor(noise.astype(np.float32), device=dev))
+        W = torch.tensor(wl.weights(sp.n_obs), device=dev)
+        out = vf.invert(ctx, ins, obs, W)
+        rows = {}
+        for tau in (0.0, 1.2, 2.0, 5.0, 1e300):
+            opts = vf.Options(hess_reuse=tau)
+            vf.invert(ctx, ins, obs, W, opts=opts, out=out)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(3):
+                vf.invert(ctx, ins, obs, W, opts=opts, out=out)
+            b.record(stream)
+            torch.cuda.synchronize()
+            c = ctx.counters()
+            ch, it = out["chi2"].cpu().numpy(), out["iters"].cpu().numpy()
+            rows["inf" if tau > 1e100 else str(tau)] = {
+                "ms": round(a.elapsed_time(b) / 3, 3), "mean_iters": float(it.mean()),
+                "median_chi2": float(np.median(ch)), "frac_chi2_below_2": float(np.mean(ch < 2.0)),
+                "hessians_per_accepted_model": round(c["hessians"] / (c["pixels"] + c["accepts"]),
+                                                     4)}
+            log("%s tau %g: %s" % (name, tau, rows["inf" if tau > 1e100 else str(tau)]))
+        result["cases"][name] = {"pixels": n, "seed": seed, "by_threshold": rows}
+        del obs, out
+        torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
 
 

@@ -136,6 +136,12 @@ typedef struct {
                        /* the damping carries over.                          */
   uint64_t restart_seed; /* offsets: SplitMix64 output (pixel << 16 | k << 4 */
                        /* | parameter) of the stream seeded with this value */
+  double hess_reuse;   /* Sect. 4.4: an accepted step that starts from a    */
+                       /* model with chi^2 below this keeps the previous    */
+                       /* J^T W J and rebuilds only the gradient (the paper */
+                       /* gives no threshold).  0 (default): always rebuilt.*/
+                       /* Changes the results (slower convergence where the */
+                       /* curvature still changes); >= 0.                   */
 } vfisv_options;
 
 /* Result of vfisv_autotune. */
@@ -156,6 +162,8 @@ typedef struct {
   int64_t passes;         /* synthesis passes executed (trials + initial)   */
   int64_t svd_fallbacks;  /* solves that needed the eigen/SVD fallback      */
   int64_t grid_waves;     /* waves launched                                 */
+  int64_t hessians;       /* J^T W J updates: initial, restart and accepted */
+                          /* models, less those kept by hess_reuse          */
 } vfisv_counters;
 
 /* ---- context ---------------------------------------------------------- */

@@ -45,7 +45,8 @@ class _Options(ctypes.Structure):
                 ("free_mask", ctypes.c_uint32), ("grid_waves", ctypes.c_int),
                 ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int),
                 ("voigt", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("restart_seed", ctypes.c_uint64)]
+                ("restarts", ctypes.c_int), ("restart_seed", ctypes.c_uint64),
+                ("hess_reuse", ctypes.c_double)]
 
 
 class _Batch(ctypes.Structure):
@@ -65,7 +66,8 @@ class _Tuning(ctypes.Structure):
 class _Counters(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("trials", ctypes.c_int64),
                 ("accepts", ctypes.c_int64), ("passes", ctypes.c_int64),
-                ("svd_fallbacks", ctypes.c_int64), ("grid_waves", ctypes.c_int64)]
+                ("svd_fallbacks", ctypes.c_int64), ("grid_waves", ctypes.c_int64),
+                ("hessians", ctypes.c_int64)]
 
 
 # Every symbol declared in include/vfisv.h.
@@ -251,11 +253,12 @@ class Options:
     fixed_iters: int = 0
     restarts: int = 0
     restart_seed: int = 0
+    hess_reuse: float = 0.0
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
                         self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt,
-                        self.fixed_iters, self.restarts, self.restart_seed)
+                        self.fixed_iters, self.restarts, self.restart_seed, self.hess_reuse)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):

@@ -66,6 +66,7 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
     return fail(ctx, VFISV_E_INVALID, "options: fixed_iters outside 0..100000");
   if (o.restarts < 0 || o.restarts > 4095)
     return fail(ctx, VFISV_E_INVALID, "options: restarts outside 0..4095");
+  if (!(o.hess_reuse >= 0.0)) return fail(ctx, VFISV_E_INVALID, "options: hess_reuse must be >= 0");
   if (o.voigt != 0 && inst->kind != KIND_DENSE6)
     return fail(ctx, VFISV_E_UNSUPPORTED, "options: the Taylor table serves HMI-shaped instruments");
   if (o.voigt != 0) {
@@ -120,6 +121,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.fixed_iters = o.fixed_iters;
   a.restarts = o.restarts;
   a.seed = (unsigned long long)o.restart_seed;
+  a.hess_reuse = o.hess_reuse;
 }
 
 static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, int kind) {
@@ -313,6 +315,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->fixed_iters = 0;
   o->restarts = 0;
   o->restart_seed = 0;
+  o->hess_reuse = 0.0;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -795,6 +798,7 @@ int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
   out->passes = (int64_t)w[4];
   out->svd_fallbacks = (int64_t)w[5];
   out->grid_waves = (int64_t)w[6];
+  out->hessians = (int64_t)w[7];
   return VFISV_OK;
 }
 

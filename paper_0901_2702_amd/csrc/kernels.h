@@ -51,6 +51,7 @@ struct LMArgs {
   int fixed_iters;  // > 0: fixed-iteration scheme with restarts (else 0)
   int restarts;     // restarts allowed per pixel in that scheme
   unsigned long long seed;  // key of the restart perturbations
+  double hess_reuse;        // keep J^T W J for steps from models below this chi^2
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:

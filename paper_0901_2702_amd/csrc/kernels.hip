@@ -61,7 +61,7 @@ __device__ __forceinline__ double restart_half(int q) {
 }
 
 struct WaveCounters {
-  unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0;
+  unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0, hess = 0;
 };
 
 // One synthesis pass with derivatives at Mc for the pixel's observations:
@@ -72,10 +72,12 @@ struct WaveCounters {
 // until chi^2 decides whether H and g are built.  NOBS = 0: banded filter,
 // rows folded into chi^2, H and g as they complete (H and g are built for
 // every trial, since the rows are gone once chi^2 is known).
+// keep_h: the step starts from a model near the minimum (Sect. 4.4): only g
+// is rebuilt and stored, H stays as it is in LDS.
 template <int NOBS, int LPP, int V>
 __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int64_t pix,
-                                          bool fresh, double chib, float* sHG, int lane,
-                                          bool& accept) {
+                                          bool fresh, double chib, bool keep_h, float* sHG,
+                                          int lane, bool& accept) {
   Pix px;
   pix_setup(Mc, A.C, px);
   RowFactors rf;
@@ -102,7 +104,7 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
     }
     chi *= A.inv_dof;
     accept = fresh || (isfinite(chi) && chi < chib);
-    if (accept) {
+    if (accept && !keep_h) {
       float H[55], g[NPAR];
 #pragma unroll
       for (int e = 0; e < 55; ++e) H[e] = 0.f;
@@ -127,6 +129,24 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
       }
 #pragma unroll
       for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+#pragma unroll
+      for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
+    } else if (accept) {  // H kept: the gradient alone
+      float g[NPAR];
+#pragma unroll
+      for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
+#pragma unroll
+      for (int i = 0; i < NOBS; ++i) {
+        float S[4], J[4][NPAR];
+        assemble_sample<true>(acc[i], A.C.row_sum[i], rf, S, J);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float w = Wp[s * NOBS + i];
+          const float r = obs[s * NOBS + i] - S[s];
+#pragma unroll
+          for (int p = 0; p < NPAR; ++p) g[p] = fmaf(w * J[s][p], r, g[p]);
+        }
+      }
 #pragma unroll
       for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
     }
@@ -159,19 +179,24 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
             const float r = ob[s] - S[s];
             chi = fma((double)w * (double)r, (double)r, chi);
 #pragma unroll
-            for (int p = 0; p < NPAR; ++p) {
-              const float wj = w * J[s][p];
-              g[p] = fmaf(wj, r, g[p]);
+            for (int p = 0; p < NPAR; ++p) g[p] = fmaf(w * J[s][p], r, g[p]);
+            if (!keep_h) {
 #pragma unroll
-              for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+              for (int p = 0; p < NPAR; ++p) {
+                const float wj = w * J[s][p];
+#pragma unroll
+                for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+              }
             }
           }
         });
     chi *= A.inv_dof;
     accept = fresh || (isfinite(chi) && chi < chib);
     if (accept) {
+      if (!keep_h) {
 #pragma unroll
-      for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+        for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+      }
 #pragma unroll
       for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
     }
@@ -305,7 +330,11 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     // ---- synthesis pass with derivatives at Mc ----------------------------
     if (leader) ++wc.pass;
     bool accept = false;
-    const double chi = lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, sHG, lane, accept);
+    // Sect. 4.4: a step from a model already near the minimum keeps H
+    const bool keep_h = !fresh && chib < A.hess_reuse;
+    const double chi =
+        lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, keep_h, sHG, lane, accept);
+    if (leader && accept && !keep_h) ++wc.hess;
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
@@ -428,7 +457,8 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
 __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCounters wc,
                                                int lane) {
   const unsigned long long p = wave_sum(wc.pix), t = wave_sum(wc.trial), a = wave_sum(wc.acc),
-                           s = wave_sum(wc.pass), f = wave_sum(wc.fb);
+                           s = wave_sum(wc.pass), f = wave_sum(wc.fb),
+                           h = wave_sum(wc.hess);
   if (lane == 0) {
     atomicAdd(&work[1], p);
     atomicAdd(&work[2], t);
@@ -436,6 +466,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
     atomicAdd(&work[4], s);
     atomicAdd(&work[5], f);
     atomicAdd(&work[6], 1ull);
+    atomicAdd(&work[7], h);
   }
 }
 
