@@ -106,10 +106,12 @@ typedef struct {
                        /* results do not depend on grid_waves or chunk_log2 */
   int lanes_per_pixel; /* 1 (default) or 2: with 2, HMI-shaped pixels use a  */
                        /* pair of lanes each (half the synthesis points per */
-                       /* lane, ~1.8x faster passes) whenever the grid can   */
-                       /* give every pixel two lanes (at most 65,536 pixels */
-                       /* on MI355X); results then differ from the one-lane */
-                       /* path by float32 rounding of the synthesis sums.    */
+                       /* lane, ~1.8x faster passes) whenever the resident */
+                       /* grid can give every pixel two lanes (at most      */
+                       /* 32,768 pixels on MI355X: 1,024 waves of 64 lanes  */
+                       /* at one wave per SIMD); results then differ from   */
+                       /* the one-lane path by float32 rounding of the      */
+                       /* synthesis sums.                                   */
                        /* The learned path's refit uses pairs when they fit; */
                        /* vfisv_invert_batches keeps one lane per pixel.     */
   int voigt;           /* H and F (Sect. 3.2) by: 0 (default) Weideman's     */
@@ -273,7 +275,8 @@ int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batch
 /* Scheduling autotuner: inverts the first `sample` pixels (<= 0: 131072,
  * at most n) of the caller's data, from the default model with opt's fit
  * settings, with every candidate persistent grid
- * (1, 2, 3, 4, 6 or 8 waves per CU, within the fallback workspace) and
+ * (1, 2, 3, 4, 6 or 8 waves per CU, up to the waves that are resident at
+ * once for the layout's kernel and within the fallback workspace) and
  * pixel-queue block (2^4, 2^8, 2^12 pixels), twice each, timed with HIP
  * events on `stream`, and keeps the fastest for this instrument's layout in
  * the context; later inversions with grid_waves == 0 and chunk_log2 == -1
@@ -438,9 +441,12 @@ int vfisv_mlp_load(vfisv_ctx *ctx, const char *path, vfisv_mlp **out);
 /* Learned-start inversion: the network proposes each pixel's starting
  * model, LM runs at most learned_max_iter trials from it, and every pixel
  * whose reduced chi^2 then exceeds chi2_accept (<= 0: the 0.99 quantile of
- * chi^2_dof / dof) is re-fitted by plain LM from the default model with
- * opt->max_iter trials; the better fit is kept, iters counts the trials of
- * both runs and status gets bit 16 (VFISV_FALLBACK_USED).  Buffers as in
+ * chi^2_dof / dof) is re-fitted by plain LM with opt->max_iter trials from
+ * the paper's combined start (Sect. 5: the network's model with the
+ * classical azimuth, and the weak-field B and gamma below 6 % polarisation,
+ * as vfisv_init_combined; the default model when n_obs < 3); the better
+ * fit is kept, iters counts the trials of both runs and status gets bit 16
+ * (VFISV_FALLBACK_USED).  Buffers as in
  * vfisv_invert (W shared or per pixel); the network must take 4*n_obs
  * inputs.  Library scratch (about 100 bytes per pixel) grows on first use
  * (a synchronising allocation). */

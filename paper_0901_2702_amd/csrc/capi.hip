@@ -96,6 +96,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.row_sums = inst->d_row_sums;
   a.qbase = QUEUE_SLOT0;
   a.lpp_max = 1;
+  a.lane_cap = 0;
   a.stokes = stokes;
   a.W = W;
   a.init = init;
@@ -145,10 +146,11 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   a.lpp_max = lpp_max;
   // with lane pairs the grid is sized for two lanes per pixel (the kernel
   // falls back to one lane per pixel when they do not fit)
-  const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n,
-                           inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
-                                                     : ctx->band_blocks_per_cu, o, inst->kind);
+  const int bpc = inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu : ctx->band_blocks_per_cu;
+  const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n, bpc, o, inst->kind);
   a.ws_stride = (int64_t)grid * 64;
+  const int64_t resident = (int64_t)ctx->num_cus * bpc;
+  a.lane_cap = (long long)(grid < resident ? grid : resident) * 64;
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
   e = launch_lm(a, inst->kind, o.voigt, grid, s);
@@ -659,7 +661,9 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   int cand = 0;
   for (int wi = 0; e == hipSuccess && wi < 6; ++wi) {
     const int64_t gw = (int64_t)ctx->num_cus * waves_per_cu[wi];
-    if (gw > ctx->ws_lanes / 64) continue;
+    // a persistent grid larger than what is resident only adds waves that
+    // start when the work is gone
+    if (gw > ctx->ws_lanes / 64 || waves_per_cu[wi] > bpc_default) continue;
     for (int ci = 0; e == hipSuccess && ci < 3; ++ci) {
       vfisv_options oc = o;
       oc.grid_waves = (int)gw;

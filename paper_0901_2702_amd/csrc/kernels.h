@@ -52,6 +52,7 @@ struct LMArgs {
   int restarts;     // restarts allowed per pixel in that scheme
   unsigned long long seed;  // key of the restart perturbations
   double hess_reuse;        // keep J^T W J for steps from models below this chi^2
+  long long lane_cap;       // lanes of the grid that are resident at once (lane-pair choice)
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:

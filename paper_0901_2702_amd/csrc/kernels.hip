@@ -479,7 +479,8 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   WaveCounters wc;
   if constexpr (NOBS > 0) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
-    if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)gridDim.x * 64ull)
+    // pairs only when every pixel gets two lanes that run at once
+    if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)A.lane_cap)
       lm_loop<NOBS, 2, V, PAPER>(A, sHG, lane, glane, wc);
     else
       lm_loop<NOBS, 1, V, PAPER>(A, sHG, lane, glane, wc);

@@ -28,6 +28,9 @@ struct vfisv_mlp {
 
 namespace {
 
+// polarisation level below which the weak-field B and gamma replace the
+// network's in the combined start (Sect. 5)
+constexpr float COMBINED_POL_THRESHOLD = 0.06f;
 constexpr uint32_t FILE_VERSION = 1;
 const char FILE_MAGIC[8] = {'V', 'F', 'I', 'S', 'V', 'M', 'L', 'P'};
 
@@ -469,12 +472,21 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
   rc = enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, ol, inv_dof,
                   params, chi2, iters, status, s, true);
   if (rc) return rc;
-  // 3. pixels whose fit is not acceptable go to plain LM from the default model
+  // 3. pixels whose fit is not acceptable go to plain LM from the combined
+  // start of Sect. 5 (the proposal with the classical azimuth, and the
+  // weak-field B and gamma where the polarisation is weak), written over the
+  // proposals once the short LM has read them
   e = zero_u64(count, 1, s);
   if (e == hipSuccess) e = fallback_select(chi2, n, tau, list, count, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: fallback selection");
-  rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, nullptr, o, inv_dof, p_fb,
-                  c_fb, i_fb, s_fb, s, false, 2);
+  const bool combined = inst->C.n_obs >= 3;
+  if (combined) {
+    rc = vfisv_init_combined(ctx, inst, n, stokes, init, COMBINED_POL_THRESHOLD, init, nullptr,
+                             stream);
+    if (rc) return rc;
+  }
+  rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, combined ? init : nullptr, o,
+                  inv_dof, p_fb, c_fb, i_fb, s_fb, s, false, 2);
   if (rc) return rc;
   // 4. keep the better of the two fits; flag the pixel
   e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, params, chi2, iters, status, s);

@@ -190,3 +190,45 @@ def test_fine_learned_start_with_448_inputs(ctx):
                                               li.mean(), fb.mean()), flush=True)
     assert li.mean() < 0.8 * pi.mean()
     assert np.median(lc) <= np.median(pc) * 1.01
+
+
+def test_learned_path_structure(ctx, small_trained):
+    """The learned path is: the network's start, at most learned_max_iter
+    LM trials, then for the pixels above the chi^2 threshold a plain LM from
+    the combined start of Sect. 5 (network start, classical azimuth, weak
+    field below 6 % polarisation), keeping the better fit.  Rebuilt here
+    from the separate entry points, it gives the same bits."""
+    spec, inst, net, info = small_trained
+    n = 8192
+    P = wl.draw_params(n, 14)
+    noise = wl.draw_noise(n, 6, 14)
+    dev = ctx.device
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                        noise=torch.tensor(noise.astype(np.float32), device=dev))
+    W = torch.tensor(wl.weights(6), device=dev)
+    tau = 2.08
+    lrn = {k: v.cpu().numpy() for k, v in learned.invert_learned(
+        ctx, inst, net, obs.view(n, 24), W, learned_max_iter=15, chi2_accept=tau).items()}
+    _, start = net.forward(obs.view(n, 24), codes=False)
+    short = {k: v.cpu().numpy() for k, v in vf.invert(
+        ctx, inst, obs, W, init=start, opts=vf.Options(max_iter=15)).items()}
+    sel = np.flatnonzero(short["chi2"] > tau)
+    print("[gpu] learned path: %d of %d refitted" % (len(sel), n), flush=True)
+    assert 0 < len(sel) < n // 2
+    comb, _ = vf.init_combined(ctx, inst, obs, start, 0.06)
+    ts = torch.tensor(sel, device=dev)
+    refit = {k: v.cpu().numpy() for k, v in vf.invert(
+        ctx, inst, obs[ts].contiguous(), W, init=comb[ts].contiguous(),
+        opts=vf.Options(lanes_per_pixel=2)).items()}
+    keep = np.ones(n, bool)
+    keep[sel] = False
+    for k in ("params", "chi2", "iters"):
+        assert np.array_equal(lrn[k][keep], short[k][keep]), k
+    assert np.array_equal(lrn["status"][keep], short["status"][keep])
+    better = refit["chi2"] < short["chi2"][sel]
+    np.testing.assert_array_equal(lrn["chi2"][sel], np.where(better, refit["chi2"],
+                                                             short["chi2"][sel]))
+    np.testing.assert_array_equal(lrn["params"][sel], np.where(better[:, None], refit["params"],
+                                                               short["params"][sel]))
+    np.testing.assert_array_equal(lrn["iters"][sel], short["iters"][sel] + refit["iters"])
+    assert np.all(lrn["status"][sel] & vf.FALLBACK_USED)
