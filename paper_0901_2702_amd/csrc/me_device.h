@@ -128,21 +128,33 @@ __device__ __forceinline__ void pix_setup(const float* M, const Consts& C, Pix& 
 //   w = 1/(sqrt(pi) (L - iz)) + 2/(L - iz)^2 sum_{n=0}^{N-1} a_{n+1} Z^n,
 //   Z = (L + iz)/(L - iz).
 // With den = L - iz = (L + a) - iu:  Z = ((L^2 - a^2 - u^2) + i 2Lu)/|den|^2.
+// The polynomial has real coefficients c_k = 2 a_{k+1}, so it is evaluated
+// by the second-order recurrence for division by the real quadratic
+// (x - Z)(x - conj Z) = x^2 - r x + s (r = 2 Re Z, s = |Z|^2):
+//   b_{N-1} = c_{N-1}, b_k = c_k + r b_{k+1} - s b_{k+2},
+//   p(Z) = b_1 Z + c_0 - s b_2,
+// two real FMAs per coefficient instead of a complex multiply-add (four);
+// in float32 its error matches complex Horner's over a in [0, 5], |u| <= 40
+// (both are dominated by the series' own 6e-7 truncation error).
 __device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C, float& H,
                                          float& F) {
   const float D = fmaf(u, u, p.denr2);
   const float rD = frcp(D);
   const float Zr = fmaf(-u, u, p.c0) * rD;
   const float Zi = C.w2L * u * rD;
-  float pr = fmaf(C.wc[NW], Zr, C.wc[NW - 1]);
-  float pi = C.wc[NW] * Zi;
+  const float r = 2.f * Zr;
+  const float s = fmaf(Zr, Zr, Zi * Zi);
+  // c_k = wc[k + 1]
+  float b2 = C.wc[NW];
+  float b1 = fmaf(r, b2, C.wc[NW - 1]);
 #pragma unroll
-  for (int n = NW - 2; n >= 1; --n) {
-    const float nr = fmaf(pr, Zr, fmaf(-pi, Zi, C.wc[n]));
-    const float ni = fmaf(pr, Zi, pi * Zr);
-    pr = nr;
-    pi = ni;
+  for (int k = NW - 3; k >= 1; --k) {
+    const float b0 = fmaf(r, b1, fmaf(-s, b2, C.wc[k + 1]));
+    b2 = b1;
+    b1 = b0;
   }
+  const float pr = fmaf(b1, Zr, fmaf(-s, b2, C.wc[1]));
+  const float pi = b1 * Zi;
   const float idr = p.denr * rD, idi = u * rD;  // 1/den
   const float qr = fmaf(pr, idr, fmaf(-pi, idi, INV_SQRT_PI));
   const float qi = fmaf(pr, idi, pi * idr);
