@@ -361,8 +361,14 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   for (int i = 0; i < NOBS; ++i)
 #pragma unroll
     for (int m = 0; m < NACC; ++m) acc[i][m] = 0.f;
-  for (int k = 0; k < C.n_pts; ++k) {
-    const Point P = load_uniform(pts, k);  // wave-uniform: scalar loads
+  // wave-uniform records through the scalar cache, each loaded one point
+  // ahead so that its latency hides behind the current point's arithmetic
+  // (one wave per SIMD has nothing else to issue meanwhile)
+  const int last = C.n_pts - 1;
+  if (last < 0) return;  // no synthesis point carries a tap
+  Point P = load_uniform(pts, 0);
+  for (int k = 0; k <= last; ++k) {
+    const Point Pn = load_uniform(pts, k < last ? k + 1 : last);
     float c[NACC];
     point_contrib<DERIV, V>(P.dl, p, C, c);
     const uint32_t mask = __float_as_uint(P.w[6]);
@@ -374,6 +380,7 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
         for (int m = 0; m < NC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
       }
     }
+    P = Pn;
   }
 }
 
