@@ -34,7 +34,7 @@ PEAK_FP32_TFLOPS = 157.3
 # Algorithmic float32 work per unit, counted from the formula sequence of the
 # synthesis: per synthesis point, per filter tap, per observed sample, plus
 # the float64 solve.
-FLOP_POINT_VALUES = 431      # 3 Faddeeva (124 each), absorption matrix, UR, mixing
+FLOP_POINT_VALUES = 317      # 3 Faddeeva (86 each), absorption matrix, UR, mixing
 FLOP_POINT_JAC_EXTRA = 379   # Eqs. 8-9, element and parameter tangents
 FLOP_TAP_VALUES = 8          # 4 normalised Stokes values per tap
 FLOP_TAP_JAC = 58            # 29 accumulators per tap
