@@ -387,7 +387,8 @@ int vfisv_solve(vfisv_ctx *ctx, int64_t n, const float *H, const float *g,
 typedef struct vfisv_mlp vfisv_mlp;
 
 /* New network with He-initialised weights (seeded).  Host arrays are
- * copied.  Errors: VFISV_E_INVALID (n_in outside 1..4096, non-finite or
+ * copied.  Errors: VFISV_E_INVALID (n_in outside 1..1248, the widest input
+ * whose 64-row activation tile fits the workgroup's LDS; non-finite or
  * non-positive std), VFISV_E_NOMEM. */
 int vfisv_mlp_create(vfisv_ctx *ctx, int n_in, const float *in_mean, const float *in_std,
                      const float *out_mean, const float *out_std, uint64_t seed,

@@ -77,7 +77,10 @@ hipError_t mlp_forward(const MlpDev& net, MlpWork& w, int64_t M, const float* st
 hipError_t mlp_decode(const MlpDev& net, const float* Y4, int64_t M, float* codes,
                       float* params, hipStream_t s);
 // Fused inference (inputs -> decoded codes/params in one kernel); LDS bytes
-// it needs for an input width K0.
+// it needs for an input width K0.  The widest input it serves keeps its
+// 64-row tile within the 160 KB of LDS of a workgroup.
+constexpr int MLP_LDS_MAX = 160 * 1024;
+constexpr int MLP_MAX_IN = 1248;  // K0 + 8 padded columns, 64 rows, bf16
 hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* codes,
                      float* params, hipStream_t s);
 size_t mlp_infer_lds_bytes(int K0);

@@ -311,8 +311,11 @@ __global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
 // (bfloat16, rows padded by 8 elements so that the 16 rows an MFMA operand
 // reads fall in different banks; each layer finishes reading the tile before
 // any wave overwrites it with the layer's outputs), weights are read as MFMA
-// operands from L2, and the outputs are decoded in place.  Wave w owns hidden columns [64 w, 64 w + 64)
-// and output rows [16 w, 16 w + 16).  The MFMA sequence per output element
+// operands from L2, and the outputs are decoded in place.  Wave w owns
+// hidden columns [64 w, 64 w + 64) and output rows [16 w, 16 w + 16).
+// (128-row tiles would halve the weight reads but need 335 registers per
+// lane, one wave per SIMD: measured 1.5x slower.)  The MFMA sequence per
+// output element
 // (same instruction, same k order, same epilogue) is that of gemm_abt, so
 // the results equal those of the layer-by-layer path.
 constexpr int FT = 64;
@@ -421,6 +424,9 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const MlpInferArgs a) {
   }
 }
 
+static_assert(MLP_MAX_IN % 32 == 0 && FT * (MLP_MAX_IN + 8) * 2 <= MLP_LDS_MAX,
+              "the widest input must fit a tile");
+
 size_t mlp_infer_lds_bytes(int K0) {
   const int ldx = K0 + 8, ld = ldx > LDH ? ldx : LDH;
   const size_t tile = sizeof(bf16) * (size_t)FT * ld;
@@ -446,6 +452,12 @@ hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* c
   a.out_std = net.out_std;
   a.codes = codes;
   a.params = params;
+  // tiles of wide inputs exceed the 64 KB default of dynamic LDS and need
+  // the kernel attribute (gfx950 has 160 KB per workgroup); set once per
+  // process, before the first launch (not a stream operation)
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void*)mlp_infer_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MLP_LDS_MAX);
+  if (attr != hipSuccess) return attr;
   const size_t lds = mlp_infer_lds_bytes(L.K0);
   mlp_infer_kernel<<<(unsigned)((M + FT - 1) / FT), 256, lds, s>>>(a);
   return hipGetLastError();

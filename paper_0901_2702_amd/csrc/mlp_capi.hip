@@ -100,7 +100,8 @@ void free_dev(MlpDev& d) {
 int build(vfisv_ctx* ctx, int n_in, const float* in_mean, const float* in_std,
           const float* out_mean, const float* out_std, const float* params, uint64_t seed,
           vfisv_mlp** out) {
-  if (n_in < 1 || n_in > 4096) return fail(ctx, VFISV_E_INVALID, "mlp: n_in must be 1..4096");
+  if (n_in < 1 || n_in > MLP_MAX_IN)
+    return fail(ctx, VFISV_E_INVALID, "mlp: n_in must be 1.." + std::to_string(MLP_MAX_IN));
   if (!in_mean || !in_std || !out_mean || !out_std)
     return fail(ctx, VFISV_E_INVALID, "mlp: NULL normalisation");
   for (int k = 0; k < n_in; ++k)
@@ -380,7 +381,7 @@ int vfisv_mlp_load(vfisv_ctx* ctx, const char* path, vfisv_mlp** out) {
   uint64_t total = 0, h_file = 0;
   bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, FILE_MAGIC, 8) == 0 &&
             std::fread(&ver, 4, 1, f) == 1 && ver == FILE_VERSION &&
-            std::fread(&n_in, 4, 1, f) == 1 && n_in >= 1 && n_in <= 4096 &&
+            std::fread(&n_in, 4, 1, f) == 1 && n_in >= 1 && n_in <= MLP_MAX_IN &&
             std::fread(&total, 8, 1, f) == 1 && (int64_t)total == mlp_layout((int)n_in).total;
   std::vector<float> im, is, om(7), os(7), params;
   if (ok) {

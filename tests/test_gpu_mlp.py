@@ -59,7 +59,7 @@ def _random_net(ctx, n_in, seed):
     return net, flat, in_mean, in_std
 
 
-@pytest.mark.parametrize("n_in", [24, 448])
+@pytest.mark.parametrize("n_in", [24, 448, 1248])
 def test_forward_matches_oracle(ctx, n_in):
     net, flat, mean, std = _random_net(ctx, n_in, 1)
     x = (np.random.default_rng(2).normal(size=(1000, n_in)) * std + mean).astype(np.float32)
@@ -100,6 +100,14 @@ def test_gradient_matches_oracle(ctx, n_in):
     gf = g.cpu().numpy()
     K0 = (n_in + 31) // 32 * 32
     assert np.all(gf[n_in * H:K0 * H] == 0.0)
+
+
+def test_input_width_limit(ctx):
+    """The fused inference keeps a 64-row tile of the inputs in LDS: 1248
+    inputs are the widest it serves (test_forward_matches_oracle covers
+    them); a wider network is refused at creation."""
+    with pytest.raises(vf.VfisvError):
+        learned.Mlp(ctx, 1249, np.zeros(1249), np.ones(1249), np.zeros(7), np.ones(7))
 
 
 def test_save_load_round_trip(ctx):
