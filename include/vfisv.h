@@ -434,6 +434,60 @@ int vfisv_mlp_train_step(vfisv_ctx *ctx, vfisv_mlp *mlp, const float *stokes,
  * (synchronising; resets the sum). */
 int vfisv_mlp_take_loss(vfisv_mlp *mlp, double *sum_sq);
 
+/* Normalisation of a training set (Sect. 5 trains on synthetic, filtered,
+ * noisy profiles): per input column the mean and standard deviation of
+ * stokes [n][n_in], per code 3..9 (v .. alpha, coded as they are) those of
+ * params [n][10]; population deviations, floored at 1e-6.  Pass them to
+ * vfisv_mlp_create.  stokes, params: dev float32; outputs: host [n_in] and
+ * [7].  n >= 2, 1 <= n_in <= 1248.  Allocates and synchronises. */
+int vfisv_mlp_stats(vfisv_ctx *ctx, int64_t n, int n_in, const float *stokes,
+                    const float *params, float *in_mean, float *in_std, float *out_mean,
+                    float *out_std, void *stream);
+
+/* Training run of Sect. 5: the network learns the models from the
+ * profiles and training stops when the error on a separate control set
+ * rises.  Targets are the standardised codes of params (the field vector
+ * (B cos g, B sin g cos 2 psi, B sin g sin 2 psi) / 3000, then v .. alpha
+ * standardised with the network's output normalisation).  Each epoch visits
+ * the training rows in a fresh random order (Fisher-Yates shuffle driven by
+ * SplitMix64 seeded with seed + epoch) in batches of `batch` rows (the
+ * last partial batch is dropped), one Adam step per batch with a cosine
+ * learning rate from lr down to lr * min_lr_frac over the whole run; after
+ * each epoch the control error (mean squared code error) is measured.  The
+ * weights of the epoch with the lowest control error are kept; the run
+ * stops early once the control error is 2% above that best and the best
+ * is 3 or more epochs old.  The Adam state is left as the last step made it. */
+typedef struct {
+  const float *stokes;       /* dev [n][n_in] training profiles           */
+  const float *params;       /* dev [n][10] their models (API units)      */
+  int64_t n;                 /* >= batch                                   */
+  const float *ctrl_stokes;  /* dev [n_ctrl][n_in] control profiles       */
+  const float *ctrl_params;  /* dev [n_ctrl][10]                          */
+  int64_t n_ctrl;            /* >= 1                                       */
+  int epochs;                /* >= 1                                       */
+  int batch;                 /* positive multiple of 32, <= 2^20           */
+  float lr;                  /* > 0                                        */
+  float min_lr_frac;         /* in (0, 1]                                  */
+  uint64_t seed;             /* shuffle key                                */
+} vfisv_train_spec;
+
+typedef struct {
+  int epochs_run;            /* epochs completed                           */
+  int best_epoch;            /* epoch whose weights were kept (from 0)     */
+  double best_control_mse;   /* its control error                          */
+  int64_t steps;             /* Adam steps made                            */
+} vfisv_train_report;
+
+/* Runs the training on `stream` (synchronising at every epoch end); the
+ * network ends with the best epoch's weights.  train_mse and control_mse
+ * (host [spec->epochs], or NULL) receive each completed epoch's mean
+ * squared code error on the training batches and on the control set.
+ * Allocates scratch for the run (about 50 bytes per training row) and
+ * frees it before returning. */
+int vfisv_mlp_train(vfisv_ctx *ctx, vfisv_mlp *mlp, const vfisv_train_spec *spec,
+                    vfisv_train_report *report, double *train_mse, double *control_mse,
+                    void *stream);
+
 /* Versioned binary file (magic, version, sizes, normalisation, parameters,
  * FNV-1a checksum).  load rejects other versions and bad checksums. */
 int vfisv_mlp_save(vfisv_mlp *mlp, const char *path);

@@ -74,7 +74,7 @@ class _Counters(ctypes.Structure):
 EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_instrument_create", "vfisv_instrument_info_get", "vfisv_instrument_destroy",
            "vfisv_options_default", "vfisv_synthesize", "vfisv_invert", "vfisv_get_counters",
-           "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params", "vfisv_mlp_num_inputs",
+           "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params", "vfisv_mlp_num_inputs", "vfisv_mlp_stats", "vfisv_mlp_train",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",

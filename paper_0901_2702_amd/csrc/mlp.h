@@ -91,6 +91,20 @@ hipError_t mlp_adam(const MlpDev& net, const MlpWork& w, float lr, float beta1, 
 hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t s);
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t s);
 
+// Training-set preparation and the control-set error (the training loop of
+// vfisv_mlp_train).  col_moments adds, for columns col0 .. col0 + ncols - 1
+// of the row-major X [n][ld], the sum and the sum of squares of each column
+// into sums[2 c], sums[2 c + 1] (float64; sums must start at zero).
+hipError_t col_moments(const float* X, int64_t n, int ld, int col0, int ncols, double* sums,
+                       hipStream_t s);
+// Standardised codes T [n][10] of the models P [n][10] (API units): the
+// field vector (B cos g, B sin g cos 2 psi, B sin g sin 2 psi) / 3000, then
+// (v .. alpha - out_mean) / out_std.
+hipError_t encode_targets(const float* P, int64_t n, const float* out_mean, const float* out_std,
+                          float* T, hipStream_t s);
+// out[0] += sum over count values of (A - B)^2, in float64.
+hipError_t sq_diff_sum(const float* A, const float* B, int64_t count, double* out, hipStream_t s);
+
 // Learned-start helpers for the inversion.
 hipError_t fallback_select(const double* chi2, int64_t n, double tau, int32_t* list,
                            unsigned long long* count, hipStream_t s);

@@ -569,6 +569,111 @@ hipError_t zero_u64(unsigned long long* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- training-set preparation --------------------------------------------
+
+// Each block takes MOM_ROWS consecutive rows.  With fewer than 256 columns
+// thread t owns column t % ncols and every (256 / ncols)-th row from
+// t / ncols, so that consecutive threads read consecutive elements; with
+// more, thread t owns columns t, t + 256, ...  Sums stay in registers, then
+// go to LDS and to the global float64 accumulators once per block.
+constexpr int MOM_ROWS = 2048;
+
+__global__ __launch_bounds__(256) void col_moments_kernel(const float* __restrict__ X, int64_t n,
+                                                          int ld, int col0, int ncols,
+                                                          double* sums) {
+  extern __shared__ double acc[];  // [2 * ncols]
+  const int t = threadIdx.x;
+  for (int c = t; c < 2 * ncols; c += blockDim.x) acc[c] = 0.0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * MOM_ROWS;
+  const int rows = (int)(n - r0 < MOM_ROWS ? n - r0 : MOM_ROWS);
+  if (ncols < 256) {
+    const int tpc = 256 / ncols;
+    if (t < tpc * ncols) {
+      const int c = t % ncols;
+      double s1 = 0.0, s2 = 0.0;
+      for (int r = t / ncols; r < rows; r += tpc) {
+        const double x = (double)X[(r0 + r) * ld + col0 + c];
+        s1 += x;
+        s2 += x * x;
+      }
+      atomicAdd(&acc[2 * c], s1);
+      atomicAdd(&acc[2 * c + 1], s2);
+    }
+  } else {
+    for (int c = t; c < ncols; c += 256) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int r = 0; r < rows; ++r) {
+        const double x = (double)X[(r0 + r) * ld + col0 + c];
+        s1 += x;
+        s2 += x * x;
+      }
+      acc[2 * c] += s1;  // this thread alone owns column c
+      acc[2 * c + 1] += s2;
+    }
+  }
+  __syncthreads();
+  for (int c = t; c < 2 * ncols; c += blockDim.x) atomicAdd(&sums[c], acc[c]);
+}
+
+hipError_t col_moments(const float* X, int64_t n, int ld, int col0, int ncols, double* sums,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  col_moments_kernel<<<blocks_for(n, MOM_ROWS), 256, sizeof(double) * 2 * ncols, s>>>(
+      X, n, ld, col0, ncols, sums);
+  return hipGetLastError();
+}
+
+__global__ void encode_targets_kernel(const float* __restrict__ P, int64_t n,
+                                      const float* __restrict__ out_mean,
+                                      const float* __restrict__ out_std, float* T) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const float* p = P + m * NPAR;
+  float* t = T + m * MLP_NCODE;
+  const float g = p[1] * (float)(3.14159265358979323846 / 180.0);
+  const float p2 = p[2] * (float)(3.14159265358979323846 / 90.0);
+  const float b = p[0] * (1.f / 3000.f);
+  t[0] = b * cosf(g);
+  t[1] = b * sinf(g) * cosf(p2);
+  t[2] = b * sinf(g) * sinf(p2);
+#pragma unroll
+  for (int c = 3; c < MLP_NCODE; ++c) t[c] = (p[c] - out_mean[c - 3]) / out_std[c - 3];
+}
+
+hipError_t encode_targets(const float* P, int64_t n, const float* out_mean, const float* out_std,
+                          float* T, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  encode_targets_kernel<<<blocks_for(n, 256), 256, 0, s>>>(P, n, out_mean, out_std, T);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void sq_diff_sum_kernel(const float* __restrict__ A,
+                                                          const float* __restrict__ B,
+                                                          int64_t count, double* out) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)A[i] - (double)B[i];
+    v += d * d;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+hipError_t sq_diff_sum(const float* A, const float* B, int64_t count, double* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  sq_diff_sum_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(A, B, count, out);
+  return hipGetLastError();
+}
+
 hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* targets,
                         const int32_t* rows, hipStream_t s) {
   const MlpLayout& L = net.L;

@@ -340,6 +340,203 @@ int vfisv_mlp_take_loss(vfisv_mlp* m, double* sum_sq) {
   return VFISV_OK;
 }
 
+int vfisv_mlp_stats(vfisv_ctx* ctx, int64_t n, int n_in, const float* stokes,
+                    const float* params, float* in_mean, float* in_std, float* out_mean,
+                    float* out_std, void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_stats: ctx is NULL");
+  if (n < 2) return fail(ctx, VFISV_E_INVALID, "mlp_stats: n must be >= 2");
+  if (n_in < 1 || n_in > MLP_MAX_IN)
+    return fail(ctx, VFISV_E_INVALID, "mlp_stats: n_in must be 1.." + std::to_string(MLP_MAX_IN));
+  if (!stokes || !params || !in_mean || !in_std || !out_mean || !out_std)
+    return fail(ctx, VFISV_E_INVALID, "mlp_stats: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int nsum = 2 * (n_in + 7);
+  double* d = nullptr;
+  e = dalloc(&d, nsum);
+  if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "mlp_stats: scratch");
+  std::vector<double> h((size_t)nsum);
+  e = zero_u64((unsigned long long*)d, nsum, s);
+  if (e == hipSuccess) e = col_moments(stokes, n, n_in, 0, n_in, d, s);
+  if (e == hipSuccess) e = col_moments(params, n, NPAR, 3, 7, d + 2 * n_in, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(double) * nsum, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(d);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_stats");
+  auto moments = [&](int c, float* mean, float* sd) {
+    const double mu = h[2 * (size_t)c] / (double)n;
+    const double var = h[2 * (size_t)c + 1] / (double)n - mu * mu;
+    *mean = (float)mu;
+    *sd = (float)std::fmax(std::sqrt(std::fmax(var, 0.0)), 1e-6);
+  };
+  for (int c = 0; c < n_in; ++c) moments(c, &in_mean[c], &in_std[c]);
+  for (int c = 0; c < 7; ++c) moments(n_in + c, &out_mean[c], &out_std[c]);
+  for (int c = 0; c < n_in; ++c)
+    if (!std::isfinite(in_mean[c]) || !std::isfinite(in_std[c]))
+      return fail(ctx, VFISV_E_INVALID, "mlp_stats: non-finite training profiles");
+  for (int c = 0; c < 7; ++c)
+    if (!std::isfinite(out_mean[c]) || !std::isfinite(out_std[c]))
+      return fail(ctx, VFISV_E_INVALID, "mlp_stats: non-finite training models");
+  return VFISV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// SplitMix64 (Steele, Lea and Flood 2014): output number c of the stream
+// seeded with seed.
+uint64_t splitmix64(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Fisher-Yates shuffle of 0 .. n-1; the draw for position i is an integer
+// in [0, i] taken from the high bits of a 64x64-bit product.
+void shuffle(int32_t* p, int64_t n, uint64_t key) {
+  for (int64_t i = 0; i < n; ++i) p[i] = (int32_t)i;
+  for (int64_t i = n - 1; i > 0; --i) {
+    const unsigned __int128 prod =
+        (unsigned __int128)splitmix64(key, (uint64_t)i) * (unsigned __int128)(uint64_t)(i + 1);
+    const int64_t j = (int64_t)(prod >> 64);
+    const int32_t t = p[i];
+    p[i] = p[j];
+    p[j] = t;
+  }
+}
+
+struct TrainScratch {
+  float *T = nullptr, *Tc = nullptr, *codes = nullptr, *best = nullptr;
+  int32_t* perm = nullptr;
+  double* acc = nullptr;
+  int32_t* host[2] = {nullptr, nullptr};
+  ~TrainScratch() {
+    hipFree(T);
+    hipFree(Tc);
+    hipFree(codes);
+    hipFree(best);
+    hipFree(perm);
+    hipFree(acc);
+    for (int k = 0; k < 2; ++k)
+      if (host[k]) hipHostFree(host[k]);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int vfisv_mlp_train(vfisv_ctx* ctx, vfisv_mlp* m, const vfisv_train_spec* sp,
+                    vfisv_train_report* report, double* train_mse, double* control_mse,
+                    void* stream) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_train: ctx is NULL");
+  int rc = check_mlp(ctx, m, "mlp_train");
+  if (rc) return rc;
+  if (!sp) return fail(ctx, VFISV_E_INVALID, "mlp_train: spec is NULL");
+  if (!sp->stokes || !sp->params || !sp->ctrl_stokes || !sp->ctrl_params)
+    return fail(ctx, VFISV_E_INVALID, "mlp_train: NULL buffer");
+  if (sp->batch <= 0 || sp->batch % 32 != 0 || sp->batch > (1 << 20))
+    return fail(ctx, VFISV_E_INVALID, "mlp_train: batch must be a positive multiple of 32");
+  if (sp->n < sp->batch || sp->n > INT32_MAX)
+    return fail(ctx, VFISV_E_INVALID, "mlp_train: n must be in batch .. 2^31 - 1");
+  if (sp->n_ctrl < 1) return fail(ctx, VFISV_E_INVALID, "mlp_train: n_ctrl must be >= 1");
+  if (sp->epochs < 1) return fail(ctx, VFISV_E_INVALID, "mlp_train: epochs must be >= 1");
+  if (!(sp->lr > 0.f) || !std::isfinite(sp->lr) || !(sp->min_lr_frac > 0.f) ||
+      !(sp->min_lr_frac <= 1.f))
+    return fail(ctx, VFISV_E_INVALID, "mlp_train: lr > 0 and min_lr_frac in (0, 1] needed");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  rc = ensure_train(m, sp->batch);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const MlpLayout& L = m->dev.L;
+  const int64_t n = sp->n, nc = sp->n_ctrl;
+  TrainScratch w;
+  e = dalloc(&w.T, n * MLP_NCODE);
+  if (e == hipSuccess) e = dalloc(&w.Tc, nc * MLP_NCODE);
+  if (e == hipSuccess) e = dalloc(&w.codes, nc * MLP_NCODE);
+  if (e == hipSuccess) e = dalloc(&w.best, L.total);
+  if (e == hipSuccess) e = dalloc(&w.perm, n);
+  if (e == hipSuccess) e = dalloc(&w.acc, 1);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipHostMalloc((void**)&w.host[k], sizeof(int32_t) * (size_t)n, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "mlp_train: scratch");
+  e = encode_targets(sp->params, n, m->dev.out_mean, m->dev.out_std, w.T, s);
+  if (e == hipSuccess) e = encode_targets(sp->ctrl_params, nc, m->dev.out_mean, m->dev.out_std, w.Tc, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: targets");
+  // any loss left from earlier steps is not this run's
+  double dummy = 0.0;
+  rc = vfisv_mlp_take_loss(m, &dummy);
+  if (rc) return rc;
+
+  const int64_t steps_per_epoch = n / sp->batch;
+  const int64_t total = (int64_t)sp->epochs * steps_per_epoch;
+  const double pi = 3.14159265358979323846;
+  double best = INFINITY;
+  int best_ep = -1, ep = 0, cur = 0;
+  int64_t step = 0;
+  shuffle(w.host[cur], n, sp->seed);
+  for (; ep < sp->epochs; ++ep) {
+    e = hipMemcpyAsync(w.perm, w.host[cur], sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: order upload");
+    for (int64_t b = 0; b < steps_per_epoch; ++b, ++step) {
+      const double frac = total > 1 ? (double)step / (double)(total - 1) : 0.0;
+      const double f = sp->min_lr_frac + (1.0 - sp->min_lr_frac) * 0.5 * (1.0 + std::cos(pi * frac));
+      const int32_t* rows = w.perm + b * sp->batch;
+      e = mlp_forward(m->dev, m->train, sp->batch, sp->stokes, rows, true, s);
+      if (e == hipSuccess) e = mlp_backward(m->dev, m->train, sp->batch, w.T, rows, s);
+      if (e == hipSuccess)
+        e = mlp_adam(m->dev, m->train, (float)(sp->lr * f), 0.9f, 0.999f, 1e-8f, m->step + 1, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: step");
+      m->step += 1;
+    }
+    // the next epoch's order is drawn on the host while this one runs
+    if (ep + 1 < sp->epochs) shuffle(w.host[1 - cur], n, sp->seed + (uint64_t)(ep + 1));
+    double sum_sq = 0.0;
+    rc = vfisv_mlp_take_loss(m, &sum_sq);
+    if (rc) return rc;
+    e = zero_u64((unsigned long long*)w.acc, 1, s);
+    if (e == hipSuccess) e = mlp_infer(m->dev, nc, sp->ctrl_stokes, w.codes, nullptr, s);
+    if (e == hipSuccess) e = sq_diff_sum(w.codes, w.Tc, nc * MLP_NCODE, w.acc, s);
+    double csum = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&csum, w.acc, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: control error");
+    const double tr = sum_sq / ((double)steps_per_epoch * sp->batch * MLP_NCODE);
+    const double ce = csum / ((double)nc * MLP_NCODE);
+    if (train_mse) train_mse[ep] = tr;
+    if (control_mse) control_mse[ep] = ce;
+    if (ce < best) {
+      best = ce;
+      best_ep = ep;
+      e = hipMemcpyAsync(w.best, m->dev.master, sizeof(float) * (size_t)L.total,
+                         hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: keep best");
+    } else if (!(ce <= best * 1.02) && ep - best_ep >= 3) {
+      ++ep;  // the control error is rising: stop
+      break;
+    }
+    cur = 1 - cur;
+  }
+  if (best_ep >= 0) {
+    e = hipMemcpyAsync(m->dev.master, w.best, sizeof(float) * (size_t)L.total,
+                       hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = mlp_refresh_bf16(m->dev, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train: restore best");
+  if (report) {
+    report->epochs_run = ep;
+    report->best_epoch = best_ep;
+    report->best_control_mse = best;
+    report->steps = step;
+  }
+  return VFISV_OK;
+}
+
 int vfisv_mlp_save(vfisv_mlp* m, const char* path) {
   if (!m || !path) return VFISV_E_INVALID;
   const MlpLayout& L = m->dev.L;

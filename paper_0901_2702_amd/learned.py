@@ -1,13 +1,12 @@
-"""Learned initialiser: binding of the network entry points of libvfisv.so
-and the training loop that drives them.
+"""Learned initialiser: binding of the network entry points of libvfisv.so.
 
-The network, its kernels and the optimiser live in the library; this module
-marshals device pointers and streams, draws the training set's random
-parameters on the host (seeded numpy), and runs the epoch / early-stopping
-loop of Sect. 5 (stop when the control-set error rises).
+The network, its kernels, the optimiser and the training run of Sect. 5
+(epochs, shuffling, learning-rate schedule, early stopping on the control
+set) live in the library; this module marshals device pointers and
+streams, and draws the training set's random parameters on the host
+(seeded numpy) for the library's synthesis.
 """
 import ctypes
-import math
 import os
 import time
 
@@ -18,6 +17,18 @@ from . import (NPAR, Context, Instrument, Options, VfisvError, _alloc_out, _Opti
                _ptr, _rows, _stream, _vp, _w_numel, lib, synthesize)
 
 NCODE = 10
+
+
+class _TrainSpec(ctypes.Structure):
+    _fields_ = [("stokes", _vp), ("params", _vp), ("n", ctypes.c_int64),
+                ("ctrl_stokes", _vp), ("ctrl_params", _vp), ("n_ctrl", ctypes.c_int64),
+                ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("min_lr_frac", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class _TrainReport(ctypes.Structure):
+    _fields_ = [("epochs_run", ctypes.c_int), ("best_epoch", ctypes.c_int),
+                ("best_control_mse", ctypes.c_double), ("steps", ctypes.c_int64)]
 
 
 def _L():
@@ -40,6 +51,12 @@ def _L():
         L.vfisv_mlp_take_loss.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.vfisv_mlp_save.argtypes = [_vp, ctypes.c_char_p]
         L.vfisv_mlp_load.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]
+        fp_ = ctypes.POINTER(ctypes.c_float)
+        dp_ = ctypes.POINTER(ctypes.c_double)
+        L.vfisv_mlp_stats.argtypes = [_vp, ctypes.c_int64, ctypes.c_int, _vp, _vp, fp_, fp_, fp_,
+                                      fp_, _vp]
+        L.vfisv_mlp_train.argtypes = [_vp, _vp, ctypes.POINTER(_TrainSpec),
+                                      ctypes.POINTER(_TrainReport), dp_, dp_, _vp]
         L.vfisv_invert_learned.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
                                            ctypes.POINTER(_Options), ctypes.c_int,
                                            ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
@@ -179,19 +196,6 @@ def invert_learned(ctx, inst, mlp, stokes, W, opts=None, learned_max_iter=15, ch
 
 # ---- training ------------------------------------------------------------
 
-def encode_targets(P):
-    """Model parameters [n, 10] (numpy float64) -> the network's raw codes
-    before output standardisation: field vector / 3000, then v .. alpha."""
-    g = np.radians(P[:, 1])
-    p2 = 2.0 * np.radians(P[:, 2])
-    T = np.empty((P.shape[0], NCODE))
-    T[:, 0] = P[:, 0] * np.cos(g) / 3000.0
-    T[:, 1] = P[:, 0] * np.sin(g) * np.cos(p2) / 3000.0
-    T[:, 2] = P[:, 0] * np.sin(g) * np.sin(p2) / 3000.0
-    T[:, 3:] = P[:, 3:]
-    return T
-
-
 def make_training_set(ctx, inst, n, seed, draw_params, draw_noise, chunk=1 << 20):
     """Synthesise n noisy pixels on the device from parameters drawn on the
     host.  Returns (stokes [n, 4*n_obs] device, params [n, 10] numpy)."""
@@ -210,52 +214,65 @@ def make_training_set(ctx, inst, n, seed, draw_params, draw_noise, chunk=1 << 20
     return stokes, P_all
 
 
+def _dev_params(P, dev):
+    if isinstance(P, torch.Tensor):
+        return P.to(device=dev, dtype=torch.float32).contiguous()
+    return torch.tensor(np.ascontiguousarray(P, dtype=np.float32), device=dev)
+
+
+def training_stats(ctx, stokes, P):
+    """Normalisation of a training set (vfisv_mlp_stats): (in_mean, in_std)
+    per input column and (out_mean, out_std) of v .. alpha, float32 numpy."""
+    dev = ctx.device
+    n = _rows(stokes)
+    n_in = stokes.shape[1]
+    Pd = _dev_params(P, dev)
+    stats = [np.empty(n_in, np.float32), np.empty(n_in, np.float32), np.empty(7, np.float32),
+             np.empty(7, np.float32)]
+    fptr = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) for a in stats]
+    ctx._check(_L().vfisv_mlp_stats(
+        ctx._h, n, n_in, _ptr(stokes, torch.float32, dev, n * n_in, name="stokes"),
+        _ptr(Pd, torch.float32, dev, n * NPAR, name="P"), *fptr, _stream(dev)),
+        "vfisv_mlp_stats")
+    return stats
+
+
+def train_network(ctx, mlp, train_stokes, train_P, control_stokes, control_P, epochs=20,
+                  batch=4096, lr=1e-3, seed=0, min_lr_frac=0.02):
+    """vfisv_mlp_train on an existing network: returns the report as a dict
+    with the per-epoch history [(epoch, train mse, control mse)]."""
+    dev = ctx.device
+    n, nc = _rows(train_stokes), _rows(control_stokes, "control_stokes")
+    n_in = mlp.n_in
+    Pt, Pc = _dev_params(train_P, dev), _dev_params(control_P, dev)
+    spec = _TrainSpec(_ptr(train_stokes, torch.float32, dev, n * n_in, name="train_stokes"),
+                      _ptr(Pt, torch.float32, dev, n * NPAR, name="train_P"), n,
+                      _ptr(control_stokes, torch.float32, dev, nc * n_in, name="control_stokes"),
+                      _ptr(Pc, torch.float32, dev, nc * NPAR, name="control_P"), nc,
+                      int(epochs), int(batch), float(lr), float(min_lr_frac), int(seed))
+    rep = _TrainReport()
+    tr = np.zeros(epochs)
+    ce = np.zeros(epochs)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    t0 = time.perf_counter()
+    ctx._check(_L().vfisv_mlp_train(ctx._h, mlp._h, ctypes.byref(spec), ctypes.byref(rep),
+                                    tr.ctypes.data_as(dptr), ce.ctypes.data_as(dptr),
+                                    _stream(dev)), "vfisv_mlp_train")
+    return dict(history=[(e, float(tr[e]), float(ce[e])) for e in range(rep.epochs_run)],
+                best_epoch=rep.best_epoch, best_control_mse=rep.best_control_mse,
+                seconds=time.perf_counter() - t0, steps=rep.steps)
+
+
 def train(ctx, inst, train_stokes, train_P, control_stokes, control_P, epochs=20, batch=4096,
           lr=1e-3, seed=0, log=print, min_lr_frac=0.02):
-    """Adam with a cosine learning-rate schedule; the weights of the epoch
-    with the lowest control-set error are kept (early stopping)."""
-    dev = ctx.device
-    n = train_stokes.shape[0]
-    S = train_stokes.float()
-    in_mean = S.mean(dim=0).cpu().numpy()
-    in_std = S.std(dim=0).clamp_min(1e-6).cpu().numpy()
-    raw = encode_targets(train_P)
-    out_mean = raw[:, 3:].mean(axis=0)
-    out_std = raw[:, 3:].std(axis=0)
-    mlp = Mlp(ctx, train_stokes.shape[1], in_mean, in_std, out_mean, out_std, seed=seed)
-
-    def std_codes(P):
-        T = encode_targets(P)
-        T[:, 3:] = (T[:, 3:] - out_mean) / out_std
-        return torch.tensor(T.astype(np.float32), device=dev)
-
-    T_train = std_codes(train_P)
-    T_ctrl = std_codes(control_P)
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    steps_per_epoch = n // batch
-    total = epochs * steps_per_epoch
-    best = (math.inf, None, -1)
-    history = []
-    step = 0
-    t0 = time.perf_counter()
-    for ep in range(epochs):
-        perm = torch.randperm(n, generator=gen).to(torch.int32).to(dev)
-        for b in range(steps_per_epoch):
-            frac = step / max(total - 1, 1)
-            cur = lr * (min_lr_frac + (1 - min_lr_frac) * 0.5 * (1 + math.cos(math.pi * frac)))
-            # a permutation of range(n): in range by construction
-            mlp.train_step(S, T_train, perm[b * batch:(b + 1) * batch], cur, check_rows=False)
-            step += 1
-        train_mse = mlp.take_loss() / (steps_per_epoch * batch * NCODE)
-        c, _ = mlp.forward(control_stokes, codes=True, params=False)
-        ctrl_mse = float(((c - T_ctrl) ** 2).mean())
-        history.append((ep, train_mse, ctrl_mse, time.perf_counter() - t0))
-        log("epoch %d  train mse %.5f  control mse %.5f  (%.1f s)" % history[-1])
-        if ctrl_mse < best[0]:
-            best = (ctrl_mse, mlp.get_params(), ep)
-        elif ctrl_mse > best[0] * 1.02 and ep - best[2] >= 3:
-            log("control error rising: stop")
-            break
-    mlp.set_params(best[1])
-    return mlp, dict(history=history, best_epoch=best[2], best_control_mse=best[0],
-                     seconds=time.perf_counter() - t0, steps=step)
+    """The library's training run on a new network: normalisation from the
+    training set, then Adam with a cosine learning rate and early stopping
+    on the control set, keeping the best epoch's weights.  train_P /
+    control_P: the models [n, 10] (numpy or tensor)."""
+    stats = training_stats(ctx, train_stokes, train_P)
+    mlp = Mlp(ctx, train_stokes.shape[1], *stats, seed=seed)
+    info = train_network(ctx, mlp, train_stokes, train_P, control_stokes, control_P,
+                         epochs=epochs, batch=batch, lr=lr, seed=seed, min_lr_frac=min_lr_frac)
+    for h in info["history"]:
+        log("epoch %d  train mse %.5f  control mse %.5f" % h)
+    return mlp, info

@@ -240,3 +240,38 @@ def test_learned_path_structure(ctx, small_trained):
                                                                short["params"][sel]))
     np.testing.assert_array_equal(lrn["iters"][sel], short["iters"][sel] + refit["iters"])
     assert np.all(lrn["status"][sel] & vf.FALLBACK_USED)
+
+
+def test_native_training_run(ctx):
+    """vfisv_mlp_stats against numpy; vfisv_mlp_train keeps the best epoch
+    (its control error re-evaluated here from the oracle's target coding),
+    and the same seed gives the same weights, another seed others."""
+    spec = wl.hmi_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    S, P = learned.make_training_set(ctx, inst, 32768, 31, wl.draw_params, wl.draw_noise)
+    Sc, Pc = learned.make_training_set(ctx, inst, 4096, 32, wl.draw_params, wl.draw_noise)
+    stats = learned.training_stats(ctx, S, P)
+    Sh = S.cpu().numpy().astype(np.float64)
+    P32 = P.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(stats[0], Sh.mean(axis=0), rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(stats[1], Sh.std(axis=0), rtol=1e-4)
+    np.testing.assert_allclose(stats[2], P32[:, 3:].mean(axis=0), rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(stats[3], P32[:, 3:].std(axis=0), rtol=1e-4)
+    kw = dict(epochs=4, batch=1024, lr=2e-3)
+    nets = [learned.Mlp(ctx, 24, *stats, seed=4) for _ in range(3)]
+    infos = [learned.train_network(ctx, nets[k], S, P, Sc, Pc, seed=9 if k < 2 else 10, **kw)
+             for k in range(3)]
+    p0, p1, p2 = (net.get_params() for net in nets)
+    assert np.array_equal(p0, p1) and not np.array_equal(p0, p2)
+    info = infos[0]
+    ctrl = [h[2] for h in info["history"]]
+    print("[gpu] native training: control mse %s, best epoch %d" % (ctrl, info["best_epoch"]),
+          flush=True)
+    assert info["steps"] == 4 * (32768 // 1024) and len(ctrl) == 4
+    assert info["best_epoch"] == int(np.argmin(ctrl)) and info["best_control_mse"] == min(ctrl)
+    assert ctrl[-1] < ctrl[0]
+    codes, _ = nets[0].forward(Sc, codes=True, params=False)
+    T = omlp.encode_targets(Pc.astype(np.float32).astype(np.float64), stats[2].astype(np.float64),
+                            stats[3].astype(np.float64))
+    mse = np.mean((codes.cpu().numpy().astype(np.float64) - T) ** 2)
+    assert abs(mse - info["best_control_mse"]) < 1e-4 * mse, (mse, info["best_control_mse"])
