@@ -106,7 +106,6 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.status = status;
   a.work = ctx->d_work;
   a.ws = ctx->d_ws;
-  a.ws_stride = 0;
   a.n = n;
   a.n_dev = n_dev;
   a.idx = idx;
@@ -148,7 +147,6 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   // falls back to one lane per pixel when they do not fit)
   const int bpc = inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu : ctx->band_blocks_per_cu;
   const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n, bpc, o, inst->kind);
-  a.ws_stride = (int64_t)grid * 64;
   const int64_t resident = (int64_t)ctx->num_cus * bpc;
   a.lane_cap = (long long)(grid < resident ? grid : resident) * 64;
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
@@ -614,7 +612,6 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o, -1);
-  for (int i = 0; i < n_batches; ++i) B.a[i].ws_stride = (int64_t)grid * 64;
   hipStream_t s = (hipStream_t)stream;
   e = launch_reset(ctx->d_work, true, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches: counter reset");
@@ -845,7 +842,6 @@ int vfisv_solve(vfisv_ctx* ctx, int64_t n, const float* H, const float* g, const
   a.n = n;
   a.free_mask = free_mask & 0x3FFu;
   const int grid = grid_for(n, ctx->ws_lanes / 64);
-  a.ws_stride = (int64_t)grid * 64;
   e = launch_solve(a, grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
   return VFISV_OK;

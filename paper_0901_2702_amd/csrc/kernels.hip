@@ -215,7 +215,8 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // pixel, restarts from a perturbed best model, the best model seen is the
 // result); otherwise exits on convergence, stall or A.max_iter.
 template <int NOBS, int LPP, int V = 0, bool PAPER = false>
-__device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, int64_t glane,
+__device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, double* sws, int lane,
+                                        int64_t glane,
                                         WaveCounters& wc) {
   static_assert(LPP == 1 || (LPP == 2 && NOBS > 0), "lane pairs serve the dense layout");
   const bool leader = LPP == 1 || (lane & 1) == 0;
@@ -244,6 +245,9 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
   double chig = 0.0, chi_first = 0.0;
   int bad = 0, kr = 0;
   bool pending = false, restart_eval = false;
+  // the damped solve needs the eigen fallback: done with the whole wave at
+  // the top of the next turn, where every lane is active
+  bool need_fb = false;
   const int limit = PAPER ? A.fixed_iters : A.max_iter;
 
   for (;;) {
@@ -321,6 +325,23 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
     }
     if (nm != 0ull && dry == (1u << NQ) - 1u) exhausted = exhausted || ((nm >> lane) & 1ull);
     if constexpr (LPP == 2) exhausted = __shfl(exhausted ? 1 : 0, mate) != 0;
+
+    // ---- eigen/SVD fallbacks of the last steps, one lane at a time --------
+    for (unsigned long long fbm = __ballot(need_fb); fbm != 0ull; fbm &= fbm - 1ull) {
+      const int L = __ffsll((unsigned long long)fbm) - 1;
+      solve_eigen_wave(sHG, L, __shfl(eps, L), A.free_mask, sws, lane);
+      if (lane == L) {
+        if (leader) ++wc.fb;
+        double Mt[NPAR];
+#pragma unroll
+        for (int q = 0; q < NPAR; ++q) Mt[q] = (double)Mb[q] + sws[200 + q];
+        project(Mt);
+#pragma unroll
+        for (int q = 0; q < NPAR; ++q) Mc[q] = (float)Mt[q];
+        need_fb = false;
+      }
+      __syncthreads();  // lane L has read the step before the record is reused
+    }
     if (__ballot(live) == 0ull) {
       if (__ballot(!exhausted) == 0ull) break;
       continue;  // lanes that met non-finite input refill first
@@ -436,19 +457,15 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, int lane, i
       double delta[NPAR], sc[NPAR], b[NPAR];
       const int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
       if (code == 1) {
-        if (leader) ++wc.fb;
-        double* ws = A.ws + glane;
-        solve_eigen_fallback(&sHG[lane], 64, &sHG[55 * 64 + lane], 64, eps, A.free_mask, ws,
-                             A.ws_stride);
+        need_fb = true;  // the step is taken at the top of the next turn
+      } else {
+        double Mt[NPAR];
 #pragma unroll
-        for (int q = 0; q < NPAR; ++q) delta[q] = ws[(int64_t)(200 + q) * A.ws_stride];
+        for (int q = 0; q < NPAR; ++q) Mt[q] = (double)Mb[q] + delta[q];
+        project(Mt);
+#pragma unroll
+        for (int q = 0; q < NPAR; ++q) Mc[q] = (float)Mt[q];
       }
-      double Mt[NPAR];
-#pragma unroll
-      for (int q = 0; q < NPAR; ++q) Mt[q] = (double)Mb[q] + delta[q];
-      project(Mt);
-#pragma unroll
-      for (int q = 0; q < NPAR; ++q) Mc[q] = (float)Mt[q];
     }
   }
 }
@@ -474,6 +491,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
 template <int NOBS, int V, bool PAPER>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
+  __shared__ double sws[WS_DOUBLES];  // the wave's eigen-fallback record
   const int lane = threadIdx.x;
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
   WaveCounters wc;
@@ -481,11 +499,11 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
     // pairs only when every pixel gets two lanes that run at once
     if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)A.lane_cap)
-      lm_loop<NOBS, 2, V, PAPER>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 2, V, PAPER>(A, sHG, sws, lane, glane, wc);
     else
-      lm_loop<NOBS, 1, V, PAPER>(A, sHG, lane, glane, wc);
+      lm_loop<NOBS, 1, V, PAPER>(A, sHG, sws, lane, glane, wc);
   } else {
-    lm_loop<NOBS, 1, V, PAPER>(A, sHG, lane, glane, wc);
+    lm_loop<NOBS, 1, V, PAPER>(A, sHG, sws, lane, glane, wc);
   }
   flush_counters(A.work, wc, lane);
 }
@@ -496,14 +514,15 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
 // the earlier ones.
 __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   __shared__ float sHG[65 * 64];
+  __shared__ double sws[WS_DOUBLES];
   const int lane = threadIdx.x;
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
   WaveCounters wc;
   for (int i = 0; i < B.n_batches; ++i) {
     if (B.kind[i] == KIND_DENSE6)
-      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, lane, glane, wc);
+      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, sws, lane, glane, wc);
     else
-      lm_loop<0, 1>(B.a[i], sHG, lane, glane, wc);
+      lm_loop<0, 1>(B.a[i], sHG, sws, lane, glane, wc);
   }
   flush_counters(B.a[0].work, wc, lane);
 }
@@ -580,10 +599,10 @@ __global__ __launch_bounds__(64) void solve_kernel(const SolveArgs A) {
     const double eps = A.eps[i];
     int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
     if (code == 1) {
-      double* ws = A.ws + (int64_t)blockIdx.x * 64 + threadIdx.x;
-      solve_eigen_fallback(A.H + i * 55, 1, A.g + i * NPAR, 1, eps, A.free_mask, ws, A.ws_stride);
+      double* ws = A.ws + ((int64_t)blockIdx.x * 64 + threadIdx.x) * WS_DOUBLES;
+      solve_eigen_fallback(A.H + i * 55, 1, A.g + i * NPAR, 1, eps, A.free_mask, ws);
 #pragma unroll
-      for (int q = 0; q < NPAR; ++q) delta[q] = ws[(int64_t)(200 + q) * A.ws_stride];
+      for (int q = 0; q < NPAR; ++q) delta[q] = ws[200 + q];
     }
 #pragma unroll
     for (int p = 0; p < NPAR; ++p) A.delta[i * NPAR + p] = delta[p];

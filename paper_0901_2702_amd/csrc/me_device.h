@@ -620,19 +620,20 @@ __device__ __forceinline__ int solve_cholesky(const float* H, const float* g, do
 }
 
 // Eigen (= SVD, the matrix being symmetric) fallback: cyclic Jacobi on
-// C + eps I held in a lane-strided float64 workspace (A at ws[e*stride],
-// eigenvectors at ws[(100 + e)*stride], the step written to
-// ws[(200 + p)*stride]); components with |lambda| below 1e-12 of the
-// largest are discarded.  H (packed, element stride hs) and g (stride gs)
+// C + eps I held in the lane's own contiguous float64 workspace of
+// WS_DOUBLES (A at ws[e], eigenvectors at ws[100 + e], the step written to
+// ws[200 + p]): it runs for single lanes, rarely, and a contiguous record
+// stays in the cache (a layout strided across the grid's lanes put every
+// element on its own page and took milliseconds per call); components with
+// |lambda| below 1e-12 of the largest are discarded.  H (packed, element stride hs) and g (stride gs)
 // are read through generic pointers (LDS or global) so that the caller keeps
 // its own arrays in registers.
 constexpr int WS_DOUBLES = 210;
 
 __device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const float* g, int gs,
-                                                  double eps, uint32_t free_mask, double* ws,
-                                                  int64_t stride) {
-  auto A = [&](int i, int j) -> double& { return ws[(int64_t)(i * NPAR + j) * stride]; };
-  auto V = [&](int i, int j) -> double& { return ws[(int64_t)(100 + i * NPAR + j) * stride]; };
+                                                  double eps, uint32_t free_mask, double* ws) {
+  auto A = [&](int i, int j) -> double& { return ws[i * NPAR + j]; };
+  auto V = [&](int i, int j) -> double& { return ws[100 + i * NPAR + j]; };
   double sc[NPAR], b[NPAR];
   double maxd = 0.0;
   for (int p = 0; p < NPAR; ++p)
@@ -660,10 +661,16 @@ __device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const 
         else off += v * v;
       }
     if (!(off > 1e-32 * dia)) break;
+    // off-diagonal elements at the rounding level of the matrix are left
+    // alone (rotating them changes nothing but the rounding), and a sweep
+    // that rotates nothing ends the iteration
+    const double floor_ = 1e-15 * sqrt(dia);
+    bool rotated = false;
     for (int p = 0; p < NPAR - 1; ++p)
       for (int q = p + 1; q < NPAR; ++q) {
         const double apq = A(p, q);
-        if (apq == 0.0) continue;
+        if (!(fabs(apq) > floor_)) continue;
+        rotated = true;
         const double th = (A(q, q) - A(p, p)) / (2.0 * apq);
         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
         const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
@@ -683,6 +690,7 @@ __device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const 
           V(k, q) = s * vkp + c * vkq;
         }
       }
+    if (!rotated) break;
   }
   double lmax = 0.0;
   for (int j = 0; j < NPAR; ++j) lmax = fmax(lmax, fabs(A(j, j)));
@@ -696,7 +704,108 @@ __device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const 
     pr /= lam;
     for (int i = 0; i < NPAR; ++i) y[i] = fma(V(i, j), pr, y[i]);
   }
-  for (int p = 0; p < NPAR; ++p) ws[(int64_t)(200 + p) * stride] = sc[p] * y[p];
+  for (int p = 0; p < NPAR; ++p) ws[200 + p] = sc[p] * y[p];
+}
+
+// The same eigen fallback for lane L of a wave, computed by the whole wave
+// (all 64 lanes active, one wave per workgroup) in an LDS record sws of
+// WS_DOUBLES: lanes 0..9 take rows or columns of each rotation, lanes
+// 10..19 the eigenvector columns.  Each element sees the same operations
+// in the same order as in solve_eigen_fallback; only the sums that decide
+// when the sweeps stop are added in another order.  H and g are lane L's
+// column of the LDS array hg (element e at hg[e * 64 + L]).  The step ends
+// in sws[200 .. 209].
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __noinline__ void solve_eigen_wave(const float* hg, int L, double eps,
+                                              uint32_t free_mask, double* sws, int lane) {
+  double sc[NPAR], b[NPAR];
+  double maxd = 0.0;
+  for (int p = 0; p < NPAR; ++p)
+    if ((free_mask >> p) & 1u) maxd = fmax(maxd, (double)hg[pk(p, p) * 64 + L]);
+  for (int p = 0; p < NPAR; ++p) {
+    const double d = (double)hg[pk(p, p) * 64 + L];
+    const bool act = ((free_mask >> p) & 1u) && maxd > 0.0 && d > 1e-30 * maxd;
+    sc[p] = act ? 1.0 / sqrt(d) : 0.0;
+    b[p] = sc[p] * (double)hg[(55 + p) * 64 + L];
+  }
+  for (int e = lane; e < NPAR * NPAR; e += 64) {
+    const int i = e / NPAR, j = e - i * NPAR;
+    const int hi = i > j ? pk(i, j) : pk(j, i);
+    double v = sc[i] * (double)hg[hi * 64 + L] * sc[j];
+    if (i == j) v = (sc[i] != 0.0) ? 1.0 + eps : 1.0;
+    sws[e] = v;
+    sws[100 + e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < NPAR * NPAR; e += 64) {
+      const double v = sws[e];
+      if (e % (NPAR + 1) == 0) dia += v * v;
+      else off += v * v;
+    }
+    off = wave_sum_f64(off);
+    dia = wave_sum_f64(dia);
+    if (!(off > 1e-32 * dia)) break;
+    const double floor_ = 1e-15 * sqrt(dia);  // as in solve_eigen_fallback
+    bool rotated = false;
+    for (int p = 0; p < NPAR - 1; ++p)
+      for (int q = p + 1; q < NPAR; ++q) {
+        const double apq = sws[p * NPAR + q];
+        if (!(fabs(apq) > floor_)) continue;  // the same decision on every lane
+        rotated = true;
+        const double th = (sws[q * NPAR + q] - sws[p * NPAR + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
+        __syncthreads();  // every lane has read the pivot elements
+        if (lane < NPAR) {  // columns p and q of A
+          const int k = lane;
+          const double akp = sws[k * NPAR + p], akq = sws[k * NPAR + q];
+          sws[k * NPAR + p] = c * akp - s * akq;
+          sws[k * NPAR + q] = s * akp + c * akq;
+        } else if (lane < 2 * NPAR) {  // columns p and q of V
+          const int k = lane - NPAR;
+          const double vkp = sws[100 + k * NPAR + p], vkq = sws[100 + k * NPAR + q];
+          sws[100 + k * NPAR + p] = c * vkp - s * vkq;
+          sws[100 + k * NPAR + q] = s * vkp + c * vkq;
+        }
+        __syncthreads();
+        if (lane < NPAR) {  // rows p and q of A
+          const int k = lane;
+          const double apk = sws[p * NPAR + k], aqk = sws[q * NPAR + k];
+          sws[p * NPAR + k] = c * apk - s * aqk;
+          sws[q * NPAR + k] = s * apk + c * aqk;
+        }
+        __syncthreads();
+      }
+    if (!rotated) break;
+  }
+  double lmax = 0.0;
+  for (int j = 0; j < NPAR; ++j) lmax = fmax(lmax, fabs(sws[j * NPAR + j]));
+  double pr[NPAR];
+  for (int j = 0; j < NPAR; ++j) {
+    const double lam = sws[j * NPAR + j];
+    pr[j] = 0.0;
+    if (!(fabs(lam) >= 1e-12 * lmax) || lam == 0.0) continue;
+    for (int i = 0; i < NPAR; ++i) pr[j] = fma(sws[100 + i * NPAR + j], b[i], pr[j]);
+    pr[j] /= lam;
+  }
+  __syncthreads();  // A and V are read
+  if (lane < NPAR) {
+    const int i = lane;
+    double y = 0.0;
+    for (int j = 0; j < NPAR; ++j) {
+      const double lam = sws[j * NPAR + j];
+      if (!(fabs(lam) >= 1e-12 * lmax) || lam == 0.0) continue;
+      y = fma(sws[100 + i * NPAR + j], pr[j], y);
+    }
+    sws[200 + i] = sc[i] * y;
+  }
+  __syncthreads();
 }
 
 // Table 2 (rows read top-down).
