@@ -64,7 +64,16 @@ def test_null_arguments_are_rejected():
     assert L.vfisv_iter_histogram(None, 0, None, 1, None, None) == -1
     assert L.vfisv_autotune(None, None, 0, None, None, 0, None, 0, None, None) == -1
     assert L.vfisv_init_classical(None, None, 0, None, None, None, None) == -1
+    assert L.vfisv_init_combined(None, None, 0, None, None, 0.06, None, None, None) == -1
+    assert L.vfisv_stokes_weights(None, None, 0, None, None, None, None, None) == -1
     assert L.vfisv_instrument_info_get(None, None) == -1
+    from paper_0901_2702_amd import learned
+    L = learned._L()  # the network functions' signatures
+    assert L.vfisv_mlp_num_inputs(None) == -1 and L.vfisv_mlp_num_params(None) == -1
+    assert L.vfisv_mlp_stats(None, 0, 0, None, None, None, None, None, None, None) == -1
+    assert L.vfisv_mlp_train(None, None, None, None, None, None, None) == -1
+    assert L.vfisv_invert_learned(None, None, None, 0, None, None, 0, None, 0, 0.0, None, None,
+                                  None, None, None) == -1
 
 
 def test_no_cpu_fallback():
