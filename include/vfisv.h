@@ -172,7 +172,7 @@ typedef struct {
 
 /* Create a context on HIP device `device` (the device is made current on
  * the calling thread).  Allocates the context's device work counters and
- * the solve workspace.  Errors: VFISV_E_INVALID (out == NULL or no such
+ * the histogram bins.  Errors: VFISV_E_INVALID (out == NULL or no such
  * device), VFISV_E_DEVICE, VFISV_E_NOMEM. */
 int vfisv_create(vfisv_ctx **out, int device);
 
@@ -276,7 +276,7 @@ int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batch
  * at most n) of the caller's data, from the default model with opt's fit
  * settings, with every candidate persistent grid
  * (1, 2, 3, 4, 6 or 8 waves per CU, up to the waves that are resident at
- * once for the layout's kernel and within the fallback workspace) and
+ * once for the layout's kernel, at most 8 waves per CU) and
  * pixel-queue block (2^4, 2^8, 2^12 pixels), twice each, timed with HIP
  * events on `stream`, and keeps the fastest for this instrument's layout in
  * the context; later inversions with grid_waves == 0 and chunk_log2 == -1

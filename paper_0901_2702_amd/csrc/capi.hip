@@ -105,7 +105,6 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.iters = iters;
   a.status = status;
   a.work = ctx->d_work;
-  a.ws = ctx->d_ws;
   a.n = n;
   a.n_dev = n_dev;
   a.idx = idx;
@@ -128,7 +127,7 @@ static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, i
   int64_t cap = (int64_t)ctx->num_cus * bpc;
   if (o.grid_waves > 0) cap = o.grid_waves;
   else if (kind >= 0 && ctx->tuned[kind].valid) cap = ctx->tuned[kind].grid_waves;
-  if (cap > ctx->ws_lanes / 64) cap = ctx->ws_lanes / 64;
+  if (cap > ctx->max_lanes / 64) cap = ctx->max_lanes / 64;
   return grid_for(n, cap);
 }
 
@@ -259,23 +258,16 @@ int vfisv_create(vfisv_ctx** out, int device) {
   e = band_blocks_per_cu(&bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
   c->band_blocks_per_cu = bpc;
-  // fallback workspace: WS_DOUBLES per lane of the largest persistent grid
-  c->ws_lanes = (int64_t)c->num_cus * 8 * 64;
-  e = hipMalloc(&c->d_ws, sizeof(double) * WS_DOUBLES * c->ws_lanes);
-  if (e != hipSuccess) {
-    delete c;
-    return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: workspace allocation");
-  }
+  // the largest persistent grid: 8 waves per CU
+  c->max_lanes = (int64_t)c->num_cus * 8 * 64;
   e = hipMalloc(&c->d_work, sizeof(unsigned long long) * (WORK_SLOTS + HIST_MAX));
   if (e != hipSuccess) {
-    hipFree(c->d_ws);
     delete c;
     return fail(nullptr, VFISV_E_NOMEM, "vfisv_create: counter allocation");
   }
   e = launch_reset(c->d_work, true, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    hipFree(c->d_ws);
     hipFree(c->d_work);
     delete c;
     return hip_fail(nullptr, e, "vfisv_create: counter reset");
@@ -293,7 +285,6 @@ int vfisv_destroy(vfisv_ctx* ctx) {
   if (!ctx) return VFISV_OK;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
-  hipFree(ctx->d_ws);
   hipFree(ctx->d_work);
   if (ctx->d_learn) hipFree(ctx->d_learn);
   if (ctx->d_vtab) hipFree(ctx->d_vtab);
@@ -660,7 +651,7 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
     const int64_t gw = (int64_t)ctx->num_cus * waves_per_cu[wi];
     // a persistent grid larger than what is resident only adds waves that
     // start when the work is gone
-    if (gw > ctx->ws_lanes / 64 || waves_per_cu[wi] > bpc_default) continue;
+    if (gw > ctx->max_lanes / 64 || waves_per_cu[wi] > bpc_default) continue;
     for (int ci = 0; e == hipSuccess && ci < 3; ++ci) {
       vfisv_options oc = o;
       oc.grid_waves = (int)gw;
@@ -838,10 +829,9 @@ int vfisv_solve(vfisv_ctx* ctx, int64_t n, const float* H, const float* g, const
   a.eps = eps;
   a.delta = delta;
   a.code = code;
-  a.ws = ctx->d_ws;
   a.n = n;
   a.free_mask = free_mask & 0x3FFu;
-  const int grid = grid_for(n, ctx->ws_lanes / 64);
+  const int grid = grid_for(n, ctx->max_lanes / 64);
   e = launch_solve(a, grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "solve launch");
   return VFISV_OK;

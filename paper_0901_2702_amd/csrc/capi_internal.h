@@ -15,8 +15,7 @@ struct vfisv_ctx {
   int lm_blocks_per_cu = 1;
   int band_blocks_per_cu = 1;
   unsigned long long* d_work = nullptr;  // WORK_SLOTS counters
-  double* d_ws = nullptr;                // eigen-fallback workspace
-  int64_t ws_lanes = 0;
+  int64_t max_lanes = 0;                 // lanes of the largest persistent grid
   float2* d_vtab = nullptr;              // Taylor table {H, F}, built on first use
   float wc[vfisv::NW + 1];
   float wL = 0.f;

@@ -35,7 +35,6 @@ struct LMArgs {
   int32_t* iters;
   int32_t* status;
   unsigned long long* work;
-  double* ws;                        // WS_DOUBLES per lane of the grid, lane-contiguous
   int64_t n;                         // pixels, unless n_dev is given
   const unsigned long long* n_dev;   // device-side pixel count, or NULL
   const int32_t* idx;                // pixel ids to invert, or NULL (0..n-1)
@@ -80,7 +79,6 @@ struct SolveArgs {
   const double* eps;
   double* delta;
   int32_t* code;
-  double* ws;  // WS_DOUBLES per lane of the grid, lane-contiguous
   int64_t n;
   uint32_t free_mask;
 };

@@ -329,7 +329,8 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, double* sws
     // ---- eigen/SVD fallbacks of the last steps, one lane at a time --------
     for (unsigned long long fbm = __ballot(need_fb); fbm != 0ull; fbm &= fbm - 1ull) {
       const int L = __ffsll((unsigned long long)fbm) - 1;
-      solve_eigen_wave(sHG, L, __shfl(eps, L), A.free_mask, sws, lane);
+      solve_eigen_wave(&sHG[L], 64, &sHG[55 * 64 + L], 64, __shfl(eps, L), A.free_mask, sws,
+                       lane);
       if (lane == L) {
         if (leader) ++wc.fb;
         double Mt[NPAR];
@@ -588,25 +589,41 @@ __global__ __launch_bounds__(64) void synth_band_kernel(const SynthArgs A) {
 }
 
 __global__ __launch_bounds__(64) void solve_kernel(const SolveArgs A) {
-  for (int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x; i < A.n;
-       i += (int64_t)gridDim.x * 64) {
-    float H[55], g[NPAR];
+  __shared__ double sws[WS_DOUBLES];  // the wave's eigen-fallback record
+  const int lane = threadIdx.x;
+  // a wave-uniform loop, so that every lane takes part in the fallbacks
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < A.n; base += (int64_t)gridDim.x * 64) {
+    const int64_t i = base + lane;
+    const bool valid = i < A.n;
+    double delta[NPAR];
+    int code = 0;
+    double eps = 0.0;
+    if (valid) {
+      float H[55], g[NPAR];
 #pragma unroll
-    for (int e = 0; e < 55; ++e) H[e] = A.H[i * 55 + e];
+      for (int e = 0; e < 55; ++e) H[e] = A.H[i * 55 + e];
 #pragma unroll
-    for (int e = 0; e < NPAR; ++e) g[e] = A.g[i * NPAR + e];
-    double delta[NPAR], sc[NPAR], b[NPAR];
-    const double eps = A.eps[i];
-    int code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
-    if (code == 1) {
-      double* ws = A.ws + ((int64_t)blockIdx.x * 64 + threadIdx.x) * WS_DOUBLES;
-      solve_eigen_fallback(A.H + i * 55, 1, A.g + i * NPAR, 1, eps, A.free_mask, ws);
-#pragma unroll
-      for (int q = 0; q < NPAR; ++q) delta[q] = ws[200 + q];
+      for (int e = 0; e < NPAR; ++e) g[e] = A.g[i * NPAR + e];
+      double sc[NPAR], b[NPAR];
+      eps = A.eps[i];
+      code = solve_cholesky(H, g, eps, A.free_mask, delta, sc, b);
     }
+    for (unsigned long long fbm = __ballot(valid && code == 1); fbm != 0ull; fbm &= fbm - 1ull) {
+      const int L = __ffsll((unsigned long long)fbm) - 1;
+      const int64_t iL = base + L;
+      solve_eigen_wave(A.H + iL * 55, 1, A.g + iL * NPAR, 1, __shfl(eps, L), A.free_mask, sws,
+                       lane);
+      if (lane == L) {
 #pragma unroll
-    for (int p = 0; p < NPAR; ++p) A.delta[i * NPAR + p] = delta[p];
-    if (A.code) A.code[i] = code;
+        for (int q = 0; q < NPAR; ++q) delta[q] = sws[200 + q];
+      }
+      __syncthreads();  // lane L has read the step before the record is reused
+    }
+    if (valid) {
+#pragma unroll
+      for (int p = 0; p < NPAR; ++p) A.delta[i * NPAR + p] = delta[p];
+      if (A.code) A.code[i] = code;
+    }
   }
 }
 

@@ -619,21 +619,30 @@ __device__ __forceinline__ int solve_cholesky(const float* H, const float* g, do
   return 0;
 }
 
-// Eigen (= SVD, the matrix being symmetric) fallback: cyclic Jacobi on
-// C + eps I held in the lane's own contiguous float64 workspace of
-// WS_DOUBLES (A at ws[e], eigenvectors at ws[100 + e], the step written to
-// ws[200 + p]): it runs for single lanes, rarely, and a contiguous record
-// stays in the cache (a layout strided across the grid's lanes put every
-// element on its own page and took milliseconds per call); components with
-// |lambda| below 1e-12 of the largest are discarded.  H (packed, element stride hs) and g (stride gs)
-// are read through generic pointers (LDS or global) so that the caller keeps
-// its own arrays in registers.
+// Eigen (= SVD, the matrix being symmetric) fallback: cyclic Jacobi on the
+// equilibrated C + eps I, components with |lambda| below 1e-12 of the
+// largest discarded.  It is rare (a few per million solves), so the whole
+// wave computes it for one lane at a time, in an LDS record of WS_DOUBLES
+// (A at sws[e], eigenvectors at sws[100 + e], the step written to
+// sws[200 + p]): lanes 0..9 take rows or columns of each rotation, lanes
+// 10..19 the eigenvector columns.  Off-diagonal elements at the rounding
+// level of the matrix (1e-15 of the diagonal's norm) are left unrotated and
+// a sweep that rotates nothing ends the iteration.  (Run by the lane alone
+// on a workspace in global memory, strided across the grid's lanes, and
+// always for its 60 sweeps, it took milliseconds per call.)
 constexpr int WS_DOUBLES = 210;
 
-__device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const float* g, int gs,
-                                                  double eps, uint32_t free_mask, double* ws) {
-  auto A = [&](int i, int j) -> double& { return ws[i * NPAR + j]; };
-  auto V = [&](int i, int j) -> double& { return ws[100 + i * NPAR + j]; };
+// Called by all 64 lanes of a one-wave workgroup for the system of lane
+// L: H (packed, element stride hs) and g (stride gs) are read through
+// generic pointers (LDS or global), eps is lane L's damping.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __noinline__ void solve_eigen_wave(const float* H, int hs, const float* g, int gs,
+                                              double eps, uint32_t free_mask, double* sws,
+                                              int lane) {
   double sc[NPAR], b[NPAR];
   double maxd = 0.0;
   for (int p = 0; p < NPAR; ++p)
@@ -644,98 +653,10 @@ __device__ __noinline__ void solve_eigen_fallback(const float* H, int hs, const 
     sc[p] = act ? 1.0 / sqrt(d) : 0.0;
     b[p] = sc[p] * (double)g[p * gs];
   }
-  for (int i = 0; i < NPAR; ++i)
-    for (int j = 0; j < NPAR; ++j) {
-      const int hi = i > j ? pk(i, j) : pk(j, i);
-      double v = sc[i] * (double)H[hi * hs] * sc[j];
-      if (i == j) v = (sc[i] != 0.0) ? 1.0 + eps : 1.0;
-      A(i, j) = v;
-      V(i, j) = (i == j) ? 1.0 : 0.0;
-    }
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int i = 0; i < NPAR; ++i)
-      for (int j = 0; j < NPAR; ++j) {
-        const double v = A(i, j);
-        if (i == j) dia += v * v;
-        else off += v * v;
-      }
-    if (!(off > 1e-32 * dia)) break;
-    // off-diagonal elements at the rounding level of the matrix are left
-    // alone (rotating them changes nothing but the rounding), and a sweep
-    // that rotates nothing ends the iteration
-    const double floor_ = 1e-15 * sqrt(dia);
-    bool rotated = false;
-    for (int p = 0; p < NPAR - 1; ++p)
-      for (int q = p + 1; q < NPAR; ++q) {
-        const double apq = A(p, q);
-        if (!(fabs(apq) > floor_)) continue;
-        rotated = true;
-        const double th = (A(q, q) - A(p, p)) / (2.0 * apq);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
-        for (int k = 0; k < NPAR; ++k) {
-          const double akp = A(k, p), akq = A(k, q);
-          A(k, p) = c * akp - s * akq;
-          A(k, q) = s * akp + c * akq;
-        }
-        for (int k = 0; k < NPAR; ++k) {
-          const double apk = A(p, k), aqk = A(q, k);
-          A(p, k) = c * apk - s * aqk;
-          A(q, k) = s * apk + c * aqk;
-        }
-        for (int k = 0; k < NPAR; ++k) {
-          const double vkp = V(k, p), vkq = V(k, q);
-          V(k, p) = c * vkp - s * vkq;
-          V(k, q) = s * vkp + c * vkq;
-        }
-      }
-    if (!rotated) break;
-  }
-  double lmax = 0.0;
-  for (int j = 0; j < NPAR; ++j) lmax = fmax(lmax, fabs(A(j, j)));
-  double y[NPAR];
-  for (int i = 0; i < NPAR; ++i) y[i] = 0.0;
-  for (int j = 0; j < NPAR; ++j) {
-    const double lam = A(j, j);
-    if (!(fabs(lam) >= 1e-12 * lmax) || lam == 0.0) continue;
-    double pr = 0.0;
-    for (int i = 0; i < NPAR; ++i) pr = fma(V(i, j), b[i], pr);
-    pr /= lam;
-    for (int i = 0; i < NPAR; ++i) y[i] = fma(V(i, j), pr, y[i]);
-  }
-  for (int p = 0; p < NPAR; ++p) ws[200 + p] = sc[p] * y[p];
-}
-
-// The same eigen fallback for lane L of a wave, computed by the whole wave
-// (all 64 lanes active, one wave per workgroup) in an LDS record sws of
-// WS_DOUBLES: lanes 0..9 take rows or columns of each rotation, lanes
-// 10..19 the eigenvector columns.  Each element sees the same operations
-// in the same order as in solve_eigen_fallback; only the sums that decide
-// when the sweeps stop are added in another order.  H and g are lane L's
-// column of the LDS array hg (element e at hg[e * 64 + L]).  The step ends
-// in sws[200 .. 209].
-__device__ __forceinline__ double wave_sum_f64(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-__device__ __noinline__ void solve_eigen_wave(const float* hg, int L, double eps,
-                                              uint32_t free_mask, double* sws, int lane) {
-  double sc[NPAR], b[NPAR];
-  double maxd = 0.0;
-  for (int p = 0; p < NPAR; ++p)
-    if ((free_mask >> p) & 1u) maxd = fmax(maxd, (double)hg[pk(p, p) * 64 + L]);
-  for (int p = 0; p < NPAR; ++p) {
-    const double d = (double)hg[pk(p, p) * 64 + L];
-    const bool act = ((free_mask >> p) & 1u) && maxd > 0.0 && d > 1e-30 * maxd;
-    sc[p] = act ? 1.0 / sqrt(d) : 0.0;
-    b[p] = sc[p] * (double)hg[(55 + p) * 64 + L];
-  }
   for (int e = lane; e < NPAR * NPAR; e += 64) {
     const int i = e / NPAR, j = e - i * NPAR;
     const int hi = i > j ? pk(i, j) : pk(j, i);
-    double v = sc[i] * (double)hg[hi * 64 + L] * sc[j];
+    double v = sc[i] * (double)H[hi * hs] * sc[j];
     if (i == j) v = (sc[i] != 0.0) ? 1.0 + eps : 1.0;
     sws[e] = v;
     sws[100 + e] = (i == j) ? 1.0 : 0.0;
@@ -751,7 +672,7 @@ __device__ __noinline__ void solve_eigen_wave(const float* hg, int L, double eps
     off = wave_sum_f64(off);
     dia = wave_sum_f64(dia);
     if (!(off > 1e-32 * dia)) break;
-    const double floor_ = 1e-15 * sqrt(dia);  // as in solve_eigen_fallback
+    const double floor_ = 1e-15 * sqrt(dia);
     bool rotated = false;
     for (int p = 0; p < NPAR - 1; ++p)
       for (int q = p + 1; q < NPAR; ++q) {
