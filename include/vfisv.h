@@ -88,6 +88,11 @@ typedef struct {
   int n_taps;              /* non-zero taps kept over all rows         */
   double max_dropped_rel;  /* largest dropped tap mass / row sum       */
   double cz_mA_per_G;      /* Eq. 7 splitting constant                 */
+  int lm_register_rows;    /* filter rows whose sums the LM pass keeps in
+                              registers at once: 6-row filters 5 when the
+                              first row to end and the last to start share
+                              at most 4 synthesis points (the first is then
+                              finished in LDS), else 6; banded filters 4 */
 } vfisv_instrument_info;
 
 /* Fit options; vfisv_options_default fills the documented defaults. */

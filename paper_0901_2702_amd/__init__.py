@@ -36,7 +36,7 @@ class _InstDesc(ctypes.Structure):
 class _InstInfo(ctypes.Structure):
     _fields_ = [("n_active_fine", ctypes.c_int), ("n_taps", ctypes.c_int),
                 ("max_dropped_rel", ctypes.c_double),
-                ("cz_mA_per_G", ctypes.c_double)]
+                ("cz_mA_per_G", ctypes.c_double), ("lm_register_rows", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):

@@ -92,6 +92,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.C = inst->C;
   a.C.vtab = ctx->d_vtab;
   a.pts = inst->d_pts;
+  a.pts5 = inst->d_pts5;
   a.blocks = inst->d_blocks;
   a.row_sums = inst->d_row_sums;
   a.qbase = QUEUE_SLOT0;
@@ -336,6 +337,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   if (!inst) return fail(ctx, VFISV_E_NOMEM, "instrument_create: host allocation");
   inst->ctx = ctx;
   std::memset(&inst->C, 0, sizeof(Consts));
+  inst->C.sw_k = -1;
   double max_drop = 0.0;
   std::vector<double> kept((size_t)no * nf);
   std::vector<float> row_sum((size_t)no);
@@ -355,7 +357,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     if (rsum > 0.0) max_drop = std::fmax(max_drop, drop / rsum);
     row_sum[(size_t)i] = (float)ksum;
   }
-  std::vector<Point> pts;
+  std::vector<Point> pts, pts5;
   std::vector<Block> blocks;
   int n_taps = 0, n_active = 0;
   if (no == NOBS_HMI) {
@@ -377,6 +379,49 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
       if (mask) pts.push_back(p);
     }
     n_active = (int)pts.size();
+    // Windowed records: row a (the first to end) and row b (the last to
+    // start) share register slot 4 when they overlap on at most OV_MAX
+    // records; the other four rows take slots 0-3 in order.
+    std::vector<int> fr(no, -1), lr(no, -1);
+    for (int k = 0; k < (int)pts.size(); ++k)
+      for (int i = 0; i < no; ++i)
+        if (pts[(size_t)k].w[i] != 0.f) {
+          if (fr[(size_t)i] < 0) fr[(size_t)i] = k;
+          lr[(size_t)i] = k;
+        }
+    int ra = -1, rb = -1;
+    bool all_rows = true;
+    for (int i = 0; i < no; ++i) {
+      if (fr[(size_t)i] < 0) all_rows = false;
+      if (ra < 0 || lr[(size_t)i] < lr[(size_t)ra]) ra = i;
+    }
+    for (int i = 0; i < no; ++i)
+      if (i != ra && (rb < 0 || fr[(size_t)i] > fr[(size_t)rb])) rb = i;
+    if (all_rows && ra >= 0 && rb >= 0 && fr[(size_t)ra] < fr[(size_t)rb] &&
+        lr[(size_t)ra] - fr[(size_t)rb] + 1 <= OV_MAX) {
+      const int sw = fr[(size_t)rb];
+      int slot = 0;
+      for (int i = 0; i < no; ++i)
+        if (i != ra && i != rb) inst->C.slot_row[slot++] = i;
+      inst->C.slot_row[4] = rb;
+      inst->C.slot_row[5] = ra;
+      for (int q = 0; q < 6; ++q) inst->C.slot_rs[q] = row_sum[(size_t)inst->C.slot_row[q]];
+      pts5.resize(pts.size());
+      for (int k = 0; k < (int)pts.size(); ++k) {
+        const Point& P = pts[(size_t)k];
+        Point& Q = pts5[(size_t)k];
+        std::memset(&Q, 0, sizeof Q);
+        Q.dl = P.dl;
+        for (int q = 0; q < 4; ++q) Q.w[q] = P.w[inst->C.slot_row[q]];
+        Q.w[4] = k < sw ? P.w[ra] : P.w[rb];
+        Q.w[5] = k < sw ? 0.f : P.w[ra];
+        uint32_t m = 0;
+        for (int q = 0; q < 6; ++q)
+          if (Q.w[q] != 0.f) m |= 1u << q;
+        std::memcpy(&Q.w[6], &m, 4);
+      }
+      inst->C.sw_k = sw;
+    }
   } else {
     // banded: row i's kept taps must lie in points a0 + 4 i .. a0 + 4 i + 15
     int64_t a0 = INT64_MAX;
@@ -436,6 +481,8 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   inst->info.n_taps = n_taps;
   inst->info.max_dropped_rel = max_drop;
   inst->info.cz_mA_per_G = cz;
+  inst->info.lm_register_rows =
+      inst->kind == KIND_BAND ? BAND_R : (inst->C.sw_k >= 0 ? 5 : NOBS_HMI);
 
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) {
@@ -465,6 +512,12 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     e = hipMalloc(&inst->d_pts, bytes);
     if (e == hipSuccess && !pts.empty())
       e = hipMemcpy(inst->d_pts, pts.data(), sizeof(Point) * pts.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pts5.empty()) {
+      e = hipMalloc(&inst->d_pts5, sizeof(Point) * pts5.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(inst->d_pts5, pts5.data(), sizeof(Point) * pts5.size(),
+                      hipMemcpyHostToDevice);
+    }
   } else {
     e = hipMalloc(&inst->d_blocks, sizeof(Block) * blocks.size());
     if (e == hipSuccess) e = hipMalloc(&inst->d_row_sums, sizeof(float) * (size_t)no);
@@ -477,6 +530,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   }
   if (e != hipSuccess) {
     if (inst->d_pts) hipFree(inst->d_pts);
+    if (inst->d_pts5) hipFree(inst->d_pts5);
     if (inst->d_blocks) hipFree(inst->d_blocks);
     if (inst->d_row_sums) hipFree(inst->d_row_sums);
     hipFree(inst->d_obs_x);
@@ -498,6 +552,7 @@ int vfisv_instrument_destroy(vfisv_instrument* inst) {
   hipSetDevice(inst->ctx->device);
   hipDeviceSynchronize();
   if (inst->d_pts) hipFree(inst->d_pts);
+  if (inst->d_pts5) hipFree(inst->d_pts5);
   if (inst->d_blocks) hipFree(inst->d_blocks);
   if (inst->d_row_sums) hipFree(inst->d_row_sums);
   if (inst->d_obs_x) hipFree(inst->d_obs_x);

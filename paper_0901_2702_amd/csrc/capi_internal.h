@@ -35,6 +35,7 @@ struct vfisv_instrument {
   vfisv_ctx* ctx = nullptr;
   int kind = vfisv::KIND_DENSE6;
   vfisv::Point* d_pts = nullptr;       // KIND_DENSE6
+  vfisv::Point* d_pts5 = nullptr;      // KIND_DENSE6, windowed records (C.sw_k >= 0)
   vfisv::Block* d_blocks = nullptr;    // KIND_BAND
   float* d_row_sums = nullptr;         // KIND_BAND
   float* d_obs_x = nullptr;            // [n_obs] observed wavelength of each sample

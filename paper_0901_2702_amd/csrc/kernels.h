@@ -25,6 +25,7 @@ constexpr int HIST_MAX = 4096;  // iteration-histogram bins (kept after the work
 struct LMArgs {
   Consts C;
   const Point* pts;        // KIND_DENSE6
+  const Point* pts5;       // KIND_DENSE6, windowed records (C.sw_k >= 0)
   const Block* blocks;     // KIND_BAND: C.n_obs + BAND_R - 1 blocks
   const float* row_sums;   // KIND_BAND: [n_obs] sums of the kept taps
   const float* stokes;

@@ -74,15 +74,100 @@ struct WaveCounters {
 // every trial, since the rows are gone once chi^2 is known).
 // keep_h: the step starts from a model near the minimum (Sect. 4.4): only g
 // is rebuilt and stored, H stays as it is in LDS.
+// One pass of the dense layout over windowed records: the same chi^2 and
+// normal equations as lm_pass, from five register slots and the row parked
+// in LDS.  After the pass every row is folded into chi^2, g (registers) and
+// H (the lane's LDS slots, 14 float4, read and written once per row), for
+// every lane: some lane of the wave accepts in practically every pass, so
+// the wave would run the fold anyway, and with H out of the registers the
+// fold needs no more of them than the point loop.  Accepted lanes then copy
+// H and g to the parking area.
+template <int NOBS, int V>
+__device__ __forceinline__ double lm_pass_win(const LMArgs& A, const Pix& px, const RowFactors& rf,
+                                              int64_t pix, bool fresh, double chib, bool keep_h,
+                                              float* sHG, float4* sHa, int lane, bool& accept) {
+  constexpr int ROWS = 4 * NOBS;
+  const float* obs = A.stokes + pix * ROWS;
+  const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
+  float4* park = sHa + H4 * 64;
+  float acc[5][NACC];
+  synth_accumulate_win<V>(A.pts5, px, A.C, acc, park, lane);
+  double chi = 0.0;
+  float g[NPAR];
+#pragma unroll
+  for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
+  if (!keep_h) {
+#pragma unroll
+    for (int c = 0; c < H4; ++c) sHa[c * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  auto fold = [&](const float* a, int q) {
+    const int i = A.C.slot_row[q];
+    float S[4], J[4][NPAR], WJ[4][NPAR];
+    assemble_sample<true>(a, A.C.slot_rs[q], rf, S, J);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float w = Wp[s * NOBS + i];
+      const float r = obs[s * NOBS + i] - S[s];
+      chi = fma((double)w * (double)r, (double)r, chi);
+#pragma unroll
+      for (int p = 0; p < NPAR; ++p) {
+        WJ[s][p] = w * J[s][p];
+        g[p] = fmaf(WJ[s][p], r, g[p]);
+      }
+    }
+    if (!keep_h) {
+      lds_rmw4<0, H4>(sHa, lane, [&](int c, float4& h) {
+        float* hv = &h.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = 4 * c + k;
+          if (e < 55) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][pk_row(e)], J[s][pk_col(e)], hv[k]);
+          }
+        }
+      });
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < 5; ++q) fold(acc[q], q);
+  {
+    float a[NACC];
+    unpark(park, lane, a);
+    fold(a, 5);
+  }
+  chi *= A.inv_dof;
+  accept = fresh || (isfinite(chi) && chi < chib);
+  if (accept) {
+    if (!keep_h) {
+#pragma unroll
+      for (int c = 0; c < H4; ++c) {
+        const float4 h = sHa[c * 64 + lane];
+        const float hv[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (4 * c + k < 55) sHG[(4 * c + k) * 64 + lane] = hv[k];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
+  }
+  return chi;
+}
+
 template <int NOBS, int LPP, int V>
 __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int64_t pix,
                                           bool fresh, double chib, bool keep_h, float* sHG,
-                                          int lane, bool& accept) {
+                                          float4* sHa, int lane, bool& accept) {
   Pix px;
   pix_setup(Mc, A.C, px);
   RowFactors rf;
   row_factors(Mc, px, A.C, rf);
   double chi = 0.0;
+  if constexpr (NOBS > 0 && LPP == 1) {
+    if (A.C.sw_k >= 0) return lm_pass_win<NOBS, V>(A, px, rf, pix, fresh, chib, keep_h, sHG, sHa,
+                                                   lane, accept);
+  }
   if constexpr (NOBS > 0) {
     constexpr int ROWS = 4 * NOBS;
     const float* obs = A.stokes + pix * ROWS;
@@ -154,11 +239,13 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
     const int no = A.C.n_obs;
     const float* obs = A.stokes + pix * (int64_t)(4 * no);
     const float* Wp = A.W_pp ? A.W + pix * (int64_t)(4 * no) : A.W;
-    float H[55], g[NPAR];
+    // H (packed, entries 0-54) and g (55-64) are accumulated in the lane's
+    // slots of LDS (17 float4, lane-interleaved), read and written once per
+    // completed row, so that the registers hold the band window and the
+    // synthesis point
 #pragma unroll
-    for (int e = 0; e < 55; ++e) H[e] = 0.f;
-#pragma unroll
-    for (int e = 0; e < NPAR; ++e) g[e] = 0.f;
+    for (int c = 0; c < HG4; ++c)
+      if (c >= G4_FIRST || !keep_h) sHa[c * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     float ob[4], wb[4], rs = 0.f;
     band_accumulate<true>(
         A.blocks, no, px, A.C,
@@ -171,34 +258,49 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
           }
         },
         [&](int, const float* a) {
-          float S[4], J[4][NPAR];
+          float S[4], J[4][NPAR], WJ[4][NPAR], R[4];
           assemble_sample<true>(a, rs, rf, S, J);
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const float w = wb[s];
-            const float r = ob[s] - S[s];
-            chi = fma((double)w * (double)r, (double)r, chi);
+            R[s] = ob[s] - S[s];
+            chi = fma((double)w * (double)R[s], (double)R[s], chi);
 #pragma unroll
-            for (int p = 0; p < NPAR; ++p) g[p] = fmaf(w * J[s][p], r, g[p]);
-            if (!keep_h) {
+            for (int p = 0; p < NPAR; ++p) WJ[s][p] = w * J[s][p];
+          }
+          auto upd = [&](int c, float4& h) {
+            float* hv = &h.x;
 #pragma unroll
-              for (int p = 0; p < NPAR; ++p) {
-                const float wj = w * J[s][p];
+            for (int k = 0; k < 4; ++k) {
+              const int e = 4 * c + k;
+              if (e < 55 && !keep_h) {
 #pragma unroll
-                for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+                for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][pk_row(e)], J[s][pk_col(e)], hv[k]);
+              } else if (e >= 55 && e < 65) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][e - 55], R[s], hv[k]);
               }
             }
-          }
+          };
+          if (!keep_h)
+            lds_rmw4<0, HG4>(sHa, lane, upd);
+          else
+            lds_rmw4<G4_FIRST, HG4>(sHa, lane, upd);
         });
     chi *= A.inv_dof;
     accept = fresh || (isfinite(chi) && chi < chib);
     if (accept) {
-      if (!keep_h) {
 #pragma unroll
-        for (int e = 0; e < 55; ++e) sHG[e * 64 + lane] = H[e];
+      for (int c = 0; c < HG4; ++c) {
+        if (c < G4_FIRST && keep_h) continue;
+        const float4 h = sHa[c * 64 + lane];
+        const float hv[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = 4 * c + k;
+          if ((e < 55 && !keep_h) || (e >= 55 && e < 65)) sHG[e * 64 + lane] = hv[k];
+        }
       }
-#pragma unroll
-      for (int e = 0; e < NPAR; ++e) sHG[(55 + e) * 64 + lane] = g[e];
     }
   }
   return chi;
@@ -215,7 +317,8 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // pixel, restarts from a perturbed best model, the best model seen is the
 // result); otherwise exits on convergence, stall or A.max_iter.
 template <int NOBS, int LPP, int V = 0, bool PAPER = false>
-__device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, double* sws, int lane,
+__device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa, double* sws,
+                                        int lane,
                                         int64_t glane,
                                         WaveCounters& wc) {
   static_assert(LPP == 1 || (LPP == 2 && NOBS > 0), "lane pairs serve the dense layout");
@@ -355,7 +458,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, double* sws
     // Sect. 4.4: a step from a model already near the minimum keeps H
     const bool keep_h = !fresh && chib < A.hess_reuse;
     const double chi =
-        lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, keep_h, sHG, lane, accept);
+        lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, keep_h, sHG, sHa, lane, accept);
     if (leader && accept && !keep_h) ++wc.hess;
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
@@ -492,7 +595,8 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
 template <int NOBS, int V, bool PAPER>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
-  __shared__ double sws[WS_DOUBLES];  // the wave's eigen-fallback record
+  __shared__ float4 sHa[PASS4 * 64];  // the pass's accumulators in LDS
+  double* sws = ws_record(sHa);       // the wave's eigen-fallback record
   const int lane = threadIdx.x;
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
   WaveCounters wc;
@@ -500,11 +604,11 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
     // pairs only when every pixel gets two lanes that run at once
     if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)A.lane_cap)
-      lm_loop<NOBS, 2, V, PAPER>(A, sHG, sws, lane, glane, wc);
+      lm_loop<NOBS, 2, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
     else
-      lm_loop<NOBS, 1, V, PAPER>(A, sHG, sws, lane, glane, wc);
+      lm_loop<NOBS, 1, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
   } else {
-    lm_loop<NOBS, 1, V, PAPER>(A, sHG, sws, lane, glane, wc);
+    lm_loop<NOBS, 1, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
   }
   flush_counters(A.work, wc, lane);
 }
@@ -515,15 +619,16 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
 // the earlier ones.
 __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   __shared__ float sHG[65 * 64];
-  __shared__ double sws[WS_DOUBLES];
+  __shared__ float4 sHa[PASS4 * 64];
+  double* sws = ws_record(sHa);
   const int lane = threadIdx.x;
   const int64_t glane = (int64_t)blockIdx.x * 64 + lane;
   WaveCounters wc;
   for (int i = 0; i < B.n_batches; ++i) {
     if (B.kind[i] == KIND_DENSE6)
-      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, sws, lane, glane, wc);
+      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, sHa, sws, lane, glane, wc);
     else
-      lm_loop<0, 1>(B.a[i], sHG, sws, lane, glane, wc);
+      lm_loop<0, 1>(B.a[i], sHG, sHa, sws, lane, glane, wc);
   }
   flush_counters(B.a[0].work, wc, lane);
 }

@@ -47,6 +47,8 @@ constexpr double DEG_D = 0.017453292519943295769;
 constexpr double C_KMS = 299792.458;
 
 // Wave-uniform constants of one launch (kernel argument -> SGPRs).
+constexpr int OV_MAX = 4;  // records shared by the two rows of the register slot 4
+
 struct Consts {
   float wc[NW + 1];      // 2 * a_n, n = 1..NW (index 0 unused)
   float wL, wL2, w2L;    // Weideman L, L^2, 2L
@@ -55,11 +57,21 @@ struct Consts {
   int n_pts;             // synthesis points with a non-zero tap
   int n_obs;
   float row_sum[8];      // sum of the kept taps of each filter row
+  // Dense layout, windowed records (slot order): from record sw_k on, the
+  // register slot 4 takes a row that starts there, and the row it held
+  // (one that ends within OV_MAX records) is parked in LDS; -1 when the
+  // filter has no such pair of rows.  slot_row / slot_rs: filter row and row
+  // sum of each slot (slot 5: the parked row).
+  int sw_k;
+  int slot_row[6];
+  float slot_rs[6];
   const float2* vtab;    // Taylor table {H, F} [VT_NA][VT_NU] (Voigt variants 1, 2)
 };
 
 // One synthesis point: offset and the taps of the (up to 6) filter rows;
-// w[6] carries the bit mask of rows with a non-zero tap.  32 bytes.
+// w[6] carries the bit mask of rows with a non-zero tap.  32 bytes.  In the
+// windowed records w[0..4] are the taps of the five register slots and w[5]
+// the tap of the parked row.
 struct __attribute__((aligned(32))) Point {
   float dl;
   float w[7];
@@ -384,6 +396,103 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   }
 }
 
+// Read-modify-write of the float4 slots [C0, C1) of a lane-interleaved LDS
+// array (slot c of lane l at base[c * 64 + l]): each read is issued two
+// slots ahead of its arithmetic, so that its latency hides behind the
+// arithmetic of the slots before it (at one wave per SIMD nothing else
+// would).  f(c, h) updates slot c in place.
+template <int C0, int C1, class F>
+__device__ __forceinline__ void lds_rmw4(float4* __restrict__ base, int lane, F&& f) {
+  static_assert(C0 < C1, "empty slot range");
+  float4 a = base[C0 * 64 + lane];
+  float4 b = a;
+  if (C0 + 1 < C1) b = base[(C0 + 1) * 64 + lane];
+#pragma unroll
+  for (int c = C0; c < C1; ++c) {
+    float4 h = a;
+    a = b;
+    if (c + 2 < C1) b = base[(c + 2) * 64 + lane];
+    f(c, h);
+    base[c * 64 + lane] = h;
+  }
+}
+
+// The dense accumulation over windowed records (Consts::sw_k >= 0, so
+// 1 <= sw_k <= n_pts - 1): five register slots instead of six rows.  At
+// record sw_k the row held by slot 4 is parked in the lane's LDS slots
+// (8 float4, lane-interleaved) and slot 4 takes the row that starts there;
+// the parked row's taps on the records it still shares with that row (mask
+// bit 5) are added in LDS.  Every row receives the same sequence of
+// products as in synth_accumulate.
+constexpr int PARK4 = (NACC + 3) / 4;  // float4 slots of a parked row
+
+__device__ __forceinline__ float4 pack4(const float* a, int c) {
+  return make_float4(a[4 * c], 4 * c + 1 < NACC ? a[4 * c + 1] : 0.f,
+                     4 * c + 2 < NACC ? a[4 * c + 2] : 0.f, 4 * c + 3 < NACC ? a[4 * c + 3] : 0.f);
+}
+
+template <int V = 0>
+__device__ __forceinline__ void synth_accumulate_win(const Point* __restrict__ pts, const Pix& p,
+                                                     const Consts& C, float (&acc)[5][NACC],
+                                                     float4* __restrict__ park, int lane) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) acc[i][m] = 0.f;
+  const int last = C.n_pts - 1, sw = C.sw_k;
+  // two loops, before and after the switch, so that no accumulator is
+  // redefined inside a loop
+  auto point = [&](const Point& P, bool parked) {
+    float c[NACC];
+    point_contrib<true, V>(P.dl, p, C, c);
+    const uint32_t mask = __float_as_uint(P.w[6]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (mask & (1u << i)) {
+        const float w = P.w[i];
+#pragma unroll
+        for (int m = 0; m < NACC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
+      }
+    }
+    if (parked && (mask & 32u)) {
+      const float w = P.w[5];
+      lds_rmw4<0, PARK4>(park, lane, [&](int q, float4& t) {
+        t.x = fmaf(w, c[4 * q], t.x);
+        if (4 * q + 1 < NACC) t.y = fmaf(w, c[4 * q + 1], t.y);
+        if (4 * q + 2 < NACC) t.z = fmaf(w, c[4 * q + 2], t.z);
+        if (4 * q + 3 < NACC) t.w = fmaf(w, c[4 * q + 3], t.w);
+      });
+    }
+  };
+  Point P = load_uniform(pts, 0);
+  for (int k = 0; k < sw; ++k) {
+    const Point Pn = load_uniform(pts, k + 1);  // k + 1 <= sw <= last
+    point(P, false);
+    P = Pn;
+  }
+#pragma unroll
+  for (int c = 0; c < PARK4; ++c) park[c * 64 + lane] = pack4(acc[4], c);
+#pragma unroll
+  for (int m = 0; m < NACC; ++m) acc[4][m] = 0.f;
+  for (int k = sw; k <= last; ++k) {
+    const Point Pn = load_uniform(pts, k < last ? k + 1 : last);
+    point(P, true);
+    P = Pn;
+  }
+}
+
+// The parked row back in registers.
+__device__ __forceinline__ void unpark(const float4* __restrict__ park, int lane, float* a) {
+#pragma unroll
+  for (int q = 0; q < PARK4; ++q) {
+    const float4 t = park[q * 64 + lane];
+    a[4 * q] = t.x;
+    if (4 * q + 1 < NACC) a[4 * q + 1] = t.y;
+    if (4 * q + 2 < NACC) a[4 * q + 2] = t.z;
+    if (4 * q + 3 < NACC) a[4 * q + 3] = t.w;
+  }
+}
+
 // The same accumulation shared by a pair of lanes (lane & 1 = odd): each
 // lane takes every other synthesis point (two wave-uniform records per
 // step, each lane selecting its own), then the pair adds its partial sums,
@@ -548,6 +657,18 @@ __device__ __forceinline__ void assemble_sample(const float* acc, float row_sum,
 }
 
 __host__ __device__ constexpr int pk(int p, int q) { return p * (p + 1) / 2 + q; }
+// row and column of packed entry e (inverse of pk)
+__host__ __device__ constexpr int pk_row(int e) {
+  int p = 0;
+  while ((p + 1) * (p + 2) / 2 <= e) ++p;
+  return p;
+}
+__host__ __device__ constexpr int pk_col(int e) { return e - pk_row(e) * (pk_row(e) + 1) / 2; }
+// float4 slots holding the packed H (entries 0-54) and g (55-64); the
+// first slot that holds an entry of g
+constexpr int HG4 = (65 + 3) / 4, G4_FIRST = 55 / 4;
+constexpr int H4 = (55 + 3) / 4;  // float4 slots holding the packed H alone
+static_assert(pk_row(54) == 9 && pk_col(54) == 9 && pk_row(45) == 9 && pk_col(44) == 8, "pk");
 
 // ---------------------------------------------------------------------
 // Damped solve in float64 (Eqs. 3-5 with the diagonal scaled by 1 + eps):
@@ -631,6 +752,16 @@ __device__ __forceinline__ int solve_cholesky(const float* H, const float* g, do
 // on a workspace in global memory, strided across the grid's lanes, and
 // always for its 60 sweeps, it took milliseconds per call.)
 constexpr int WS_DOUBLES = 210;
+
+// LDS of a pass, per wave, in float4 slots of 64 lanes: the banded pass's H
+// and g (HG4), or the windowed dense pass's H (H4) and parked row (PARK4).
+// The eigen-fallback record lies in the parked row's slots: it is used
+// between passes only.
+constexpr int PASS4 = (HG4 > H4 + PARK4) ? HG4 : H4 + PARK4;
+static_assert(PARK4 * 64 * 16 >= WS_DOUBLES * 8, "the fallback record fits the parked row");
+__device__ __forceinline__ double* ws_record(float4* sHa) {
+  return reinterpret_cast<double*>(sHa + H4 * 64);
+}
 
 // Called by all 64 lanes of a one-wave workgroup for the system of lane
 // L: H (packed, element stride hs) and g (stride gs) are read through
