@@ -112,20 +112,22 @@ __device__ __forceinline__ double lm_pass_win(const LMArgs& A, const Pix& px, co
 #pragma unroll
       for (int p = 0; p < NPAR; ++p) {
         WJ[s][p] = w * J[s][p];
-        g[p] = fmaf(WJ[s][p], r, g[p]);
+        if (!jzero(s, p)) g[p] = fmaf(WJ[s][p], r, g[p]);
       }
     }
     if (!keep_h) {
-      lds_rmw4<0, H4>(sHa, lane, [&](int c, float4& h) {
+      lds_rmw4<0, H4>(sHa, lane, [&](auto cc, float4& h) __attribute__((always_inline)) {
         float* hv = &h.x;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int e = 4 * c + k;
-          if (e < 55) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][pk_row(e)], J[s][pk_col(e)], hv[k]);
+        static_for<4>([&](auto kk) __attribute__((always_inline)) {
+          constexpr int k = decltype(kk)::value, e = 4 * decltype(cc)::value + k;
+          if constexpr (e < 55) {
+            constexpr int p = pk_row(e), q2 = pk_col(e);
+            static_for<4>([&](auto ss) __attribute__((always_inline)) {
+              constexpr int s = decltype(ss)::value;
+              if constexpr (!hzero(s, e)) hv[k] = fmaf(WJ[s][p], J[s][q2], hv[k]);
+            });
           }
-        }
+        });
       });
     }
   };
@@ -206,9 +208,11 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 #pragma unroll
           for (int p = 0; p < NPAR; ++p) {
             const float wj = w * J[s][p];
+            if (jzero(s, p)) continue;
             g[p] = fmaf(wj, r, g[p]);
 #pragma unroll
-            for (int q = 0; q <= p; ++q) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
+            for (int q = 0; q <= p; ++q)
+              if (!jzero(s, q)) H[pk(p, q)] = fmaf(wj, J[s][q], H[pk(p, q)]);
           }
         }
       }
@@ -229,7 +233,8 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
           const float w = Wp[s * NOBS + i];
           const float r = obs[s * NOBS + i] - S[s];
 #pragma unroll
-          for (int p = 0; p < NPAR; ++p) g[p] = fmaf(w * J[s][p], r, g[p]);
+          for (int p = 0; p < NPAR; ++p)
+            if (!jzero(s, p)) g[p] = fmaf(w * J[s][p], r, g[p]);
         }
       }
 #pragma unroll
@@ -268,24 +273,33 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 #pragma unroll
             for (int p = 0; p < NPAR; ++p) WJ[s][p] = w * J[s][p];
           }
-          auto upd = [&](int c, float4& h) {
+          // slot c: entries of H (unless H is kept) and of g
+          auto upd = [&](auto cc, float4& h, auto with_h) __attribute__((always_inline)) {
             float* hv = &h.x;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int e = 4 * c + k;
-              if (e < 55 && !keep_h) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][pk_row(e)], J[s][pk_col(e)], hv[k]);
-              } else if (e >= 55 && e < 65) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) hv[k] = fmaf(WJ[s][e - 55], R[s], hv[k]);
+            static_for<4>([&](auto kk) __attribute__((always_inline)) {
+              constexpr int k = decltype(kk)::value, e = 4 * decltype(cc)::value + k;
+              if constexpr (e < 55 && decltype(with_h)::value) {
+                constexpr int p = pk_row(e), q2 = pk_col(e);
+                static_for<4>([&](auto ss) __attribute__((always_inline)) {
+                  constexpr int s = decltype(ss)::value;
+                  if constexpr (!hzero(s, e)) hv[k] = fmaf(WJ[s][p], J[s][q2], hv[k]);
+                });
+              } else if constexpr (e >= 55 && e < 65) {
+                static_for<4>([&](auto ss) __attribute__((always_inline)) {
+                  constexpr int s = decltype(ss)::value;
+                  if constexpr (!jzero(s, e - 55)) hv[k] = fmaf(WJ[s][e - 55], R[s], hv[k]);
+                });
               }
-            }
+            });
           };
           if (!keep_h)
-            lds_rmw4<0, HG4>(sHa, lane, upd);
+            lds_rmw4<0, HG4>(sHa, lane, [&](auto cc, float4& h) __attribute__((always_inline)) {
+              upd(cc, h, std::true_type{});
+            });
           else
-            lds_rmw4<G4_FIRST, HG4>(sHa, lane, upd);
+            lds_rmw4<G4_FIRST, HG4>(sHa, lane, [&](auto cc, float4& h) __attribute__((always_inline)) {
+              upd(cc, h, std::false_type{});
+            });
         });
     chi *= A.inv_dof;
     accept = fresh || (isfinite(chi) && chi < chib);

@@ -34,6 +34,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace vfisv {
 
 constexpr int NPAR = 10;
@@ -396,25 +399,42 @@ __device__ __forceinline__ void synth_accumulate(const Point* __restrict__ pts, 
   }
 }
 
+// f(std::integral_constant<int, I>{}) for I = 0 .. N-1: the index is a
+// constant expression in f, so tables indexed by it fold at compile time
+// whatever the unrolling heuristics decide.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Read-modify-write of the float4 slots [C0, C1) of a lane-interleaved LDS
 // array (slot c of lane l at base[c * 64 + l]): each read is issued two
 // slots ahead of its arithmetic, so that its latency hides behind the
 // arithmetic of the slots before it (at one wave per SIMD nothing else
-// would).  f(c, h) updates slot c in place.
+// would).  f(std::integral_constant<int, c>, h) updates slot c in place.
+template <int C, int C1, class F>
+__device__ __forceinline__ void lds_rmw4_from(float4* __restrict__ base, int lane, float4 a,
+                                              float4 b, F& f) {
+  if constexpr (C < C1) {
+    float4 nb = b;
+    if constexpr (C + 2 < C1) nb = base[(C + 2) * 64 + lane];
+    float4 h = a;
+    f(std::integral_constant<int, C>{}, h);
+    base[C * 64 + lane] = h;
+    lds_rmw4_from<C + 1, C1>(base, lane, b, nb, f);
+  }
+}
 template <int C0, int C1, class F>
 __device__ __forceinline__ void lds_rmw4(float4* __restrict__ base, int lane, F&& f) {
   static_assert(C0 < C1, "empty slot range");
-  float4 a = base[C0 * 64 + lane];
+  const float4 a = base[C0 * 64 + lane];
   float4 b = a;
-  if (C0 + 1 < C1) b = base[(C0 + 1) * 64 + lane];
-#pragma unroll
-  for (int c = C0; c < C1; ++c) {
-    float4 h = a;
-    a = b;
-    if (c + 2 < C1) b = base[(c + 2) * 64 + lane];
-    f(c, h);
-    base[c * 64 + lane] = h;
-  }
+  if constexpr (C0 + 1 < C1) b = base[(C0 + 1) * 64 + lane];
+  lds_rmw4_from<C0, C1>(base, lane, a, b, f);
 }
 
 // The dense accumulation over windowed records (Consts::sw_k >= 0, so
@@ -456,11 +476,12 @@ __device__ __forceinline__ void synth_accumulate_win(const Point* __restrict__ p
     }
     if (parked && (mask & 32u)) {
       const float w = P.w[5];
-      lds_rmw4<0, PARK4>(park, lane, [&](int q, float4& t) {
+      lds_rmw4<0, PARK4>(park, lane, [&](auto qq, float4& t) __attribute__((always_inline)) {
+        constexpr int q = decltype(qq)::value;
         t.x = fmaf(w, c[4 * q], t.x);
-        if (4 * q + 1 < NACC) t.y = fmaf(w, c[4 * q + 1], t.y);
-        if (4 * q + 2 < NACC) t.z = fmaf(w, c[4 * q + 2], t.z);
-        if (4 * q + 3 < NACC) t.w = fmaf(w, c[4 * q + 3], t.w);
+        if constexpr (4 * q + 1 < NACC) t.y = fmaf(w, c[4 * q + 1], t.y);
+        if constexpr (4 * q + 2 < NACC) t.z = fmaf(w, c[4 * q + 2], t.z);
+        if constexpr (4 * q + 3 < NACC) t.w = fmaf(w, c[4 * q + 3], t.w);
       });
     }
   };
@@ -657,6 +678,20 @@ __device__ __forceinline__ void assemble_sample(const float* acc, float row_sum,
 }
 
 __host__ __device__ constexpr int pk(int p, int q) { return p * (p + 1) / 2 + q; }
+// Jacobian entries that assemble_sample sets to zero by construction: the
+// azimuth column of I and V, the S0 column of Q, U and V.  Products with
+// them are left out of g and H (for finite entries that changes nothing).
+__host__ __device__ constexpr bool jzero(int s, int p) {
+  return (p == 2 && (s == 0 || s == 3)) || (p == 7 && s != 0);
+}
+// The same for packed entry e of H (row or column 2, row or column 7),
+// written without a loop so that it folds in unrolled code.
+__host__ __device__ constexpr bool hzero(int s, int e) {
+  const bool in2 = (e >= 3 && e <= 5) || e == 8 || e == 12 || e == 17 || e == 23 || e == 30 ||
+                   e == 38 || e == 47;
+  const bool in7 = (e >= 28 && e <= 35) || e == 43 || e == 52;
+  return ((s == 0 || s == 3) && in2) || (s != 0 && in7);
+}
 // row and column of packed entry e (inverse of pk)
 __host__ __device__ constexpr int pk_row(int e) {
   int p = 0;
@@ -669,6 +704,13 @@ __host__ __device__ constexpr int pk_col(int e) { return e - pk_row(e) * (pk_row
 constexpr int HG4 = (65 + 3) / 4, G4_FIRST = 55 / 4;
 constexpr int H4 = (55 + 3) / 4;  // float4 slots holding the packed H alone
 static_assert(pk_row(54) == 9 && pk_col(54) == 9 && pk_row(45) == 9 && pk_col(44) == 8, "pk");
+constexpr bool hzero_matches() {
+  for (int s = 0; s < 4; ++s)
+    for (int e = 0; e < 55; ++e)
+      if (hzero(s, e) != (jzero(s, pk_row(e)) || jzero(s, pk_col(e)))) return false;
+  return true;
+}
+static_assert(hzero_matches(), "hzero lists the entries of H with a zero factor");
 
 // ---------------------------------------------------------------------
 // Damped solve in float64 (Eqs. 3-5 with the diagonal scaled by 1 + eps):
