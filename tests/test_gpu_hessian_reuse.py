@@ -117,3 +117,49 @@ def test_reuse_statistics_match_the_oracle(setup):
     assert abs(a - b) / b < 0.05
     assert abs(ia - ib) / ib < 0.1
     assert kept_r > 0.05 and abs(kept_g - kept_r) < 0.05
+
+
+@pytest.fixture(scope="module")
+def fine_setup(setup):
+    ctx = setup[0]
+    spec = wl.fine_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+    n = 192
+    P = wl.draw_params(n, 73)
+    obs = (oracle.forward_batch(oi, P) + wl.draw_noise(n, spec.n_obs, 73)).astype(np.float32)
+    W = wl.weights(spec.n_obs)
+    dev = ctx.device
+    return ctx, inst, oi, P, obs, W, torch.tensor(obs, device=dev), torch.tensor(W, device=dev)
+
+
+def test_banded_reuse_linear_model_and_first_steps(fine_setup):
+    """The banded layout accumulates g alone when the Hessian is kept: with
+    only S0 and S1 free the kept Hessian gives the plain fit bit for bit and
+    the oracle's minimum; three trials with the start's Hessian follow the
+    oracle's path."""
+    ctx, inst, oi, P, obs, W, to, tW = fine_setup
+    print("[gpu-hess] banded layout, %d pixels" % len(P), flush=True)
+    mask = (1 << 7) | (1 << 8)
+    init = P.copy()
+    init[:, 7:9] = [0.45, 0.3]
+    ti = torch.tensor(init.astype(np.float32), device=ctx.device)
+    a = _np(vf.invert(ctx, inst, to, tW, init=ti, opts=vf.Options(free_mask=mask)))
+    b = _np(vf.invert(ctx, inst, to, tW, init=ti,
+                      opts=vf.Options(free_mask=mask, hess_reuse=BIG)))
+    c = ctx.counters()
+    assert c["hessians"] == c["pixels"] == len(P) and c["accepts"] > 0
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    ref = oracle.invert(oi, obs, W, init=init.astype(np.float32).astype(np.float64),
+                        opts=oracle.Options(free_mask=mask, hess_reuse=BIG))
+    rel = np.abs(b["chi2"] - ref["chi2"]) / ref["chi2"]
+    assert np.quantile(rel, 0.99) < 2e-4
+    np.testing.assert_allclose(b["params"][:, 7:9], ref["params"][:, 7:9], rtol=0, atol=2e-4)
+    opts = dict(max_iter=3, hess_reuse=BIG)
+    out = _np(vf.invert(ctx, inst, to, tW, opts=vf.Options(**opts)))
+    ref = oracle.invert(oi, obs, W, opts=oracle.Options(**opts))
+    same = np.isclose(out["params"][:, 0], ref["params"][:, 0], rtol=1e-3, atol=0.5)
+    print("[gpu-hess] banded, 3 kept-H steps: %.3f on the oracle's path" % same.mean(),
+          flush=True)
+    assert same.mean() > 0.9
