@@ -1,6 +1,6 @@
 """GPU parity: libvfisv.so (through the C ABI) against the FP64 oracle.
 
-Tolerances (derivations in DESIGN.md, "Parity bar"):
+Tolerances (each derived from the float32 arithmetic of the step it bounds):
 * synthesis values: |S_gpu - S_ref| <= 2e-6 (float32 Faddeeva series, ~6e-7
   relative, through the Unno-Rachkovsky quotients);
 * Jacobian: |J_gpu - J_ref| <= 2e-4 * column max + 3e-5 * typical column
