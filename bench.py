@@ -9,7 +9,7 @@ line.
 
 Workload (the learned-initialiser configuration): HMI-shaped pixels (Fe I
 6173.3356 A, 6 Gaussian filters, 101-point synthesis grid), parameters from
-the cfg0 priors, N(0, 1e-3) noise, W = 1e6.
+the synthetic priors, N(0, 1e-3) noise, W = 1e6.
 * training set: 10M pixels (seed 1003), control set 250k (seed 1103);
 * held-out set: 1M pixels (seed 2003) -- the timed batch.
 Learned path: network start, <= 15 LM trials, plain-LM fallback (<= 50 trials
@@ -156,10 +156,10 @@ def main():
     # ---- training (untimed) -----------------------------------------------
     t0 = time.perf_counter()
     S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
-                                           wl.CONFIGS["cfg3_train"]["seed"], wl.draw_params,
+                                           wl.CONFIGS["learned_train"]["seed"], wl.draw_params,
                                            wl.draw_noise)
     S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
-                                           wl.CONFIGS["cfg3_control"]["seed"], wl.draw_params,
+                                           wl.CONFIGS["learned_control"]["seed"], wl.draw_params,
                                            wl.draw_noise)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
@@ -171,7 +171,7 @@ def main():
 
     # ---- held-out batch -----------------------------------------------------
     n = args.n
-    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    seed = wl.CONFIGS["learned_heldout"]["seed"]
     P = wl.draw_params(n, seed)
     noise = wl.draw_noise(n, n_obs, seed)
     obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
@@ -252,7 +252,7 @@ def main():
         "dtype": "f32+f64 (LM), bf16/f32 (network)",
         "data": "synthetic",
         "config": {
-            "workload": "1M held-out HMI-shaped pixels (cfg0 priors, seed 2003, noise 1e-3); "
+            "workload": "1M held-out HMI-shaped pixels (synthetic priors, seed 2003, noise 1e-3); "
                         "learned start + <= %d LM trials + plain-LM fallback"
                         % args.learned_max_iter,
             "pixels": n,
@@ -331,7 +331,7 @@ def full_disk(args, ctx, inst, spec, log):
     import workloads as wl
     dev = ctx.device
     stream = torch.cuda.current_stream(dev)
-    seed = wl.CONFIGS["cfg2"]["seed"]
+    seed = wl.CONFIGS["full_disk"]["seed"]
     n_obs = spec.n_obs
     W = torch.tensor(wl.weights(n_obs), device=dev)
 
@@ -427,7 +427,7 @@ def full_disk(args, ctx, inst, spec, log):
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "full disk 4096^2 (13,176,792 pixels), 80%% quiet "
                                "(B ~ U[0,200] G) / 20%% active (B ~ U[500,3500] G) in clustered "
-                               "regions, cfg0 priors otherwise, seed %d; plain LM from the "
+                               "regions, synthetic priors otherwise, seed %d; plain LM from the "
                                "default model, <= 50 trials" % seed,
                    "pixels": n, "active_fraction": round(float(active.mean()), 5)},
         "iterations": {
@@ -495,8 +495,8 @@ def fine_mixed(args, ctx, inst, spec, log):
         return P, noise, obs, torch.tensor(wl.weights(sp.n_obs), device=dev)
 
     t0 = time.perf_counter()
-    Pf, nf_, of, Wf = make(fspec, finst, n_f, wl.CONFIGS["cfg4_fine"]["seed"])
-    Ph, nh_, oh, Wh = make(spec, inst, n_h, wl.CONFIGS["cfg4_hmi"]["seed"])
+    Pf, nf_, of, Wf = make(fspec, finst, n_f, wl.CONFIGS["mixed_fine"]["seed"])
+    Ph, nh_, oh, Wh = make(spec, inst, n_h, wl.CONFIGS["mixed_hmi"]["seed"])
     torch.cuda.synchronize()
     log("fine + HMI inputs in %.1f s" % (time.perf_counter() - t0))
     out_f, out_h = vf._alloc_out(n_f, dev), vf._alloc_out(n_h, dev)
@@ -545,11 +545,11 @@ def fine_mixed(args, ctx, inst, spec, log):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "%d fine-spectrum pixels (Fe I 6302.4936 A, 112 samples at "
                                "21.5 mA, 15-tap Gaussian of 25 mA FWHM on a 464-point grid, "
-                               "seed %d) + %d HMI-shaped pixels (seed %d), cfg0 priors, noise "
+                               "seed %d) + %d HMI-shaped pixels (seed %d), synthetic priors, noise "
                                "1e-3; plain LM from the default model, <= 50 trials; one "
                                "launch, fine batch first"
-                               % (n_f, wl.CONFIGS["cfg4_fine"]["seed"], n_h,
-                                  wl.CONFIGS["cfg4_hmi"]["seed"]),
+                               % (n_f, wl.CONFIGS["mixed_fine"]["seed"], n_h,
+                                  wl.CONFIGS["mixed_hmi"]["seed"]),
                    "pixels": n},
         "autotune": tuning,
         "separate_launches_ms": {"fine": round(ms_f, 3), "hmi": round(ms_h, 3),
@@ -603,8 +603,8 @@ def parity(args, ctx, inst, spec, log):
     import paper_0901_2702_amd as vf
     import workloads as wl
     dev = ctx.device
-    n = wl.CONFIGS["cfg1"]["n"]
-    seed = wl.CONFIGS["cfg1"]["seed"]
+    n = wl.CONFIGS["hmi_512x512"]["n"]
+    seed = wl.CONFIGS["hmi_512x512"]["seed"]
     m = min(args.cpu_sample, n)
     n_obs = spec.n_obs
     P = wl.draw_params(n, seed)
@@ -617,7 +617,7 @@ def parity(args, ctx, inst, spec, log):
     names = ["B", "gamma", "psi", "v", "dlD", "a", "eta0", "S0", "S1", "alpha"]
     tol = {"B": 1.0, "gamma": 0.1, "psi": 0.1, "v": 1e-3}
     result = {"metric": "per-parameter |GPU - FP64 oracle| on the 512x512 HMI set",
-              "config": {"workload": "262,144 HMI-shaped pixels (cfg0 priors, seed %d, noise "
+              "config": {"workload": "262,144 HMI-shaped pixels (synthetic priors, seed %d, noise "
                                      "1e-3); GPU on all, oracle on the first %d" % (seed, m),
                          "tolerances": "B 1 G, gamma and psi 0.1 deg, v 1 m/s, chi2 1e-4 "
                                        "relative"}}
@@ -679,17 +679,17 @@ def init_compare(args, ctx, inst, spec, log):
     stream = torch.cuda.current_stream(dev)
     n_obs = spec.n_obs
     S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
-                                           wl.CONFIGS["cfg3_train"]["seed"], wl.draw_params,
+                                           wl.CONFIGS["learned_train"]["seed"], wl.draw_params,
                                            wl.draw_noise)
     S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
-                                           wl.CONFIGS["cfg3_control"]["seed"], wl.draw_params,
+                                           wl.CONFIGS["learned_control"]["seed"], wl.draw_params,
                                            wl.draw_noise)
     net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
                                batch=4096, lr=2e-3, log=log)
     del S_tr
     torch.cuda.empty_cache()
     n = args.n
-    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    seed = wl.CONFIGS["learned_heldout"]["seed"]
     P = wl.draw_params(n, seed)
     noise = wl.draw_noise(n, n_obs, seed)
     obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
@@ -760,7 +760,7 @@ def init_compare(args, ctx, inst, spec, log):
                               (("sigma_B_G", 0), ("sigma_gamma_deg", 1), ("sigma_psi_deg", 2))}
     result = {"metric": "starting models for the same LM: default / classical / network / "
                         "combined",
-              "config": {"workload": "1M held-out HMI-shaped pixels (cfg0 priors, seed %d, "
+              "config": {"workload": "1M held-out HMI-shaped pixels (synthetic priors, seed %d, "
                                      "noise 1e-3); plain LM (convergence exits, <= 50 trials) "
                                      "from each start; network trained on %d pixels"
                                      % (seed, args.train_samples)},
@@ -781,9 +781,9 @@ def hess_reuse(args, ctx, inst, spec, log):
     dev = ctx.device
     stream = torch.cuda.current_stream(dev)
     result = {"metric": "plain LM with the Hessian kept near the minimum", "cases": {}}
-    for name, sp, n, seed in (("hmi", spec, args.n, wl.CONFIGS["cfg3_heldout"]["seed"]),
+    for name, sp, n, seed in (("hmi", spec, args.n, wl.CONFIGS["learned_heldout"]["seed"]),
                               ("fine", wl.fine_instrument(), 100_000,
-                               wl.CONFIGS["cfg4_fine"]["seed"])):
+                               wl.CONFIGS["mixed_fine"]["seed"])):
         ins = inst if name == "hmi" else vf.Instrument.from_spec(ctx, sp)
         P = wl.draw_params(n, seed)
         noise = wl.draw_noise(n, sp.n_obs, seed)
@@ -825,7 +825,7 @@ def plain_only(args, ctx, inst, spec, log):
     import workloads as wl
     dev = ctx.device
     n = args.n
-    seed = wl.CONFIGS["cfg3_heldout"]["seed"]
+    seed = wl.CONFIGS["learned_heldout"]["seed"]
     P = wl.draw_params(n, seed)
     noise = wl.draw_noise(n, spec.n_obs, seed)
     obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),

@@ -32,7 +32,7 @@ def test_full_disk_plain_lm():
     spec = wl.hmi_instrument()
     inst = vf.Instrument.from_spec(ctx, spec)
     oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
-    seed = wl.CONFIGS["cfg2"]["seed"]
+    seed = wl.CONFIGS["full_disk"]["seed"]
     P, active, mask = wl.full_disk(seed=seed)
     n = P.shape[0]
     assert n == 13_176_792

@@ -28,7 +28,7 @@ def test_full_disk_split_ranges_and_clustering():
         B = P[:, 0]
         assert (B[active] >= 500).all() and (B[active] <= 3500).all()
         assert (B[~active] >= 0).all() and (B[~active] <= 200).all()
-        # the other parameters keep the cfg0 priors
+        # the other parameters keep the synthetic priors
         assert (P[:, 4] >= 20).all() and (P[:, 4] <= 50).all()
         np.testing.assert_allclose(P[:, 7] + P[:, 8], 1.0)
         # neighbour of an active pixel is active: clustered >> i.i.d.

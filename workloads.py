@@ -16,13 +16,13 @@ synthetic; shapes follow the paper's HMI set-up of Sect. 1 and Sect. 5):
   profile; synthesis on a x4 grid padded by 8 points per side (464 points),
   15-tap rows.
 
-Full disk ("cfg2"): the pixels of a 4096 x 4096 image inside the disk of
+Full disk: the pixels of a 4096 x 4096 image inside the disk of
 centre (2047.5, 2047.5) and radius 2048 (13,176,792 pixels, row-major), 80%
 quiet (B ~ U[0,200] G) and 20% active (B ~ U[500,3500] G); active pixels are
 a seeded union of random discs (spatially clustered load), or i.i.d. in the
-variant; the other parameters follow the cfg0 priors.
+variant; the other parameters follow the synthetic priors.
 
-Parameter priors ("cfg0"): B ~ U[0,3000] G, cos(gamma) ~ U[-1,1],
+Parameter priors (every workload): B ~ U[0,3000] G, cos(gamma) ~ U[-1,1],
 psi ~ U[0,180) deg, v ~ U[-3,3] km/s, Doppler width ~ U[20,50] mA,
 a ~ U[0,0.5], eta0 ~ U[1,30], S0 ~ U[0.1,0.5], S1 = 1 - S0,
 alpha ~ U[0.2,1].  Noise: N(0, 1e-3) added to every observed sample.
@@ -36,14 +36,14 @@ FWHM_TO_SIGMA = 1.0 / (2.0 * np.sqrt(2.0 * np.log(2.0)))
 
 # Sizes and seeds of the workloads.
 CONFIGS = {
-    "cfg0": dict(n=64 * 64, seed=1000),
-    "cfg1": dict(n=512 * 512, seed=1001),
-    "cfg2": dict(grid=4096, seed=1002),
-    "cfg3_train": dict(n=10_000_000, seed=1003),
-    "cfg3_control": dict(n=250_000, seed=1103),
-    "cfg3_heldout": dict(n=1_000_000, seed=2003),
-    "cfg4_fine": dict(n=1_000_000, seed=1004),
-    "cfg4_hmi": dict(n=1_000_000, seed=1104),
+    "hmi_64x64": dict(n=64 * 64, seed=1000),
+    "hmi_512x512": dict(n=512 * 512, seed=1001),
+    "full_disk": dict(grid=4096, seed=1002),
+    "learned_train": dict(n=10_000_000, seed=1003),
+    "learned_control": dict(n=250_000, seed=1103),
+    "learned_heldout": dict(n=1_000_000, seed=2003),
+    "mixed_fine": dict(n=1_000_000, seed=1004),
+    "mixed_hmi": dict(n=1_000_000, seed=1104),
 }
 
 
@@ -90,7 +90,7 @@ def fine_instrument(n_obs=112, step_mA=21.5, oversample=4, pad=8, fwhm_mA=25.0, 
     return InstrumentSpec("fine", 6302.4936, 2.5, fine, F, obs)
 
 
-def draw_params(n, seed, prior="cfg0", b_range=None):
+def draw_params(n, seed, b_range=None):
     """[n, 10] float64 parameter vectors in API units."""
     rng = np.random.default_rng(seed)
     P = np.empty((n, NPAR))
@@ -123,7 +123,7 @@ def weights(n_obs, sigma=1e-3, w=(1.0, 1.0, 1.0, 1.0)):
 
 
 def default_model():
-    """The plain-LM starting model: midpoints of the cfg0 priors."""
+    """The plain-LM starting model: midpoints of the synthetic priors."""
     return np.array([1500.0, 90.0, 90.0, 0.0, 35.0, 0.25, 15.5, 0.3, 0.7, 0.6])
 
 
