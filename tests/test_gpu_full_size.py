@@ -1,0 +1,135 @@
+"""Parity at the configurations' full sizes, in the launch configuration the
+benchmark times: the 512 x 512 HMI set (262,144 pixels) and the mixed launch
+of 1M fine-spectrum and 1M HMI pixels.
+
+The whole set is synthesised on the device; a seeded sample instead gets
+observations synthesised by the FP64 oracle, so that for those pixels the
+oracle and the GPU see identical float32 inputs.  Checked: properties that
+hold at any size (status and iteration ranges, the box, work counters, the
+exact iteration histogram), the mixed launch against separate launches bit
+for bit, the GPU's chi^2 re-evaluated by the oracle at the GPU's own result,
+and the oracle's own inversion of the sample (statistically)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+vf = pytest.importorskip("paper_0901_2702_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[full-size] " + msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return vf.Context(0)
+
+
+def _set(ctx, spec, inst, oi, n, seed, n_sample, sample_seed):
+    """Device observations of n pixels, with oracle-made observations on a
+    seeded sample; returns (P, sample indices, float32 sample observations,
+    device observations)."""
+    dev = ctx.device
+    P = wl.draw_params(n, seed)
+    noise = wl.draw_noise(n, spec.n_obs, seed).astype(np.float32)
+    obs = vf.synthesize(ctx, inst, torch.tensor(P.astype(np.float32), device=dev),
+                        noise=torch.tensor(noise, device=dev))
+    smp = np.sort(np.random.default_rng(sample_seed).choice(n, n_sample, replace=False))
+    obs_s = (oracle.forward_batch(oi, P[smp]) + noise[smp].astype(np.float64)).astype(np.float32)
+    obs[torch.tensor(smp, device=dev)] = torch.tensor(obs_s, device=dev)
+    return P, smp, obs_s, obs
+
+
+def _properties(ctx, out, n, max_iter=50):
+    st = out["status"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    params = out["params"].cpu().numpy()
+    chi2 = out["chi2"].cpu().numpy()
+    assert np.isin(st, (0, 1, 2)).all()
+    assert iters.min() >= 1 and iters.max() <= max_iter
+    assert np.isfinite(params).all() and np.isfinite(chi2).all() and (chi2 >= 0).all()
+    assert np.array_equal(vf.iter_histogram(ctx, out["iters"], max_iter + 1),
+                          np.bincount(iters, minlength=max_iter + 1))
+    for p, lo, hi in ((0, 0, 5000), (1, 0, 180), (2, 0, 180), (3, -20, 20), (4, 5, 150),
+                      (5, 0, 5), (6, 1e-3, 1e3), (7, -1, 3), (8, 0, 5), (9, 0, 1)):
+        assert (params[:, p] >= lo).all() and (params[:, p] <= hi).all(), p
+    return st, iters, params, chi2
+
+
+def _sample_checks(name, oi, W, obs_s, gp, gc, gi, ev_med, ev_max, stat_tol, iter_tol):
+    # the GPU's chi^2 at its own result, re-evaluated by the oracle
+    ev = oracle.invert(oi, obs_s, W, init=gp.astype(np.float64), opts=oracle.Options(max_iter=0))
+    rel = np.abs(gc - ev["chi2"]) / ev["chi2"]
+    _say("%s: chi2 at the GPU result, oracle vs GPU: median %.2e max %.2e"
+         % (name, np.median(rel), rel.max()))
+    assert np.median(rel) < ev_med and rel.max() < ev_max
+    # the oracle's own inversion of the sample from the default start
+    ref = oracle.invert(oi, obs_s, W)
+    a, b = np.median(gc), np.median(ref["chi2"])
+    ia, ib = gi.mean(), ref["iters"].mean()
+    _say("%s: median chi2 gpu %.4f oracle %.4f; mean trials gpu %.2f oracle %.2f"
+         % (name, a, b, ia, ib))
+    assert abs(a - b) / b < stat_tol
+    assert abs(np.mean(gc < 2.0) - np.mean(ref["chi2"] < 2.0)) < 0.08
+    assert abs(ia - ib) / ib < iter_tol
+
+
+def test_hmi_512x512_full_size(ctx):
+    spec = wl.hmi_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+    cfg = wl.CONFIGS["hmi_512x512"]
+    n = cfg["n"]
+    assert n == 262_144
+    P, smp, obs_s, obs = _set(ctx, spec, inst, oi, n, cfg["seed"], 512, 5150)
+    W = wl.weights(spec.n_obs)
+    _say("inverting %d HMI pixels" % n)
+    out = vf.invert(ctx, inst, obs, torch.tensor(W, device=ctx.device))
+    c = ctx.counters()
+    st, iters, params, chi2 = _properties(ctx, out, n)
+    assert c["pixels"] == n and c["trials"] == int(iters.sum())
+    assert c["passes"] == c["trials"] + n
+    _sample_checks("hmi 512x512", oi, W, obs_s, params[smp], chi2[smp], iters[smp],
+                   2e-5, 1e-3, 0.1, 0.12)
+
+
+def test_fine_and_hmi_full_size_in_one_launch(ctx):
+    fspec, hspec = wl.fine_instrument(), wl.hmi_instrument()
+    finst = vf.Instrument.from_spec(ctx, fspec)
+    hinst = vf.Instrument.from_spec(ctx, hspec)
+    foi = oracle.Instrument(fspec.lambda0_A, fspec.geff, fspec.fine_offset_mA, fspec.filter)
+    hoi = oracle.Instrument(hspec.lambda0_A, hspec.geff, hspec.fine_offset_mA, hspec.filter)
+    nf, nh = wl.CONFIGS["mixed_fine"]["n"], wl.CONFIGS["mixed_hmi"]["n"]
+    assert nf == nh == 1_000_000
+    _say("synthesising %d fine + %d HMI pixels" % (nf, nh))
+    Pf, sf, of_s, of = _set(ctx, fspec, finst, foi, nf, wl.CONFIGS["mixed_fine"]["seed"], 96,
+                            5151)
+    Ph, sh, oh_s, oh = _set(ctx, hspec, hinst, hoi, nh, wl.CONFIGS["mixed_hmi"]["seed"], 256,
+                            5152)
+    dev = ctx.device
+    Wf, Wh = wl.weights(fspec.n_obs), wl.weights(hspec.n_obs)
+    tWf, tWh = torch.tensor(Wf, device=dev), torch.tensor(Wh, device=dev)
+    _say("one launch")
+    mixed = vf.invert_batches(ctx, [dict(inst=finst, stokes=of, W=tWf),
+                                    dict(inst=hinst, stokes=oh, W=tWh)])
+    c = ctx.counters()
+    _say("separate launches")
+    sep_f = vf.invert(ctx, finst, of, tWf)
+    sep_h = vf.invert(ctx, hinst, oh, tWh)
+    for a, b in ((mixed[0], sep_f), (mixed[1], sep_h)):
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+    stf, itf, pf, cf = _properties(ctx, mixed[0], nf)
+    sth, ith, ph, ch = _properties(ctx, mixed[1], nh)
+    assert c["pixels"] == nf + nh and c["trials"] == int(itf.sum()) + int(ith.sum())
+    assert c["passes"] == c["trials"] + nf + nh
+    _sample_checks("fine", foi, Wf, of_s, pf[sf], cf[sf], itf[sf], 1e-4, 1e-3, 0.1, 0.15)
+    _sample_checks("hmi (mixed launch)", hoi, Wh, oh_s, ph[sh], ch[sh], ith[sh],
+                   2e-5, 1e-3, 0.1, 0.12)
