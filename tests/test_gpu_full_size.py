@@ -52,7 +52,8 @@ def _properties(ctx, out, n, max_iter=50):
     iters = out["iters"].cpu().numpy()
     params = out["params"].cpu().numpy()
     chi2 = out["chi2"].cpu().numpy()
-    assert np.isin(st, (0, 1, 2)).all()
+    assert np.isin(st & 15, (0, 1, 2)).all()  # exit code; bit 4: fallback flag
+    assert ((st & ~15) & ~vf.FALLBACK_USED == 0).all()
     assert iters.min() >= 1 and iters.max() <= max_iter
     assert np.isfinite(params).all() and np.isfinite(chi2).all() and (chi2 >= 0).all()
     assert np.array_equal(vf.iter_histogram(ctx, out["iters"], max_iter + 1),
@@ -133,3 +134,52 @@ def test_fine_and_hmi_full_size_in_one_launch(ctx):
     _sample_checks("fine", foi, Wf, of_s, pf[sf], cf[sf], itf[sf], 1e-4, 1e-3, 0.1, 0.15)
     _sample_checks("hmi (mixed launch)", hoi, Wh, oh_s, ph[sh], ch[sh], ith[sh],
                    2e-5, 1e-3, 0.1, 0.12)
+
+
+def test_learned_path_full_size(ctx):
+    """The learned configuration at full size: a network trained by the
+    library on 10M synthetic pixels (control set 250k), then the learned path
+    on the 1M held-out pixels.  At any size: outputs finite and in the box,
+    the fallback flag on exactly the pixels the path refitted (at most 15
+    trials otherwise).  On a sample with oracle-made observations: the
+    oracle's chi^2 at the GPU's result, and the learned fits at least as
+    good as the oracle's own plain-LM fits of the same pixels."""
+    from paper_0901_2702_amd import learned
+    spec = wl.hmi_instrument()
+    inst = vf.Instrument.from_spec(ctx, spec)
+    oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
+    _say("training on 10M pixels")
+    S_tr, P_tr = learned.make_training_set(ctx, inst, wl.CONFIGS["learned_train"]["n"],
+                                           wl.CONFIGS["learned_train"]["seed"], wl.draw_params,
+                                           wl.draw_noise)
+    S_ct, P_ct = learned.make_training_set(ctx, inst, wl.CONFIGS["learned_control"]["n"],
+                                           wl.CONFIGS["learned_control"]["seed"],
+                                           wl.draw_params, wl.draw_noise)
+    net, info = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=20, batch=4096, lr=2e-3,
+                              log=lambda m: None)
+    del S_tr
+    torch.cuda.empty_cache()
+    cfg = wl.CONFIGS["learned_heldout"]
+    n = cfg["n"]
+    assert n == 1_000_000
+    P, smp, obs_s, obs = _set(ctx, spec, inst, oi, n, cfg["seed"], 256, 5153)
+    W = wl.weights(spec.n_obs)
+    _say("learned path on %d pixels" % n)
+    out = learned.invert_learned(ctx, inst, net, obs, torch.tensor(W, device=ctx.device))
+    st, iters, params, chi2 = _properties(ctx, out, n, max_iter=65)
+    fb = (st & vf.FALLBACK_USED) != 0
+    assert (iters[~fb] <= 15).all() and (iters[fb] > 0).all()
+    _say("fallback share %.4f, mean trials %.2f" % (fb.mean(), iters.mean()))
+    assert 0.0 < fb.mean() < 0.1
+    gp, gc = params[smp].astype(np.float64), chi2[smp]
+    ev = oracle.invert(oi, obs_s, W, init=gp, opts=oracle.Options(max_iter=0))
+    rel = np.abs(gc - ev["chi2"]) / ev["chi2"]
+    _say("learned: chi2 at the GPU result, oracle vs GPU: median %.2e max %.2e"
+         % (np.median(rel), rel.max()))
+    assert np.median(rel) < 2e-5 and rel.max() < 1e-3
+    ref = oracle.invert(oi, obs_s, W)
+    _say("learned median chi2 %.4f, share below 2 %.3f; oracle plain LM %.4f, %.3f"
+         % (np.median(gc), np.mean(gc < 2.0), np.median(ref["chi2"]),
+            np.mean(ref["chi2"] < 2.0)))
+    assert np.median(gc) <= 1.01 * np.median(ref["chi2"])
+    assert np.mean(gc < 2.0) >= np.mean(ref["chi2"] < 2.0)
