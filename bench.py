@@ -110,8 +110,9 @@ def main():
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the inversion is per-pixel independent and "
-              "this build runs on a single MI355X (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU only: pixels are inverted independently, so "
+              "several GPUs would each run this benchmark on their own share of the "
+              "pixels (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -55,7 +55,7 @@ extern "C" {
                                  /* non-finite or negative weight/filter   */
 #define VFISV_E_DEVICE (-2)      /* HIP error (message in last_error)       */
 #define VFISV_E_NOMEM (-3)       /* device or host allocation failed        */
-#define VFISV_E_UNSUPPORTED (-4) /* valid request this build cannot serve   */
+#define VFISV_E_UNSUPPORTED (-4) /* valid request the library cannot serve */
 
 /* Per-pixel status word: low 4 bits = exit code. */
 #define VFISV_CONVERGED 0  /* relative chi^2 decrease below rel_tol      */
@@ -78,7 +78,8 @@ typedef struct {
   double geff;                  /* effective Lande factor               */
   int n_fine;                   /* synthesis points, 1..4096            */
   const double *fine_offset_mA; /* host [n_fine], offsets from lambda0  */
-  int n_obs;                    /* observed samples; this build: 6      */
+  int n_obs;                    /* observed samples: 6, or 1..4096 with
+                                   a banded filter                      */
   const double *filter;         /* host [n_obs][n_fine], row-major      */
   double tap_threshold;         /* relative; 0 <= t < 1                 */
 } vfisv_instrument_desc;
