@@ -48,6 +48,7 @@ FLOP_SOLVE_FP64 = 1100       # equilibration, 10x10 Cholesky, substitutions, pro
 # copy of known size).  Reported only while the kernel sources hash to the
 # value recorded with the counters; otherwise the figure is stale and null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_plain_traffic.md")
+FINE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_fine_1M_traffic.md")
 KERNEL_SOURCES = ("paper_0901_2702_amd/csrc/kernels.hip", "paper_0901_2702_amd/csrc/kernels.h",
                   "paper_0901_2702_amd/csrc/me_device.h")
 
@@ -61,11 +62,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(n):
+def committed_traffic(n, profile=TRAFFIC_PROFILE):
     """HBM bytes per plain-LM launch over n pixels, or None when no counter
     run matches the current kernel sources and batch size."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(profile) as fh:
             kv = dict(line.strip("- `\n").split(": ", 1) for line in fh
                       if line.startswith("- `") and ": " in line)
         if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv["pixels"]) != n:
@@ -536,6 +537,7 @@ def fine_mixed(args, ctx, inst, spec, log):
     f_trial, f_jac, f_solve = work_model(fi["n_active_fine"], fi["n_taps"], fspec.n_obs)
     alg = c_f["trials"] * (f_trial + f_solve) + (c_f["pixels"] + c_f["accepts"]) * f_jac
     achieved = alg / (ev_f * 1e-3) / 1e12
+    tr_f = committed_traffic(n_f, FINE_TRAFFIC_PROFILE)
     n = n_f + n_h
     result = {
         "metric": "inverted pixels/s on 1 MI355X, fine-spectrum + HMI pixels in one launch, "
@@ -560,7 +562,11 @@ def fine_mixed(args, ctx, inst, spec, log):
         "hmi": {"mean_iters": float(it_h.mean())},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None, "kernel": "lm_kernel<0> (banded, fine pixels alone)",
+                     "traffic": None if tr_f is None else tr_f["fetch_bytes"] + tr_f["write_bytes"],
+                     "traffic_detail": None if tr_f is None else dict(
+                         tr_f, algorithmic_bytes=n_f * (4 * fspec.n_obs * 4 + 56),
+                         source=os.path.relpath(FINE_TRAFFIC_PROFILE, ROOT)),
+                     "kernel": "lm_kernel<0> (banded, fine pixels alone)",
                      "kernel_ms": round(ev_f, 3), "flop_per_trial": f_trial,
                      "flop_per_jacobian_pass": f_jac,
                      "work_fine": {k: c_f[k] for k in ("trials", "accepts", "passes", "pixels")},
