@@ -247,7 +247,10 @@ int vfisv_synthesize_voigt(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t
  *   status: dev [n] status word, or NULL.
  * Per-pixel numerical trouble never fails the call; it is reported in
  * status.  n == 0 enqueues nothing.  4*n_obs - (free parameters) must be
- * > 0. */
+ * > 0.  With a banded instrument the pass reads an interleaved copy of
+ * stokes (16 bytes per pixel and sample) that the call makes first, in a
+ * context buffer that grows when a larger batch comes (the growth
+ * allocates and waits for the device; calls after it allocate nothing). */
 int vfisv_invert(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                  const float *stokes, const float *W, int W_per_pixel,
                  const float *init, const vfisv_options *opt, float *params,

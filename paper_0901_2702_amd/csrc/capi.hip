@@ -99,6 +99,7 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.lpp_max = 1;
   a.lane_cap = 0;
   a.stokes = stokes;
+  a.stokes4 = nullptr;
   a.W = W;
   a.init = init;
   a.params = params;
@@ -132,6 +133,22 @@ static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, i
   return grid_for(n, cap);
 }
 
+// The context's buffer for interleaved observations, grown to at least
+// `bytes` (hipFree waits for the work that may still read the old one).
+static int grow_obs4(vfisv_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->obs4_bytes) return VFISV_OK;
+  if (ctx->d_obs4) hipFree(ctx->d_obs4);
+  ctx->d_obs4 = nullptr;
+  ctx->obs4_bytes = 0;
+  hipError_t e = hipMalloc(&ctx->d_obs4, bytes);
+  if (e != hipSuccess) {
+    ctx->d_obs4 = nullptr;
+    return hip_fail(ctx, e, "invert: interleaved observations");
+  }
+  ctx->obs4_bytes = bytes;
+  return VFISV_OK;
+}
+
 int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
                const float* W, int W_pp, const float* init, const vfisv_options& o,
@@ -149,6 +166,16 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n, bpc, o, inst->kind);
   const int64_t resident = (int64_t)ctx->num_cus * bpc;
   a.lane_cap = (long long)(grid < resident ? grid : resident) * 64;
+  if (inst->kind == KIND_BAND && !idx && !n_dev && n > 0) {
+    // a whole banded batch: the pass reads an interleaved copy
+    const int no = inst->C.n_obs;
+    const int rc = grow_obs4(ctx, sizeof(float4) * (size_t)n * (size_t)no);
+    if (rc) return rc;
+    float4* o4 = (float4*)ctx->d_obs4;
+    hipError_t e0 = launch_interleave(stokes, o4, n, no, s);
+    if (e0 != hipSuccess) return hip_fail(ctx, e0, "invert: interleave");
+    a.stokes4 = o4;
+  }
   hipError_t e = launch_reset(ctx->d_work, reset_all, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert: counter reset");
   e = launch_lm(a, inst->kind, o.voigt, grid, s);
@@ -288,6 +315,7 @@ int vfisv_destroy(vfisv_ctx* ctx) {
   hipDeviceSynchronize();
   hipFree(ctx->d_work);
   if (ctx->d_learn) hipFree(ctx->d_learn);
+  if (ctx->d_obs4) hipFree(ctx->d_obs4);
   if (ctx->d_vtab) hipFree(ctx->d_vtab);
   delete ctx;
   return VFISV_OK;
@@ -659,6 +687,23 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o, -1);
   hipStream_t s = (hipStream_t)stream;
+  // banded batches read interleaved copies, side by side in one buffer
+  size_t need = 0;
+  for (int i = 0; i < n_batches; ++i)
+    if (B.kind[i] == KIND_BAND) need += (size_t)batches[i].n * (size_t)batches[i].inst->C.n_obs;
+  if (need > 0) {
+    const int rc = grow_obs4(ctx, sizeof(float4) * need);
+    if (rc) return rc;
+    float4* o4 = (float4*)ctx->d_obs4;
+    for (int i = 0; i < n_batches; ++i) {
+      if (B.kind[i] != KIND_BAND || batches[i].n == 0) continue;
+      const int no = batches[i].inst->C.n_obs;
+      e = launch_interleave(batches[i].stokes, o4, batches[i].n, no, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches: interleave");
+      B.a[i].stokes4 = o4;
+      o4 += (size_t)batches[i].n * (size_t)no;
+    }
+  }
   e = launch_reset(ctx->d_work, true, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_batches: counter reset");
   e = launch_lm_batches(B, grid, s);

@@ -28,6 +28,9 @@ struct vfisv_ctx {
   // learned-start scratch (grown on demand)
   void* d_learn = nullptr;
   size_t learn_bytes = 0;
+  // interleaved observations of banded batches (grown on demand)
+  void* d_obs4 = nullptr;
+  size_t obs4_bytes = 0;
   std::string err;
 };
 

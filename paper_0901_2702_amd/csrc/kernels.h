@@ -52,6 +52,7 @@ struct LMArgs {
   unsigned long long seed;  // key of the restart perturbations
   double hess_reuse;        // keep J^T W J for steps from models below this chi^2
   long long lane_cap;       // lanes of the grid that are resident at once (lane-pair choice)
+  const float4* stokes4;    // KIND_BAND: [n][n_obs] interleaved copy of stokes, or NULL
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:
@@ -92,6 +93,8 @@ hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s);
 hipError_t launch_synth(const SynthArgs& a, int kind, int voigt, bool deriv, int grid,
                         hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
+// out[p][j] = (I, Q, U, V) of sample j of pixel p, from in = [n][4][n_obs]
+hipError_t launch_interleave(const float* in, float4* out, int64_t n, int n_obs, hipStream_t s);
 hipError_t lm_blocks_per_cu(int* out);
 hipError_t band_blocks_per_cu(int* out);
 

@@ -256,11 +256,18 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
         A.blocks, no, px, A.C,
         [&](int j) {
           rs = A.row_sums[j];
+          if (A.stokes4) {  // one 16-byte load; a line serves 8 consecutive rows
+            const float4 o4 = A.stokes4[pix * (int64_t)no + j];
+            ob[0] = o4.x;
+            ob[1] = o4.y;
+            ob[2] = o4.z;
+            ob[3] = o4.w;
+          } else {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            ob[s] = obs[s * no + j];
-            wb[s] = Wp[s * no + j];
+            for (int s = 0; s < 4; ++s) ob[s] = obs[s * no + j];
           }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) wb[s] = Wp[s * no + j];
         },
         [&](int, const float* a) {
           float S[4], J[4][NPAR], WJ[4][NPAR], R[4];
@@ -827,6 +834,32 @@ hipError_t launch_synth(const SynthArgs& a, int kind, int voigt, bool deriv, int
 
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s) {
   solve_kernel<<<grid, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// The banded pass reads a row's four Stokes values together; in the API
+// layout [n][4][n_obs] they lie in four cache lines that are each reused
+// over 32 rows, longer than an XCD's L2 keeps them with every lane of the
+// XCD streaming its own pixel, so the pass re-fetched them many times over.
+__global__ __launch_bounds__(256) void interleave_kernel(const float* __restrict__ in,
+                                                         float4* __restrict__ out, int64_t n,
+                                                         int n_obs) {
+  const int64_t total = n * (int64_t)n_obs;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t p = t / n_obs;
+    const int64_t j = t - p * n_obs;
+    const float* src = in + p * 4 * (int64_t)n_obs + j;
+    out[t] = make_float4(src[0], src[n_obs], src[2 * (int64_t)n_obs], src[3 * (int64_t)n_obs]);
+  }
+}
+
+hipError_t launch_interleave(const float* in, float4* out, int64_t n, int n_obs, hipStream_t s) {
+  const int64_t total = n * (int64_t)n_obs;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  const int grid = (int)(blocks < 65536 ? blocks : 65536);
+  interleave_kernel<<<grid, 256, 0, s>>>(in, out, n, n_obs);
   return hipGetLastError();
 }
 
