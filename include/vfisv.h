@@ -521,6 +521,29 @@ int vfisv_invert_learned(vfisv_ctx *ctx, const vfisv_instrument *inst, vfisv_mlp
                          float *params, double *chi2, int32_t *iters, int32_t *status,
                          void *stream);
 
+/* Allocation-free learned-start inversion, for callers that cannot allocate
+ * device memory: code under HIP graph capture, serving loops and harnesses
+ * that forbid hipMalloc.  Arguments, kernels and results are those of
+ * vfisv_invert_learned (the same bits), but the per-call scratch (about 100
+ * bytes per pixel) lies in a fixed device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, and the call makes
+ * no allocation of any kind.  The caller passes inputs and outputs as for
+ * vfisv_invert_learned.  Limits and differences:
+ *  - n <= VFISV_NOALLOC_MAX_PIXELS, else VFISV_E_INVALID (split the batch);
+ *  - banded instruments are read in the API layout (no interleaved copy);
+ *    the results are the same;
+ *  - options.voigt != 0 needs the Taylor table, which an earlier call that
+ *    may allocate builds (else VFISV_E_UNSUPPORTED).
+ * Every call on one GPU, from any context or stream, uses that GPU's single
+ * array, which keeps the last call's contents: calls that overlap in time on
+ * one GPU race and give wrong results; serialise them. */
+#define VFISV_NOALLOC_MAX_PIXELS 524288
+int vfisv_invert_learned_noalloc(vfisv_ctx *ctx, const vfisv_instrument *inst, vfisv_mlp *mlp,
+                                 int64_t n, const float *stokes, const float *W,
+                                 int W_per_pixel, const vfisv_options *opt,
+                                 int learned_max_iter, double chi2_accept, float *params,
+                                 double *chi2, int32_t *iters, int32_t *status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

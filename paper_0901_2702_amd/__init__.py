@@ -77,7 +77,8 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_solve", "vfisv_mlp_create", "vfisv_mlp_destroy", "vfisv_mlp_num_params", "vfisv_mlp_num_inputs", "vfisv_mlp_stats", "vfisv_mlp_train",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
-           "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_iter_histogram",
+           "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_invert_learned_noalloc",
+           "vfisv_iter_histogram",
            "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
            "vfisv_init_classical", "vfisv_init_combined", "vfisv_stokes_weights")
 

@@ -48,7 +48,7 @@ int grid_for(int64_t n, int64_t cap) {
 }
 
 int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_options* opt,
-                  vfisv_options* out, double* inv_dof) {
+                  vfisv_options* out, double* inv_dof, bool may_alloc) {
   vfisv_options o;
   vfisv_options_default(&o);
   if (opt) o = *opt;
@@ -69,6 +69,10 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   if (!(o.hess_reuse >= 0.0)) return fail(ctx, VFISV_E_INVALID, "options: hess_reuse must be >= 0");
   if (o.voigt != 0 && inst->kind != KIND_DENSE6)
     return fail(ctx, VFISV_E_UNSUPPORTED, "options: the Taylor table serves HMI-shaped instruments");
+  if (o.voigt != 0 && !may_alloc && !ctx->d_vtab)
+    return fail(ctx, VFISV_E_UNSUPPORTED,
+                "options: the Taylor table is built on first use, which allocates; build it "
+                "with an earlier call that may allocate");
   if (o.voigt != 0) {
     const int rc = ensure_vtab(ctx);
     if (rc) return rc;
@@ -153,7 +157,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
                const float* W, int W_pp, const float* init, const vfisv_options& o,
                double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
-               hipStream_t s, bool reset_all, int lpp_max) {
+               hipStream_t s, bool reset_all, int lpp_max, bool may_alloc) {
   LMArgs a;
   fill_lm_args(ctx, inst, n, n_dev, idx, stokes, W, W_pp, init, o, inv_dof, params, chi2, iters,
                status, a);
@@ -166,7 +170,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n, bpc, o, inst->kind);
   const int64_t resident = (int64_t)ctx->num_cus * bpc;
   a.lane_cap = (long long)(grid < resident ? grid : resident) * 64;
-  if (inst->kind == KIND_BAND && !idx && !n_dev && n > 0) {
+  if (inst->kind == KIND_BAND && !idx && !n_dev && n > 0 && may_alloc) {
     // a whole banded batch: the pass reads an interleaved copy
     const int no = inst->C.n_obs;
     const int rc = grow_obs4(ctx, sizeof(float4) * (size_t)n * (size_t)no);
@@ -299,6 +303,12 @@ int vfisv_create(vfisv_ctx** out, int device) {
     hipFree(c->d_work);
     delete c;
     return hip_fail(nullptr, e, "vfisv_create: counter reset");
+  }
+  if (noalloc_scratch_setup(c) != VFISV_OK) {
+    g_create_err = c->err;
+    hipFree(c->d_work);
+    delete c;
+    return VFISV_E_DEVICE;
   }
   double L, a[NW + 1];
   weideman_coefficients(NW, &L, a);

@@ -28,6 +28,9 @@ struct vfisv_ctx {
   // learned-start scratch (grown on demand)
   void* d_learn = nullptr;
   size_t learn_bytes = 0;
+  // device address of the fixed scratch array of the allocation-free
+  // learned path on this context's device (resolved at vfisv_create)
+  void* noalloc_scratch = nullptr;
   // interleaved observations of banded batches (grown on demand)
   void* d_obs4 = nullptr;
   size_t obs4_bytes = 0;
@@ -54,19 +57,26 @@ int check_inst(vfisv_ctx* ctx, const vfisv_instrument* inst, const char* fn);
 int grid_for(int64_t n, int64_t cap);
 // Build the Taylor table of H and F on the device (once per context).
 int ensure_vtab(vfisv_ctx* ctx);
+// may_alloc = false: refuse (VFISV_E_UNSUPPORTED) options that would make
+// the library allocate (the Taylor table before it exists).
 int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_options* opt,
-                  vfisv_options* out, double* inv_dof);
+                  vfisv_options* out, double* inv_dof, bool may_alloc = true);
+// Resolve the device address of the allocation-free path's scratch array on
+// ctx's device (current on the calling thread); once per device.
+int noalloc_scratch_setup(vfisv_ctx* ctx);
 
 // Enqueue the persistent LM kernel.  With idx != NULL the pixels are
 // idx[0 .. count), count read from n_dev on the device (n bounds the grid);
 // reset_all clears every work counter, otherwise only the queue heads.
 // lpp_max = 2 lets dense pixels use a pair of lanes each when the grid has
 // at least twice as many lanes as pixels (results then differ from the
-// one-lane path by float32 rounding of the synthesis sums).
+// one-lane path by float32 rounding of the synthesis sums).  may_alloc =
+// false: a whole banded batch is read in the API layout instead of through
+// the context's interleaved copy (same values, so the same results).
 int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                const unsigned long long* n_dev, const int32_t* idx, const float* stokes,
                const float* W, int W_pp, const float* init, const vfisv_options& o,
                double inv_dof, float* params, double* chi2, int32_t* iters, int32_t* status,
-               hipStream_t s, bool reset_all, int lpp_max = 1);
+               hipStream_t s, bool reset_all, int lpp_max = 1, bool may_alloc = true);
 
 }  // namespace vfisv_capi

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -603,11 +604,75 @@ int vfisv_mlp_load(vfisv_ctx* ctx, const char* path, vfisv_mlp** out) {
   return build(ctx, (int)n_in, im.data(), is.data(), om.data(), os.data(), params.data(), 0, out);
 }
 
-int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m, int64_t n,
-                         const float* stokes, const float* W, int W_per_pixel,
-                         const vfisv_options* opt, int learned_max_iter, double chi2_accept,
-                         float* params, double* chi2, int32_t* iters, int32_t* status,
-                         void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Scratch of one learned-path call over n pixels, carved from one buffer:
+// init [n][10] f32 | list [n] i32 | count u64 | p_fb [n][10] f32 |
+// c_fb [n] f64 | i_fb [n] i32 | s_fb [n] i32, each part 256-byte aligned.
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+struct LearnedScratch {
+  size_t o_init = 0, o_list = 0, o_cnt = 0, o_pfb = 0, o_cfb = 0, o_ifb = 0, o_sfb = 0, bytes = 0;
+  constexpr explicit LearnedScratch(int64_t n) {
+    auto al = align256;
+    o_init = 0;
+    o_list = o_init + al(sizeof(float) * NPAR * n);
+    o_cnt = o_list + al(sizeof(int32_t) * n);
+    o_pfb = o_cnt + 256;
+    o_cfb = o_pfb + al(sizeof(float) * NPAR * n);
+    o_ifb = o_cfb + al(sizeof(double) * n);
+    o_sfb = o_ifb + al(sizeof(int32_t) * n);
+    bytes = o_sfb + al(sizeof(int32_t) * n);
+  }
+};
+
+// The fixed scratch of vfisv_invert_learned_noalloc: one copy per GPU the
+// library runs on, held until the process ends.  Host code never uses this
+// name as an address (on the host it only stands for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device, in
+// noalloc_scratch_setup below.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static_assert(LearnedScratch(VFISV_NOALLOC_MAX_PIXELS).bytes <= NOALLOC_SCRATCH_BYTES,
+              "the fixed scratch serves the documented largest batch");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace vfisv_capi {
+
+int noalloc_scratch_setup(vfisv_ctx* ctx) {
+  static std::mutex mu;
+  static std::vector<void*> per_device;  // device address of scratch, by device
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)per_device.size() <= ctx->device) per_device.resize((size_t)ctx->device + 1, nullptr);
+  if (!per_device[(size_t)ctx->device]) {
+    void* p = nullptr;
+    // the caller has made ctx->device current
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "vfisv_create: address of the allocation-free scratch");
+    per_device[(size_t)ctx->device] = p;
+  }
+  ctx->noalloc_scratch = per_device[(size_t)ctx->device];
+  return VFISV_OK;
+}
+
+}  // namespace vfisv_capi
+
+
+namespace {
+
+// The learned-start inversion.  noalloc: the scratch is the fixed device
+// array (at most NOALLOC_SCRATCH_BYTES) and nothing is allocated; otherwise
+// the context's scratch, grown on demand.
+int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m, int64_t n,
+                        const float* stokes, const float* W, int W_per_pixel,
+                        const vfisv_options* opt, int learned_max_iter, double chi2_accept,
+                        float* params, double* chi2, int32_t* iters, int32_t* status,
+                        void* stream, bool noalloc) {
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert_learned: ctx is NULL");
   int rc = check_inst(ctx, inst, "invert_learned");
   if (rc) return rc;
@@ -617,7 +682,7 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
     return fail(ctx, VFISV_E_INVALID, "invert_learned: network inputs != 4 * n_obs");
   vfisv_options o;
   double inv_dof;
-  rc = check_options(ctx, inst, opt, &o, &inv_dof);
+  rc = check_options(ctx, inst, opt, &o, &inv_dof, !noalloc);
   if (rc) return rc;
   if (o.fixed_iters != 0)
     return fail(ctx, VFISV_E_UNSUPPORTED, "invert_learned: the fixed-iteration scheme is not served here");
@@ -625,40 +690,42 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: n < 0");
   if (n == 0) return VFISV_OK;
   if (n > INT32_MAX) return fail(ctx, VFISV_E_INVALID, "invert_learned: n must be < 2^31");
+  if (noalloc && n > VFISV_NOALLOC_MAX_PIXELS)
+    return fail(ctx, VFISV_E_INVALID,
+                "invert_learned_noalloc: n = " + std::to_string(n) + " exceeds the " +
+                    std::to_string(VFISV_NOALLOC_MAX_PIXELS) +
+                    " pixels its fixed scratch serves; split the batch");
   if (!stokes || !W || !params || !chi2 || !iters)
     return fail(ctx, VFISV_E_INVALID, "invert_learned: NULL buffer");
   const double tau = chi2_accept > 0.0 ? chi2_accept : chi2_red_q99((int)std::lround(1.0 / inv_dof));
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
 
-  // scratch: init [n][10] f32 | list [n] i32 | count u64 | p_fb [n][10] f32 |
-  //          c_fb [n] f64 | i_fb [n] i32 | s_fb [n] i32
-  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t o_init = 0;
-  const size_t o_list = o_init + al(sizeof(float) * NPAR * n);
-  const size_t o_cnt = o_list + al(sizeof(int32_t) * n);
-  const size_t o_pfb = o_cnt + 256;
-  const size_t o_cfb = o_pfb + al(sizeof(float) * NPAR * n);
-  const size_t o_ifb = o_cfb + al(sizeof(double) * n);
-  const size_t o_sfb = o_ifb + al(sizeof(int32_t) * n);
-  const size_t bytes = o_sfb + al(sizeof(int32_t) * n);
-  if (ctx->learn_bytes < bytes) {
-    e = hipDeviceSynchronize();
-    if (ctx->d_learn) hipFree(ctx->d_learn);
-    ctx->d_learn = nullptr;
-    ctx->learn_bytes = 0;
-    if (e == hipSuccess) e = hipMalloc(&ctx->d_learn, bytes);
-    if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "invert_learned: scratch allocation");
-    ctx->learn_bytes = bytes;
+  const LearnedScratch sl(n);
+  char* base = nullptr;
+  if (noalloc) {
+    if (!ctx->noalloc_scratch || sl.bytes > NOALLOC_SCRATCH_BYTES)
+      return fail(ctx, VFISV_E_INVALID, "invert_learned_noalloc: scratch unavailable");
+    base = (char*)ctx->noalloc_scratch;
+  } else {
+    if (ctx->learn_bytes < sl.bytes) {
+      e = hipDeviceSynchronize();
+      if (ctx->d_learn) hipFree(ctx->d_learn);
+      ctx->d_learn = nullptr;
+      ctx->learn_bytes = 0;
+      if (e == hipSuccess) e = hipMalloc(&ctx->d_learn, sl.bytes);
+      if (e != hipSuccess) return fail(ctx, VFISV_E_NOMEM, "invert_learned: scratch allocation");
+      ctx->learn_bytes = sl.bytes;
+    }
+    base = (char*)ctx->d_learn;
   }
-  char* base = (char*)ctx->d_learn;
-  float* init = (float*)(base + o_init);
-  int32_t* list = (int32_t*)(base + o_list);
-  unsigned long long* count = (unsigned long long*)(base + o_cnt);
-  float* p_fb = (float*)(base + o_pfb);
-  double* c_fb = (double*)(base + o_cfb);
-  int32_t* i_fb = (int32_t*)(base + o_ifb);
-  int32_t* s_fb = (int32_t*)(base + o_sfb);
+  float* init = (float*)(base + sl.o_init);
+  int32_t* list = (int32_t*)(base + sl.o_list);
+  unsigned long long* count = (unsigned long long*)(base + sl.o_cnt);
+  float* p_fb = (float*)(base + sl.o_pfb);
+  double* c_fb = (double*)(base + sl.o_cfb);
+  int32_t* i_fb = (int32_t*)(base + sl.o_ifb);
+  int32_t* s_fb = (int32_t*)(base + sl.o_sfb);
   hipStream_t s = (hipStream_t)stream;
 
   // 1. network proposal of the starting model
@@ -668,7 +735,7 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
   vfisv_options ol = o;
   ol.max_iter = learned_max_iter;
   rc = enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, ol, inv_dof,
-                  params, chi2, iters, status, s, true);
+                  params, chi2, iters, status, s, true, 1, !noalloc);
   if (rc) return rc;
   // 3. pixels whose fit is not acceptable go to plain LM from the combined
   // start of Sect. 5 (the proposal with the classical azimuth, and the
@@ -684,12 +751,35 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
     if (rc) return rc;
   }
   rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, combined ? init : nullptr, o,
-                  inv_dof, p_fb, c_fb, i_fb, s_fb, s, false, 2);
+                  inv_dof, p_fb, c_fb, i_fb, s_fb, s, false, 2, !noalloc);
   if (rc) return rc;
   // 4. keep the better of the two fits; flag the pixel
   e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, params, chi2, iters, status, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: merge");
   return VFISV_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m, int64_t n,
+                         const float* stokes, const float* W, int W_per_pixel,
+                         const vfisv_options* opt, int learned_max_iter, double chi2_accept,
+                         float* params, double* chi2, int32_t* iters, int32_t* status,
+                         void* stream) {
+  return invert_learned_impl(ctx, inst, m, n, stokes, W, W_per_pixel, opt, learned_max_iter,
+                             chi2_accept, params, chi2, iters, status, stream, false);
+}
+
+int vfisv_invert_learned_noalloc(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m,
+                                 int64_t n, const float* stokes, const float* W, int W_per_pixel,
+                                 const vfisv_options* opt, int learned_max_iter,
+                                 double chi2_accept, float* params, double* chi2, int32_t* iters,
+                                 int32_t* status, void* stream) {
+  return invert_learned_impl(ctx, inst, m, n, stokes, W, W_per_pixel, opt, learned_max_iter,
+                             chi2_accept, params, chi2, iters, status, stream, true);
 }
 
 }  // extern "C"

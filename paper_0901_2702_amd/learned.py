@@ -60,6 +60,7 @@ def _L():
         L.vfisv_invert_learned.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int,
                                            ctypes.POINTER(_Options), ctypes.c_int,
                                            ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+        L.vfisv_invert_learned_noalloc.argtypes = L.vfisv_invert_learned.argtypes
         L._mlp_sigs = True
     return L
 
@@ -176,21 +177,29 @@ class Mlp:
         return s.value
 
 
+# largest batch of vfisv_invert_learned_noalloc (its fixed scratch)
+NOALLOC_MAX_PIXELS = 524288
+
+
 def invert_learned(ctx, inst, mlp, stokes, W, opts=None, learned_max_iter=15, chi2_accept=0.0,
-                   out=None):
-    """Learned start + at most learned_max_iter LM trials, plain-LM fallback."""
+                   out=None, noalloc=False):
+    """Learned start + at most learned_max_iter LM trials, plain-LM fallback.
+    noalloc: through vfisv_invert_learned_noalloc (fixed library scratch, no
+    allocation; out must then be given by a caller that cannot allocate)."""
     dev = ctx.device
     opts = opts or Options()
     n = _rows(stokes)
     if out is None:
         out = _alloc_out(n, dev)
     o = opts.c()
-    ctx._check(_L().vfisv_invert_learned(
+    fn = _L().vfisv_invert_learned_noalloc if noalloc else _L().vfisv_invert_learned
+    ctx._check(fn(
         ctx._h, inst._h, mlp._h, n,
         _ptr(stokes, torch.float32, dev, n * 4 * inst.n_obs, name="stokes"),
         _ptr(W, torch.float32, dev, _w_numel(W, n, inst.n_obs), name="W"),
         1 if W.dim() == 3 else 0, ctypes.byref(o), int(learned_max_iter), float(chi2_accept),
-        *_out_ptrs(out, n, dev), _stream(dev)), "vfisv_invert_learned")
+        *_out_ptrs(out, n, dev), _stream(dev)),
+        "vfisv_invert_learned_noalloc" if noalloc else "vfisv_invert_learned")
     return out
 
 
