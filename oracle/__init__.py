@@ -111,6 +111,8 @@ class Instrument:
         self.filt = np.ascontiguousarray(filt, dtype=np.float64)
         assert self.filt.shape[1] == self.fine.shape[0]
         assert voigt in (0, 1, 2)
+        self.lambda0_A = float(lambda0_A)
+        self.geff = float(geff)
         self.n_fine = self.fine.shape[0]
         self.n_obs = self.filt.shape[0]
         self.voigt = voigt

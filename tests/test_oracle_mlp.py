@@ -82,3 +82,46 @@ def test_encode_decode_round_trip():
     dpsi = np.abs(Q[1:, 2] - P[1:, 2])
     assert np.all(np.minimum(dpsi, 180 - dpsi) < 1e-8)
     np.testing.assert_allclose(Q[:, 3:], P[:, 3:], rtol=1e-12, atol=1e-12)
+
+
+def _adam_run(g_seq, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    P = {"W": np.zeros(3)}
+    m = {"W": np.zeros(3)}
+    v = {"W": np.zeros(3)}
+    out = []
+    for t, g in enumerate(g_seq, start=1):
+        P = mlp.adam_step(P, {"W": g}, m, v, t, lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        out.append(P["W"].copy())
+    return np.array(out)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """A constant gradient g: the bias-corrected moments are g and g^2 at
+    every step, so each step moves by lr * g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 1e-3])
+    path = _adam_run([g] * 6)
+    step = 1e-3 * g / (np.abs(g) + 1e-8)
+    expect = -np.outer(np.arange(1, 7), step)
+    np.testing.assert_allclose(path, expect, rtol=1e-12, atol=0)
+
+
+def test_adam_alternating_gradient_follows_the_geometric_moment():
+    """g_t = (-1)^(t-1) g: v-hat stays g^2, while
+    m_t = (1 - b1) g (-1)^(t-1) (1 - (-b1)^t) / (1 + b1), corrected by
+    1 / (1 - b1^t).  Swapped betas or a wrong bias correction change every
+    step after the first."""
+    b1 = 0.9
+    g = np.array([0.5, -2.0, 3.0])
+    T = 7
+    path = _adam_run([g * (-1.0) ** t for t in range(T)])
+    expect = np.zeros((T, 3))
+    w = np.zeros(3)
+    for t in range(1, T + 1):
+        m = (1 - b1) * g * (-1.0) ** (t - 1) * (1 - (-b1) ** t) / (1 + b1)
+        mh = m / (1 - b1 ** t)
+        w = w - 1e-3 * mh / (np.abs(g) + 1e-8)
+        expect[t - 1] = w
+    np.testing.assert_allclose(path, expect, rtol=1e-10, atol=1e-18)
+    # the second step, written out: m-hat = -(0.01 / 0.19) g
+    np.testing.assert_allclose(path[1] - path[0], 1e-3 * (0.01 / 0.19) * g / (np.abs(g) + 1e-8),
+                               rtol=1e-10)
