@@ -12,9 +12,14 @@ Workload (the learned-initialiser configuration): HMI-shaped pixels (Fe I
 the synthetic priors, N(0, 1e-3) noise, W = 1e6.
 * training set: 10M pixels (seed 1003), control set 250k (seed 1103);
 * held-out set: 1M pixels (seed 2003) -- the timed batch.
-Learned path: network start, <= 15 LM trials, plain-LM fallback (<= 50 trials
-from the default model) for pixels with reduced chi^2 above the 0.99
-quantile.  Plain path: LM from the default model, <= 50 trials.
+Learned path: network start, <= 15 LM trials, then the pixels whose reduced
+chi^2 exceeds the 0.99 quantile of chi^2_dof / dof are fitted again by plain
+LM (<= 50 trials) from the combined start of Sect. 5 (network model, classical
+azimuth, weak-field B and inclination below 6% polarisation), keeping the
+better fit.  Plain path: LM from the default model, <= 50 trials.  The
+learned step is timed as a replay of its captured HIP graph.  A side leg runs
+the fallback as first stated (re-fit also the pixels that did not converge,
+from the default model, keeping the re-fit).
 Observations are synthesised on the device by the library's forward model
 from host-drawn (seeded numpy) parameters and noise; the network is trained
 before the timed region (its time is reported separately).
@@ -28,8 +33,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peak used for the roofline fraction.
+# Published MI355X peaks used for the roofline fractions (dense).
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+# Network inference per pixel: 2 (24*256 + 2*256*256 + 256*10) FLOP.
+MLP_FLOP_PER_PIXEL = 2 * (24 * 256 + 2 * 256 * 256 + 256 * 10)
 
 # Algorithmic float32 work per unit, counted from the formula sequence of the
 # synthesis: per synthesis point, per filter tap, per observed sample, plus
@@ -48,6 +56,7 @@ FLOP_SOLVE_FP64 = 1100       # equilibration, 10x10 Cholesky, substitutions, pro
 # copy of known size).  Reported only while the kernel sources hash to the
 # value recorded with the counters; otherwise the figure is stale and null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_plain_traffic.md")
+LEARNED_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_learned_short_traffic.md")
 FINE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_fine_1M_traffic.md")
 KERNEL_SOURCES = ("paper_0901_2702_amd/csrc/kernels.hip", "paper_0901_2702_amd/csrc/kernels.h",
                   "paper_0901_2702_amd/csrc/me_device.h")
@@ -95,7 +104,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
     ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity",
@@ -168,6 +177,7 @@ def main():
     log("training data %.1f s" % t_data)
     net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
                                batch=4096, lr=2e-3, log=log)
+    net_stats = tinfo["stats"]
     del S_tr
     torch.cuda.empty_cache()
 
@@ -187,23 +197,36 @@ def main():
                     iters=torch.empty(n, device=dev, dtype=torch.int32),
                     status=torch.empty(n, device=dev, dtype=torch.int32))
 
-    out_l, out_p = alloc(), alloc()
+    out_l, out_p, out_s = alloc(), alloc(), alloc()
     opts = vf.Options()
     # scheduling (persistent grid, pixel-queue block) chosen by the library's
     # autotuner on a sample of this batch; results do not depend on it
     tuning = vf.autotune(ctx, inst, obs, W, opts=opts, sample=131072)
     log("autotune: %s" % tuning)
 
-    def learned_step():
-        learned.invert_learned(ctx, inst, net, obs2, W, opts=opts,
-                               learned_max_iter=args.learned_max_iter, out=out_l)
+    def learned_step(rule=0, out=out_l):
+        learned.invert_learned(ctx, inst, net, obs2, W, opts=vf.Options(fallback_rule=rule),
+                               learned_max_iter=args.learned_max_iter, out=out)
 
     def plain_step():
         vf.invert(ctx, inst, obs, W, opts=opts, out=out_p)
 
-    def timed(fn, steps):
-        for _ in range(args.warmup):
+    def capture(fn):
+        """The step as a HIP graph (its library scratch grown by an eager call
+        first; the calls enqueue kernels only)."""
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
             fn()
+        torch.cuda.synchronize()
+        return g
+
+    def timed(run, steps, warm):
+        """warm untimed runs, then steps runs, each bracketed by HIP events on
+        the stream; returns (wall ms per step, event ms per run)."""
+        for _ in range(warm):
+            run()
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
@@ -211,18 +234,50 @@ def main():
         t = time.perf_counter()
         for a, b in ev:
             a.record(stream)
-            fn()
+            run()
             b.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        return wall * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        return wall * 1e3 / steps, [a.elapsed_time(b) for a, b in ev]
 
-    ms_l, ev_l = timed(learned_step, args.steps)
+    # ---- headline: the learned step, replayed as a captured graph ----------
+    for _ in range(args.warmup):
+        learned_step()
+    g_l = capture(learned_step)
+    ms_l, ev_l = timed(g_l.replay, args.steps, 2)
     c_l = ctx.counters()
-    ms_p, ev_p = timed(plain_step, max(3, args.steps // 2))
+    lc = out_l["chi2"].cpu().numpy()
+    # the replays give the eager call's results
+    learned_step(out=out_s)
+    torch.cuda.synchronize()
+    graph_equals_eager = bool(np.array_equal(lc, out_s["chi2"].cpu().numpy()) and torch.equal(
+        out_l["params"], out_s["params"]))
+    g_p = capture(plain_step)
+    ms_p, ev_p = timed(g_p.replay, max(3, args.steps // 2), 2)
     c_p = ctx.counters()
+    del g_l, g_p
 
-    lc, pc = out_l["chi2"].cpu().numpy(), out_p["chi2"].cpu().numpy()
+    # ---- per-launch times of the learned step (eager, HIP events between
+    # the library's phases on the stream) for the rooflines -------------------
+    learned.phase_timing(ctx, True)
+    ph_runs = []
+    for _ in range(max(3, args.steps // 2)):
+        learned_step(out=out_s)
+        ph_runs.append(learned.learned_phases(ctx))
+    learned.phase_timing(ctx, False)
+    ph_ms = {k: float(np.mean([r["ms"][k] for r in ph_runs])) for k in learned.PHASES}
+    ph = ph_runs[-1]
+
+    # ---- side leg: the fallback as first stated (re-fit every pixel that did
+    # not converge within the short fit or ends above tau, from the default
+    # model, keeping the re-fit) ------------------------------------------------
+    as_stated = vf.REFIT_UNCONVERGED | vf.REFIT_FROM_DEFAULT | vf.REFIT_KEEP_REFIT
+    out_a = alloc()
+    ms_a, _ = timed(lambda: learned_step(rule=as_stated, out=out_a), 3, 1)
+    ac = out_a["chi2"].cpu().numpy()
+    fb_a = (out_a["status"].cpu().numpy() & vf.FALLBACK_USED) != 0
+
+    pc = out_p["chi2"].cpu().numpy()
     li, pi = out_l["iters"].cpu().numpy(), out_p["iters"].cpu().numpy()
     ls, ps = out_l["status"].cpu().numpy(), out_p["status"].cpu().numpy()
     fb = (ls & vf.FALLBACK_USED) != 0
@@ -232,13 +287,57 @@ def main():
     def alg(c):
         return c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
 
-    achieved = alg(c_p) / (ev_p * 1e-3) / 1e12
-    executed = (c_p["passes"] * f_jac + c_p["trials"] * f_solve) / (ev_p * 1e-3) / 1e12
+    def executed(c):
+        return c["passes"] * f_jac + c["trials"] * f_solve
 
     def q(a, p):
         return float(np.quantile(a, p))
 
-    tr = committed_traffic(n)
+    def matched(a, b):
+        """The learned fits' chi^2 (a) against plain LM's (b) on the same
+        pixels, under the two readings of "matched chi^2"."""
+        med_a, med_b, p99_a, p99_b = q(a, 0.5), q(b, 0.5), q(a, 0.99), q(b, 0.99)
+        return {
+            "median_learned": med_a, "median_plain": med_b,
+            "p90_learned": q(a, 0.9), "p90_plain": q(b, 0.9),
+            "p99_learned": p99_a, "p99_plain": p99_b,
+            "frac_learned_worse_1pct": float(np.mean(a > 1.01 * b)),
+            "frac_learned_better_1pct": float(np.mean(a < 0.99 * b)),
+            "frac_chi2_below_2": [float(np.mean(a < 2.0)), float(np.mean(b < 2.0))],
+            # equal medians and 99th percentiles within 1e-3 relative
+            "equal_within_1e-3": bool(abs(med_a - med_b) <= 1e-3 * med_b
+                                      and abs(p99_a - p99_b) <= 1e-3 * p99_b),
+            # the learned fits at least as good at the median and the 99th
+            # percentile (the claim this line makes)
+            "learned_not_worse": bool(med_a <= med_b and p99_a <= p99_b),
+        }
+
+    # rooflines of the learned step's launches: the short fit (the dominant
+    # kernel), the re-fit, and the network (bf16 matrix cores)
+    sf, rf = ph["short_fit"], ph["refit"]
+    mlp_flop = n * MLP_FLOP_PER_PIXEL
+    launches = {
+        "short_fit": {"kernel": "lm_kernel<6> (learned start, <= %d trials)" % args.learned_max_iter,
+                      "ms": round(ph_ms["short_fit"], 4), "bound": "alu", "unit": "TFLOP/s",
+                      "peak": PEAK_FP32_TFLOPS,
+                      "achieved": round(alg(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
+                      "executed": round(executed(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
+                      "work": {k: sf[k] for k in ("pixels", "trials", "accepts", "passes")}},
+        "refit": {"kernel": "lm_kernel<6> (re-fit of the pixels above tau, <= 50 trials)",
+                  "ms": round(ph_ms["refit"], 4), "bound": "alu", "unit": "TFLOP/s",
+                  "peak": PEAK_FP32_TFLOPS,
+                  "achieved": round(alg(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
+                  "executed": round(executed(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
+                  "work": {k: rf[k] for k in ("pixels", "trials", "accepts", "passes")}},
+        "network": {"kernel": "mlp_infer_kernel (fused 4-layer inference + decode)",
+                    "ms": round(ph_ms["network"], 4), "bound": "mfma", "unit": "TFLOP/s",
+                    "peak": PEAK_BF16_TFLOPS,
+                    "achieved": round(mlp_flop / (ph_ms["network"] * 1e-3) / 1e12, 3)},
+    }
+    for v in launches.values():
+        v["frac"] = round(v["achieved"] / v["peak"], 4)
+    dom = launches["short_fit"]
+    tr = committed_traffic(n, LEARNED_TRAFFIC_PROFILE)
 
     result = {
         "metric": "inverted pixels/s on 1 MI355X, learned-init LM vs plain LM at matched chi^2",
@@ -255,7 +354,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "1M held-out HMI-shaped pixels (synthetic priors, seed 2003, noise 1e-3); "
-                        "learned start + <= %d LM trials + plain-LM fallback"
+                        "learned start + <= %d LM trials + re-fit above the chi^2 0.99 quantile"
                         % args.learned_max_iter,
             "pixels": n,
             "n_obs": n_obs,
@@ -263,22 +362,32 @@ def main():
             "train_pixels": args.train_samples,
             "control_pixels": args.control_samples,
         },
+        "timing": {"method": "HIP-graph replay of the whole learned step (network, short fit, "
+                             "selection, combined start, re-fit, merge); %d eager warm-ups, 2 "
+                             "untimed replays, %d timed replays" % (args.warmup, args.steps),
+                   "event_ms_median": round(float(np.median(ev_l)), 4),
+                   "event_ms": [round(x, 4) for x in ev_l],
+                   "graph_equals_eager": graph_equals_eager,
+                   "phases_ms": {k: round(v, 4) for k, v in ph_ms.items()}},
         "plain_lm": {
             "value": round(n / (ms_p * 1e-3), 1), "unit": "pixels/s", "ms_per_step": round(ms_p, 4),
+            "event_ms_median": round(float(np.median(ev_p)), 4),
             "mean_iters": float(pi.mean()), "status_counts": np.bincount(ps, minlength=4).tolist(),
         },
         "speedup_vs_plain": round(ms_p / ms_l, 3),
         "autotune": tuning,
-        "matched_chi2": {
-            "median_learned": q(lc, 0.5), "median_plain": q(pc, 0.5),
-            "p90_learned": q(lc, 0.9), "p90_plain": q(pc, 0.9),
-            "p99_learned": q(lc, 0.99), "p99_plain": q(pc, 0.99),
-            "frac_learned_worse_1pct": float(np.mean(lc > 1.01 * pc)),
-            "frac_learned_better_1pct": float(np.mean(lc < 0.99 * pc)),
-            "frac_chi2_below_2": [float(np.mean(lc < 2.0)), float(np.mean(pc < 2.0))],
-            "fallback_rate": float(fb.mean()),
-            "mean_iters_learned": float(li.mean()),
-        },
+        "matched_chi2": dict(matched(lc, pc), fallback_rate=float(fb.mean()),
+                             mean_iters_learned=float(li.mean()),
+                             claim="learned_not_worse: median and 99th percentile of the learned "
+                                   "fits' chi^2 at or below plain LM's on the same pixels; the "
+                                   "stricter reading (both within 1e-3) is reported as "
+                                   "equal_within_1e-3"),
+        "fallback_as_stated": dict(matched(ac, pc), ms_per_step=round(ms_a, 4),
+                                   value=round(n / (ms_a * 1e-3), 1),
+                                   fallback_rate=float(fb_a.mean()),
+                                   rule="re-fit pixels not converged within the short fit or "
+                                        "above tau, from the default model, keeping the "
+                                        "re-fit"),
         "training": {
             "seconds": round(tinfo["seconds"], 2), "data_seconds": round(t_data, 2),
             "epochs_run": len(tinfo["history"]), "best_epoch": tinfo["best_epoch"],
@@ -286,39 +395,54 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "achieved": round(achieved, 3),
+            "achieved": dom["achieved"],
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "frac": dom["frac"],
             "traffic": None if tr is None else tr["fetch_bytes"] + tr["write_bytes"],
             "traffic_detail": None if tr is None else dict(
-                tr, algorithmic_bytes=n * (4 * n_obs * 4 + 56), source=os.path.relpath(
-                    TRAFFIC_PROFILE, ROOT)),
-            "kernel": "lm_kernel (plain-LM leg: one launch per step)",
-            "kernel_ms": round(ev_p, 4),
-            "executed_tflops": round(executed, 3),
+                tr, algorithmic_bytes=n * (4 * n_obs * 4 + 40 + 56), source=os.path.relpath(
+                    LEARNED_TRAFFIC_PROFILE, ROOT)),
+            "kernel": dom["kernel"] + ", the dominant launch of the learned step",
+            "kernel_ms": dom["ms"],
+            "executed_tflops": dom["executed"],
             "flop_per_trial": f_trial, "flop_per_jacobian_pass": f_jac,
             "flop64_per_solve": f_solve,
-            "work_plain": {k: c_p[k] for k in ("trials", "accepts", "passes", "pixels")},
-            "work_learned": {k: c_l[k] for k in ("trials", "accepts", "passes", "pixels")},
+            "launches": launches,
+            "plain_lm_launch": {
+                "ms": round(float(np.median(ev_p)), 4),
+                "achieved": round(alg(c_p) / (np.median(ev_p) * 1e-3) / 1e12, 3),
+                "work": {k: c_p[k] for k in ("trials", "accepts", "passes", "pixels")}},
         },
     }
 
     if not args.no_cpu_baseline:
         import oracle
+        from oracle import learned as olearned
         m = min(args.cpu_sample, n)
         oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
         obs_cpu = (oracle.forward_batch(oi, P[:m]) + noise[:m]).astype(np.float32)
-        t1 = time.perf_counter()
-        ref = oracle.invert(oi, obs_cpu, wl.weights(n_obs))
-        dt = time.perf_counter() - t1
+        stats = [net_stats[k] for k in range(4)]
+        flat = net.get_params()
+        runs = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            starts, _ = olearned.network_starts(flat, 4 * n_obs, *stats,
+                                                obs_cpu.reshape(m, 4 * n_obs))
+            ref = olearned.learned_invert(oi, obs_cpu, wl.weights(n_obs), starts,
+                                          short_max_iter=args.learned_max_iter)
+            runs.append(time.perf_counter() - t1)
+        dt = float(np.median(runs))
         result["cpu_baseline"] = {
-            "value": round(m / dt, 2), "unit": "pixels/s", "cores": ref["threads"],
+            "value": round(m / dt, 2), "unit": "pixels/s", "cores": ref["short"]["threads"],
             "kind": "oracle",
             "sample": "first %d of the %d held-out pixels (same parameters and noise, "
-                      "observations synthesised by the FP64 oracle), plain LM from the default "
-                      "model, max 50 iterations" % (m, n),
-            "seconds": round(dt, 3),
+                      "observations synthesised by the FP64 oracle); the oracle's learned path "
+                      "(network start in float64 from the library's trained weights, <= %d LM "
+                      "trials, re-fit above tau from the combined start); median of 3 runs; "
+                      "cores = host threads used" % (m, n, args.learned_max_iter),
+            "seconds": round(dt, 3), "runs_s": [round(x, 3) for x in runs],
+            "refit_rate": float(ref["refit"].mean()),
         }
     print(json.dumps(result), flush=True)
 

@@ -150,7 +150,24 @@ typedef struct {
                        /* gives no threshold).  0 (default): always rebuilt.*/
                        /* Changes the results (slower convergence where the */
                        /* curvature still changes); >= 0.                   */
+  uint32_t fallback_rule; /* learned path only (vfisv_invert_learned): which  */
+                       /* pixels are re-fitted after the short fit, from    */
+                       /* where, and which fit is kept.  0 (default): pixels */
+                       /* with reduced chi^2 above the threshold, from the  */
+                       /* combined start, keeping the lower chi^2.  Bits:   */
+                       /* VFISV_REFIT_UNCONVERGED, VFISV_REFIT_FROM_DEFAULT, */
+                       /* VFISV_REFIT_KEEP_REFIT (all three: the rule as    */
+                       /* stated for the learned initialiser's fallback).    */
 } vfisv_options;
+
+/* vfisv_options.fallback_rule bits (Sect. 5 leaves the fallback open). */
+#define VFISV_REFIT_UNCONVERGED 1  /* also re-fit pixels whose short fit did
+                                      not end CONVERGED (non-finite input
+                                      excepted)                             */
+#define VFISV_REFIT_FROM_DEFAULT 2 /* re-fit from the default model, not the
+                                      combined start                        */
+#define VFISV_REFIT_KEEP_REFIT 4   /* keep the re-fit's result even where its
+                                      chi^2 is higher than the short fit's  */
 
 /* Result of vfisv_autotune. */
 typedef struct {
@@ -505,13 +522,15 @@ int vfisv_mlp_load(vfisv_ctx *ctx, const char *path, vfisv_mlp **out);
 /* Learned-start inversion: the network proposes each pixel's starting
  * model, LM runs at most learned_max_iter trials from it, and every pixel
  * whose reduced chi^2 then exceeds chi2_accept (<= 0: the 0.99 quantile of
- * chi^2_dof / dof) is re-fitted by plain LM with opt->max_iter trials from
- * the paper's combined start (Sect. 5: the network's model with the
- * classical azimuth, and the weak-field B and gamma below 6 % polarisation,
- * as vfisv_init_combined; the default model when n_obs < 3); the better
- * fit is kept, iters counts the trials of both runs and status gets bit 16
- * (VFISV_FALLBACK_USED).  Buffers as in
- * vfisv_invert (W shared or per pixel); the network must take 4*n_obs
+ * chi^2_dof / dof, vfisv_chi2_quantile) is re-fitted by plain LM with
+ * opt->max_iter trials from the paper's combined start (Sect. 5: the
+ * network's model with the classical azimuth, and the weak-field B and gamma
+ * below 6 % polarisation, as vfisv_init_combined; the default model when
+ * n_obs < 3); the better fit is kept, iters counts the trials of both runs
+ * and status gets bit 16 (VFISV_FALLBACK_USED).  opt->fallback_rule changes
+ * the refit set, start and choice (VFISV_REFIT_* bits).  Pixels with
+ * non-finite input (status VFISV_NONFINITE) are never re-fitted.  Buffers as
+ * in vfisv_invert (W shared or per pixel); the network must take 4*n_obs
  * inputs.  Library scratch (about 100 bytes per pixel) grows on first use
  * (a synchronising allocation). */
 #define VFISV_FALLBACK_USED 16
@@ -520,6 +539,32 @@ int vfisv_invert_learned(vfisv_ctx *ctx, const vfisv_instrument *inst, vfisv_mlp
                          const vfisv_options *opt, int learned_max_iter, double chi2_accept,
                          float *params, double *chi2, int32_t *iters, int32_t *status,
                          void *stream);
+
+/* The learned path's default acceptance threshold: the q-quantile of a
+ * chi-square variable with dof degrees of freedom divided by dof (the
+ * reduced chi^2 of Eq. 1 that a pixel fitted to noise of the stated sigma
+ * stays below with probability q).  Host computation (regularised
+ * incomplete gamma function, bisection to 1e-13 relative); no device work.
+ * Errors: VFISV_E_INVALID for dof < 1 or dof > 1e6, q outside (0, 1), out
+ * NULL. */
+int vfisv_chi2_quantile(int dof, double q, double *out);
+
+/* Per-phase timing of vfisv_invert_learned (measurement aid).  With on != 0,
+ * later calls that are not being captured into a graph record HIP events on
+ * their stream between the phases (network inference, short fit, selection
+ * and combined start, re-fit, merge) and keep the work counters of the
+ * short-fit launch apart from those of the re-fit launch.  Enabling creates
+ * the events and a 256-byte device buffer (allocates and synchronises);
+ * on == 0 releases them.  vfisv_learned_phases_get synchronises with the
+ * most recent timed call and reports it (VFISV_E_INVALID if none). */
+typedef struct {
+  double ms[5];              /* network, short fit, selection + combined
+                                start, re-fit, merge (HIP event times)   */
+  vfisv_counters short_fit;  /* work of the short-fit launch             */
+  vfisv_counters refit;      /* work of the re-fit launch                */
+} vfisv_learned_phases;
+int vfisv_learned_phase_timing(vfisv_ctx *ctx, int on);
+int vfisv_learned_phases_get(vfisv_ctx *ctx, vfisv_learned_phases *out);
 
 /* Allocation-free learned-start inversion, for callers that cannot allocate
  * device memory: code under HIP graph capture, serving loops and harnesses

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libvfisv.so")
 NPAR = 10
 CONVERGED, MAX_ITER, STALLED, NONFINITE = 0, 1, 2, 3
 FALLBACK_USED = 16
+# Options.fallback_rule bits (learned path)
+REFIT_UNCONVERGED, REFIT_FROM_DEFAULT, REFIT_KEEP_REFIT = 1, 2, 4
 PARAM_NAMES = ("B", "gamma", "psi", "v_los", "doppler_width", "damping", "eta0", "S0", "S1",
                "alpha")
 
@@ -46,7 +48,7 @@ class _Options(ctypes.Structure):
                 ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int),
                 ("voigt", ctypes.c_int), ("fixed_iters", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("restart_seed", ctypes.c_uint64),
-                ("hess_reuse", ctypes.c_double)]
+                ("hess_reuse", ctypes.c_double), ("fallback_rule", ctypes.c_uint32)]
 
 
 class _Batch(ctypes.Structure):
@@ -78,6 +80,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_invert_learned_noalloc",
+           "vfisv_chi2_quantile", "vfisv_learned_phase_timing", "vfisv_learned_phases_get",
            "vfisv_iter_histogram",
            "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
            "vfisv_init_classical", "vfisv_init_combined", "vfisv_stokes_weights")
@@ -255,11 +258,13 @@ class Options:
     restarts: int = 0
     restart_seed: int = 0
     hess_reuse: float = 0.0
+    fallback_rule: int = 0
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
                         self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt,
-                        self.fixed_iters, self.restarts, self.restart_seed, self.hess_reuse)
+                        self.fixed_iters, self.restarts, self.restart_seed, self.hess_reuse,
+                        self.fallback_rule)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):

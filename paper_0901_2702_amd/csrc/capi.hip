@@ -67,6 +67,8 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   if (o.restarts < 0 || o.restarts > 4095)
     return fail(ctx, VFISV_E_INVALID, "options: restarts outside 0..4095");
   if (!(o.hess_reuse >= 0.0)) return fail(ctx, VFISV_E_INVALID, "options: hess_reuse must be >= 0");
+  if (o.fallback_rule & ~7u)
+    return fail(ctx, VFISV_E_INVALID, "options: fallback_rule takes the VFISV_REFIT_* bits only");
   if (o.voigt != 0 && inst->kind != KIND_DENSE6)
     return fail(ctx, VFISV_E_UNSUPPORTED, "options: the Taylor table serves HMI-shaped instruments");
   if (o.voigt != 0 && !may_alloc && !ctx->d_vtab)
@@ -327,6 +329,7 @@ int vfisv_destroy(vfisv_ctx* ctx) {
   if (ctx->d_learn) hipFree(ctx->d_learn);
   if (ctx->d_obs4) hipFree(ctx->d_obs4);
   if (ctx->d_vtab) hipFree(ctx->d_vtab);
+  vfisv_learned_phase_timing(ctx, 0);
   delete ctx;
   return VFISV_OK;
 }
@@ -346,6 +349,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->restarts = 0;
   o->restart_seed = 0;
   o->hess_reuse = 0.0;
+  o->fallback_rule = 0u;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,

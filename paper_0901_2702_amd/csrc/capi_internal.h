@@ -31,6 +31,13 @@ struct vfisv_ctx {
   // device address of the fixed scratch array of the allocation-free
   // learned path on this context's device (resolved at vfisv_create)
   void* noalloc_scratch = nullptr;
+  // per-phase timing of the learned path (vfisv_learned_phase_timing):
+  // events between its phases and the work counters after the short fit
+  // ([0, 8)) and after the re-fit ([8, 16))
+  bool phase_on = false;
+  bool phase_valid = false;
+  hipEvent_t phase_ev[6] = {};
+  unsigned long long* d_phase_snap = nullptr;
   // interleaved observations of banded batches (grown on demand)
   void* d_obs4 = nullptr;
   size_t obs4_bytes = 0;

@@ -90,6 +90,8 @@ hipError_t mlp_adam(const MlpDev& net, const MlpWork& w, float lr, float beta1, 
                     float eps, int step, hipStream_t s);
 hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t s);
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t s);
+// dst[0, n) = src[0, n) by a kernel (capturable, unlike a memcpy node).
+hipError_t copy_u64(unsigned long long* dst, const unsigned long long* src, int n, hipStream_t s);
 
 // Training-set preparation and the control-set error (the training loop of
 // vfisv_mlp_train).  col_moments adds, for columns col0 .. col0 + ncols - 1
@@ -105,12 +107,16 @@ hipError_t encode_targets(const float* P, int64_t n, const float* out_mean, cons
 // out[0] += sum over count values of (A - B)^2, in float64.
 hipError_t sq_diff_sum(const float* A, const float* B, int64_t count, double* out, hipStream_t s);
 
-// Learned-start helpers for the inversion.
-hipError_t fallback_select(const double* chi2, int64_t n, double tau, int32_t* list,
-                           unsigned long long* count, hipStream_t s);
+// Learned-start helpers for the inversion.  Selection: pixels with finite
+// chi^2 above tau, and with `unconverged` also those whose status (low 4
+// bits) is neither CONVERGED nor NONFINITE.  Merge: the re-fit replaces the
+// short fit where its chi^2 is lower, or always with keep_refit.
+hipError_t fallback_select(const double* chi2, const int32_t* status, int64_t n, double tau,
+                           bool unconverged, int32_t* list, unsigned long long* count,
+                           hipStream_t s);
 hipError_t fallback_merge(const int32_t* list, const unsigned long long* count, int64_t n,
                           const float* p_fb, const double* c_fb, const int32_t* i_fb,
-                          const int32_t* s_fb, float* params, double* chi2, int32_t* iters,
-                          int32_t* status, hipStream_t s);
+                          const int32_t* s_fb, bool keep_refit, float* params, double* chi2,
+                          int32_t* iters, int32_t* status, hipStream_t s);
 
 }  // namespace vfisv

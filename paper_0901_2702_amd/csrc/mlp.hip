@@ -470,8 +470,9 @@ hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* c
 // serialise in L2).
 constexpr int SELECT_PER_THREAD = 16;
 __global__ __launch_bounds__(256) void fallback_select_kernel(const double* __restrict__ chi2,
+                                                              const int32_t* __restrict__ status,
                                                               int64_t n, double tau,
-                                                              int32_t* list,
+                                                              int unconverged, int32_t* list,
                                                               unsigned long long* count) {
   __shared__ unsigned int scan[256];
   __shared__ unsigned long long base;
@@ -483,7 +484,12 @@ __global__ __launch_bounds__(256) void fallback_select_kernel(const double* __re
     const int64_t i = start + (int64_t)k * 256 + t;
     if (i < n) {
       const double v = chi2[i];
-      if (!(v <= tau) && !isnan(v)) {  // not acceptable (non-finite input stays as is)
+      bool sel = !(v <= tau) && !isnan(v);  // not acceptable (non-finite input stays as is)
+      if (unconverged && !isnan(v)) {
+        const int code = status[i] & 15;
+        sel = sel || (code != 0 && code != 3);
+      }
+      if (sel) {
         mask |= 1u << k;
         ++c;
       }
@@ -511,12 +517,13 @@ __global__ void fallback_merge_kernel(const int32_t* __restrict__ list,
                                       const float* __restrict__ p_fb,
                                       const double* __restrict__ c_fb,
                                       const int32_t* __restrict__ i_fb,
-                                      const int32_t* __restrict__ s_fb, float* params,
-                                      double* chi2, int32_t* iters, int32_t* status) {
+                                      const int32_t* __restrict__ s_fb, int keep_refit,
+                                      float* params, double* chi2, int32_t* iters,
+                                      int32_t* status) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((unsigned long long)t >= *count) return;
   const int64_t i = list[t];
-  const bool better = c_fb[i] < chi2[i];
+  const bool better = keep_refit || c_fb[i] < chi2[i];
   if (better) {
 #pragma unroll
     for (int q = 0; q < NPAR; ++q) params[i * NPAR + q] = p_fb[i * NPAR + q];
@@ -556,6 +563,16 @@ hipError_t mlp_decode(const MlpDev& net, const float* Y4, int64_t M, float* code
                       hipStream_t s) {
   decode_kernel<<<blocks_for(M, 256), 256, 0, s>>>(Y4, M, net.out_mean, net.out_std, codes,
                                                    params);
+  return hipGetLastError();
+}
+
+__global__ void copy_u64_kernel(unsigned long long* dst, const unsigned long long* src, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t copy_u64(unsigned long long* dst, const unsigned long long* src, int n, hipStream_t s) {
+  copy_u64_kernel<<<1, 64, 0, s>>>(dst, src, n);
   return hipGetLastError();
 }
 
@@ -754,19 +771,21 @@ hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t fallback_select(const double* chi2, int64_t n, double tau, int32_t* list,
-                           unsigned long long* count, hipStream_t s) {
-  fallback_select_kernel<<<blocks_for(n, 256 * SELECT_PER_THREAD), 256, 0, s>>>(chi2, n, tau,
-                                                                               list, count);
+hipError_t fallback_select(const double* chi2, const int32_t* status, int64_t n, double tau,
+                           bool unconverged, int32_t* list, unsigned long long* count,
+                           hipStream_t s) {
+  if (unconverged && !status) return hipErrorInvalidValue;
+  fallback_select_kernel<<<blocks_for(n, 256 * SELECT_PER_THREAD), 256, 0, s>>>(
+      chi2, status, n, tau, unconverged ? 1 : 0, list, count);
   return hipGetLastError();
 }
 
 hipError_t fallback_merge(const int32_t* list, const unsigned long long* count, int64_t n,
                           const float* p_fb, const double* c_fb, const int32_t* i_fb,
-                          const int32_t* s_fb, float* params, double* chi2, int32_t* iters,
-                          int32_t* status, hipStream_t s) {
-  fallback_merge_kernel<<<blocks_for(n, 256), 256, 0, s>>>(list, count, p_fb, c_fb, i_fb, s_fb,
-                                                           params, chi2, iters, status);
+                          const int32_t* s_fb, bool keep_refit, float* params, double* chi2,
+                          int32_t* iters, int32_t* status, hipStream_t s) {
+  fallback_merge_kernel<<<blocks_for(n, 256), 256, 0, s>>>(
+      list, count, p_fb, c_fb, i_fb, s_fb, keep_refit ? 1 : 0, params, chi2, iters, status);
   return hipGetLastError();
 }
 

@@ -203,11 +203,52 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
   return h;
 }
 
-// 0.99 quantile of chi^2_k / k by the Wilson-Hilferty cube approximation.
-double chi2_red_q99(int k) {
-  const double z = 2.3263478740408408, a = 2.0 / (9.0 * k);
-  const double c = 1.0 - a + z * std::sqrt(a);
-  return c * c * c;
+// Regularised lower incomplete gamma function P(a, x): its power series
+// (Abramowitz & Stegun 6.5.29) below x = a + 1, above it 1 - Q(a, x) with Q
+// from Legendre's continued fraction (A&S 6.5.31), evaluated by the modified
+// Lentz method.
+double gamma_p(double a, double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double pre = std::exp(-x + a * std::log(x) - std::lgamma(a));
+  if (x < a + 1.0) {
+    double ap = a, term = 1.0 / a, sum = term;
+    for (int k = 0; k < 1000000; ++k) {
+      ap += 1.0;
+      term *= x / ap;
+      sum += term;
+      if (std::fabs(term) < std::fabs(sum) * 1e-17) break;
+    }
+    return sum * pre;
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 1000000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-16) break;
+  }
+  return 1.0 - pre * h;
+}
+
+// q-quantile of chi^2_dof / dof: the x with P(dof / 2, x dof / 2) = q, by
+// bisection (the CDF is increasing).
+double chi2_reduced_quantile(int dof, double q) {
+  const double a = 0.5 * dof;
+  double lo = 0.0, hi = 1.0 + 10.0 / std::sqrt((double)dof);
+  while (gamma_p(a, hi * a) < q) hi *= 2.0;
+  for (int it = 0; it < 400 && hi - lo > 1e-14 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (gamma_p(a, mid * a) < q) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 }  // namespace
@@ -610,10 +651,12 @@ namespace {
 
 // Scratch of one learned-path call over n pixels, carved from one buffer:
 // init [n][10] f32 | list [n] i32 | count u64 | p_fb [n][10] f32 |
-// c_fb [n] f64 | i_fb [n] i32 | s_fb [n] i32, each part 256-byte aligned.
+// c_fb [n] f64 | i_fb [n] i32 | s_fb [n] i32 | s_short [n] i32 (the short
+// fit's status when the caller passes none), each part 256-byte aligned.
 constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct LearnedScratch {
-  size_t o_init = 0, o_list = 0, o_cnt = 0, o_pfb = 0, o_cfb = 0, o_ifb = 0, o_sfb = 0, bytes = 0;
+  size_t o_init = 0, o_list = 0, o_cnt = 0, o_pfb = 0, o_cfb = 0, o_ifb = 0, o_sfb = 0,
+         o_sst = 0, bytes = 0;
   constexpr explicit LearnedScratch(int64_t n) {
     auto al = align256;
     o_init = 0;
@@ -623,7 +666,8 @@ struct LearnedScratch {
     o_cfb = o_pfb + al(sizeof(float) * NPAR * n);
     o_ifb = o_cfb + al(sizeof(double) * n);
     o_sfb = o_ifb + al(sizeof(int32_t) * n);
-    bytes = o_sfb + al(sizeof(int32_t) * n);
+    o_sst = o_sfb + al(sizeof(int32_t) * n);
+    bytes = o_sst + al(sizeof(int32_t) * n);
   }
 };
 
@@ -697,7 +741,11 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
                     " pixels its fixed scratch serves; split the batch");
   if (!stokes || !W || !params || !chi2 || !iters)
     return fail(ctx, VFISV_E_INVALID, "invert_learned: NULL buffer");
-  const double tau = chi2_accept > 0.0 ? chi2_accept : chi2_red_q99((int)std::lround(1.0 / inv_dof));
+  const double tau =
+      chi2_accept > 0.0 ? chi2_accept : chi2_reduced_quantile((int)std::lround(1.0 / inv_dof), 0.99);
+  const bool refit_unconverged = (o.fallback_rule & VFISV_REFIT_UNCONVERGED) != 0;
+  const bool refit_default = (o.fallback_rule & VFISV_REFIT_FROM_DEFAULT) != 0;
+  const bool keep_refit = (o.fallback_rule & VFISV_REFIT_KEEP_REFIT) != 0;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
 
@@ -726,36 +774,64 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
   double* c_fb = (double*)(base + sl.o_cfb);
   int32_t* i_fb = (int32_t*)(base + sl.o_ifb);
   int32_t* s_fb = (int32_t*)(base + sl.o_sfb);
+  int32_t* s_short = status ? status : (int32_t*)(base + sl.o_sst);
   hipStream_t s = (hipStream_t)stream;
+  // per-phase events (measurement), not inside a graph capture
+  bool timing = ctx->phase_on;
+  if (timing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cs);
+    timing = e == hipSuccess && cs == hipStreamCaptureStatusNone;
+  }
+  auto mark = [&](int k) -> hipError_t {
+    return timing ? hipEventRecord(ctx->phase_ev[k], s) : hipSuccess;
+  };
 
   // 1. network proposal of the starting model
+  e = mark(0);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase event");
   rc = vfisv_mlp_forward(ctx, m, n, stokes, nullptr, init, stream);
   if (rc) return rc;
+  e = mark(1);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase event");
   // 2. short LM from the proposal
   vfisv_options ol = o;
   ol.max_iter = learned_max_iter;
   rc = enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, ol, inv_dof,
-                  params, chi2, iters, status, s, true, 1, !noalloc);
+                  params, chi2, iters, s_short, s, true, 1, !noalloc);
   if (rc) return rc;
+  e = mark(2);
+  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap, ctx->d_work, 8, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase record");
   // 3. pixels whose fit is not acceptable go to plain LM from the combined
   // start of Sect. 5 (the proposal with the classical azimuth, and the
   // weak-field B and gamma where the polarisation is weak), written over the
   // proposals once the short LM has read them
   e = zero_u64(count, 1, s);
-  if (e == hipSuccess) e = fallback_select(chi2, n, tau, list, count, s);
+  if (e == hipSuccess)
+    e = fallback_select(chi2, s_short, n, tau, refit_unconverged, list, count, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: fallback selection");
-  const bool combined = inst->C.n_obs >= 3;
+  const bool combined = inst->C.n_obs >= 3 && !refit_default;
   if (combined) {
     rc = vfisv_init_combined(ctx, inst, n, stokes, init, COMBINED_POL_THRESHOLD, init, nullptr,
                              stream);
     if (rc) return rc;
   }
+  e = mark(3);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase event");
   rc = enqueue_lm(ctx, inst, n, count, list, stokes, W, W_per_pixel, combined ? init : nullptr, o,
                   inv_dof, p_fb, c_fb, i_fb, s_fb, s, false, 2, !noalloc);
   if (rc) return rc;
+  e = mark(4);
+  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap + 8, ctx->d_work, 8, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase record");
   // 4. keep the better of the two fits; flag the pixel
-  e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, params, chi2, iters, status, s);
+  e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, keep_refit, params, chi2, iters,
+                     status, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: merge");
+  e = mark(5);
+  if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase event");
+  if (timing) ctx->phase_valid = true;
   return VFISV_OK;
 }
 
@@ -771,6 +847,72 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
                          void* stream) {
   return invert_learned_impl(ctx, inst, m, n, stokes, W, W_per_pixel, opt, learned_max_iter,
                              chi2_accept, params, chi2, iters, status, stream, false);
+}
+
+int vfisv_learned_phase_timing(vfisv_ctx* ctx, int on) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "learned_phase_timing: ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (!on) {
+    if (ctx->phase_on) hipDeviceSynchronize();
+    for (hipEvent_t& ev : ctx->phase_ev)
+      if (ev) {
+        hipEventDestroy(ev);
+        ev = nullptr;
+      }
+    if (ctx->d_phase_snap) hipFree(ctx->d_phase_snap);
+    ctx->d_phase_snap = nullptr;
+    ctx->phase_on = ctx->phase_valid = false;
+    return VFISV_OK;
+  }
+  if (ctx->phase_on) return VFISV_OK;
+  for (hipEvent_t& ev : ctx->phase_ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_phase_snap, 16 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    vfisv_learned_phase_timing(ctx, 0);
+    return hip_fail(ctx, e, "learned_phase_timing: events");
+  }
+  ctx->phase_on = true;
+  ctx->phase_valid = false;
+  return VFISV_OK;
+}
+
+int vfisv_learned_phases_get(vfisv_ctx* ctx, vfisv_learned_phases* out) {
+  if (!ctx) return fail(nullptr, VFISV_E_INVALID, "learned_phases_get: ctx is NULL");
+  if (!out) return fail(ctx, VFISV_E_INVALID, "learned_phases_get: out is NULL");
+  if (!ctx->phase_on || !ctx->phase_valid)
+    return fail(ctx, VFISV_E_INVALID, "learned_phases_get: no timed learned-path call");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipEventSynchronize(ctx->phase_ev[5]);
+  for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ctx->phase_ev[k], ctx->phase_ev[k + 1]);
+    out->ms[k] = ms;
+  }
+  unsigned long long w[16];
+  if (e == hipSuccess) e = hipMemcpy(w, ctx->d_phase_snap, sizeof w, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "learned_phases_get");
+  auto fill = [](vfisv_counters& c, const unsigned long long* a, const unsigned long long* b) {
+    // counters of slots 1..7 of a, less those of b (b == nullptr: none)
+    auto d = [&](int i) { return (int64_t)(a[i] - (b ? b[i] : 0ull)); };
+    c.pixels = d(1);
+    c.trials = d(2);
+    c.accepts = d(3);
+    c.passes = d(4);
+    c.svd_fallbacks = d(5);
+    c.grid_waves = d(6);
+    c.hessians = d(7);
+  };
+  fill(out->short_fit, w, nullptr);
+  fill(out->refit, w + 8, w);
+  return VFISV_OK;
+}
+
+int vfisv_chi2_quantile(int dof, double q, double* out) {
+  if (!out || dof < 1 || dof > 1000000 || !(q > 0.0 && q < 1.0)) return VFISV_E_INVALID;
+  *out = chi2_reduced_quantile(dof, q);
+  return VFISV_OK;
 }
 
 int vfisv_invert_learned_noalloc(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp* m,

@@ -13,8 +13,8 @@ import time
 import numpy as np
 import torch
 
-from . import (NPAR, Context, Instrument, Options, VfisvError, _alloc_out, _Options, _out_ptrs,
-               _ptr, _rows, _stream, _vp, _w_numel, lib, synthesize)
+from . import (NPAR, Context, Instrument, Options, VfisvError, _alloc_out, _Counters, _Options,
+               _out_ptrs, _ptr, _rows, _stream, _vp, _w_numel, lib, synthesize)
 
 NCODE = 10
 
@@ -24,6 +24,10 @@ class _TrainSpec(ctypes.Structure):
                 ("ctrl_stokes", _vp), ("ctrl_params", _vp), ("n_ctrl", ctypes.c_int64),
                 ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
                 ("min_lr_frac", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class _LearnedPhases(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("short_fit", _Counters), ("refit", _Counters)]
 
 
 class _TrainReport(ctypes.Structure):
@@ -61,6 +65,8 @@ def _L():
                                            ctypes.POINTER(_Options), ctypes.c_int,
                                            ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
         L.vfisv_invert_learned_noalloc.argtypes = L.vfisv_invert_learned.argtypes
+        L.vfisv_learned_phase_timing.argtypes = [_vp, ctypes.c_int]
+        L.vfisv_learned_phases_get.argtypes = [_vp, ctypes.POINTER(_LearnedPhases)]
         L._mlp_sigs = True
     return L
 
@@ -203,6 +209,28 @@ def invert_learned(ctx, inst, mlp, stokes, W, opts=None, learned_max_iter=15, ch
     return out
 
 
+PHASES = ("network", "short_fit", "select_combined", "refit", "merge")
+
+
+def phase_timing(ctx, on=True):
+    """Per-phase HIP-event timing of later learned-path calls (not captured
+    ones): vfisv_learned_phase_timing."""
+    ctx._check(_L().vfisv_learned_phase_timing(ctx._h, 1 if on else 0),
+               "vfisv_learned_phase_timing")
+
+
+def learned_phases(ctx):
+    """The most recent timed learned-path call: {"ms": {phase: ms},
+    "short_fit": counters, "refit": counters}."""
+    r = _LearnedPhases()
+    ctx._check(_L().vfisv_learned_phases_get(ctx._h, ctypes.byref(r)), "vfisv_learned_phases_get")
+
+    def cnt(c):
+        return {f: int(getattr(c, f)) for f, _ in _Counters._fields_}
+    return {"ms": dict(zip(PHASES, list(r.ms))), "short_fit": cnt(r.short_fit),
+            "refit": cnt(r.refit)}
+
+
 # ---- training ------------------------------------------------------------
 
 def make_training_set(ctx, inst, n, seed, draw_params, draw_noise, chunk=1 << 20):
@@ -284,4 +312,5 @@ def train(ctx, inst, train_stokes, train_P, control_stokes, control_P, epochs=20
                          epochs=epochs, batch=batch, lr=lr, seed=seed, min_lr_frac=min_lr_frac)
     for h in info["history"]:
         log("epoch %d  train mse %.5f  control mse %.5f" % h)
+    info["stats"] = stats
     return mlp, info

@@ -20,7 +20,7 @@ def _lib():
 def _declared():
     src = open(os.path.join(ROOT, "include", "vfisv.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(vfisv_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(vfisv_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -43,8 +43,8 @@ def test_options_default_and_version():
     L.vfisv_options_default(ctypes.byref(o))
     assert (o.max_iter, o.eps0, o.eps_max, o.rel_tol, o.free_mask, o.grid_waves,
             o.chunk_log2, o.lanes_per_pixel, o.voigt, o.fixed_iters, o.restarts,
-            o.restart_seed, o.hess_reuse) == (50, 1e-3, 1e8, 1e-5, 0x3FF, 0, -1, 1, 0, 0, 0, 0,
-                                              0.0)
+            o.restart_seed, o.hess_reuse, o.fallback_rule) == (50, 1e-3, 1e8, 1e-5, 0x3FF, 0,
+                                                                 -1, 1, 0, 0, 0, 0, 0.0, 0)
     # the Python defaults are the library's
     d = vf.Options().c()
     assert all(getattr(d, f) == getattr(o, f) for f, _ in vf._Options._fields_)
@@ -102,3 +102,36 @@ def test_binding_checks_sizes_before_any_call():
     with pytest.raises(ValueError):
         _ptr(t.t(), torch.float32, cpu, 40)
     assert _ptr(None, torch.float32, cpu, 40) is None
+
+
+def test_chi2_quantile_host_function():
+    """The learned path's default threshold: the 0.99 quantile of
+    chi^2_dof / dof, against the even-dof closed form (a Poisson sum) and
+    against scipy for odd dof; bad arguments are refused."""
+    import math
+    from scipy.stats import chi2
+    vf, L = _lib()
+    L.vfisv_chi2_quantile.argtypes = [ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]
+
+    def q(k, p=0.99):
+        out = ctypes.c_double()
+        assert L.vfisv_chi2_quantile(k, p, ctypes.byref(out)) == 0
+        return out.value
+
+    def cdf_even(x, k):
+        # 1 - exp(-x/2) sum_{j < k/2} (x/2)^j / j!, each term in log space
+        h = 0.5 * x
+        return 1.0 - sum(math.exp(j * math.log(h) - math.lgamma(j + 1) - h)
+                         for j in range(k // 2))
+
+    for k in (2, 14, 438, 4096):
+        x = q(k) * k
+        assert cdf_even(x, k) == pytest.approx(0.99, abs=1e-12), k
+    for k in (1, 3, 15, 439):
+        assert q(k) == pytest.approx(chi2.ppf(0.99, k) / k, rel=1e-12), k
+    assert q(14, 0.5) == pytest.approx(chi2.ppf(0.5, 14) / 14, rel=1e-12)
+    out = ctypes.c_double()
+    assert L.vfisv_chi2_quantile(0, 0.99, ctypes.byref(out)) == -1
+    assert L.vfisv_chi2_quantile(14, 1.0, ctypes.byref(out)) == -1
+    assert L.vfisv_chi2_quantile(14, 0.99, None) == -1

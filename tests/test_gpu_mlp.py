@@ -59,6 +59,44 @@ def _random_net(ctx, n_in, seed):
     return net, flat, in_mean, in_std
 
 
+def _abs_forward(P, cache):
+    """|a3| |W4| + |b4| with the oracle's bfloat16 activations and weights:
+    the sum of the magnitudes that make up each output, the scale of one
+    bfloat16 rounding step taken differently by the two sides."""
+    return np.abs(cache["a3"]) @ np.abs(omlp.to_bf16(P["W4"])) + np.abs(P["b4"])
+
+
+def _abs_backward(P, cache, t):
+    """The backward pass of the oracle with every factor replaced by its
+    magnitude: for each gradient element, the sum of the magnitudes of the
+    products that make it up (through every upstream path)."""
+    r = omlp.to_bf16
+    y = cache["y"]
+    B, n_out = y.shape
+    dz = np.abs(r(2.0 * (y - t) / (B * n_out)))
+    G = {"W4": np.abs(cache["a3"]).T @ dz, "b4": dz.sum(axis=0)}
+    da = dz @ np.abs(r(P["W4"])).T
+    for l in (3, 2, 1):
+        dz = da * np.abs(omlp.gelu_grad(cache["z%d" % l]))
+        G["W%d" % l] = np.abs(cache["a%d" % (l - 1)]).T @ dz
+        G["b%d" % l] = dz.sum(axis=0)
+        if l > 1:
+            da = dz @ np.abs(r(P["W%d" % l])).T
+    return G
+
+
+# A bfloat16 value holds 8 significant bits: where a pre-activation computed
+# by the GPU (float32 MFMA sums) and by the oracle (float64) straddles a
+# rounding midpoint, the two sides store activations one bfloat16 step
+# (<= 2^-7 relative) apart.  Every output and gradient element is a sum of
+# products of such values, so its difference is at most one such step of the
+# sum of the magnitudes of its products (_abs_forward / _abs_backward) when
+# every term differs by a step; such differences are rare (a pre-activation
+# must fall within float32 rounding of a midpoint), so the measured worst
+# case is ~1e-3 of that sum and the median ~1e-6 (float32 accumulation).
+BF16_BOUND = 2.0 ** -7
+
+
 @pytest.mark.parametrize("n_in", [24, 448, 1248])
 def test_forward_matches_oracle(ctx, n_in):
     net, flat, mean, std = _random_net(ctx, n_in, 1)
@@ -67,20 +105,33 @@ def test_forward_matches_oracle(ctx, n_in):
     codes = codes.cpu().numpy()
     P = _unpack(flat, n_in)
     xs = ((x - mean.astype(np.float32)) * (1.0 / std.astype(np.float32))).astype(np.float32)
-    ref, _ = omlp.forward(P, xs, emulate_bf16=True)
-    scale = np.abs(ref).max()
+    ref, cache = omlp.forward(P, xs, emulate_bf16=True)
+    bound = _abs_forward(P, cache)
     err = np.abs(codes - ref)
-    print("[gpu] forward max err %.3g mean err %.3g scale %.3g" % (err.max(), err.mean(), scale))
-    assert err.max() < 2e-2 * scale and err.mean() < 1e-3 * scale
-    # decoded starting models are inside the box and follow the decoding
-    p = params.cpu().numpy()
+    ratio = err / bound
+    print("[gpu] forward max err %.3g, max err / magnitude sum %.3g, p99 %.3g, median %.3g"
+          % (err.max(), ratio.max(), np.quantile(ratio, 0.99), np.median(ratio)))
+    assert np.all(err <= BF16_BOUND * bound)
+    assert np.median(ratio) < 1e-5
+    # decoded starting models: all ten parameters follow the decoding of the
+    # GPU's own codes (Sect. 5 network outputs -> model) and the box
+    p = params.cpu().numpy().astype(np.float64)
     dec = omlp.decode_outputs(codes.astype(np.float64), np.zeros(7), np.ones(7))
     dec = np.array([oracle.project(m) for m in dec])
-    np.testing.assert_allclose(p[:, [0, 1, 3]], dec[:, [0, 1, 3]], rtol=1e-4, atol=1e-3)
+    d = np.abs(p - dec)
+    d[:, 2] = np.minimum(d[:, 2], 180.0 - d[:, 2])  # psi is 180-periodic
+    scale = np.maximum(np.abs(dec), 1.0)
+    print("[gpu] decode max rel err per parameter %s" % np.array2string(
+        (d / scale).max(axis=0), precision=2))
+    assert np.all(d[:, [1, 2]] < 1e-3)                       # degrees
+    assert np.all(d[:, [0, 3, 4, 5, 6, 7, 8, 9]] <= 1e-6 * scale[:, [0, 3, 4, 5, 6, 7, 8, 9]])
 
 
 @pytest.mark.parametrize("n_in", [24, 448])
 def test_gradient_matches_oracle(ctx, n_in):
+    """vfisv_mlp_gradient element by element against the oracle's backward
+    pass with the GPU's bfloat16 roundings (BF16_BOUND of the magnitude sum
+    of every element)."""
     net, flat, mean, std = _random_net(ctx, n_in, 3)
     rng = np.random.default_rng(4)
     x = (rng.normal(size=(512, n_in)) * std + mean).astype(np.float32)
@@ -91,15 +142,53 @@ def test_gradient_matches_oracle(ctx, n_in):
     xs = ((x - mean.astype(np.float32)) * (1.0 / std.astype(np.float32))).astype(np.float32)
     y, cache = omlp.forward(P, xs, emulate_bf16=True)
     R = omlp.backward(P, cache, t.astype(np.float64), emulate_bf16=True)
-    assert loss.item() == pytest.approx(np.sum((y - t) ** 2), rel=1e-2)
+    A = _abs_backward(P, cache, t.astype(np.float64))
+    assert loss.item() == pytest.approx(np.sum((y - t) ** 2), rel=1e-4)
     for k in R:
-        rel = np.linalg.norm(G[k] - R[k]) / np.linalg.norm(R[k])
-        print("[gpu] grad %s rel err %.3g" % (k, rel))
-        assert rel < 3e-2, k
+        err = np.abs(G[k] - R[k])
+        ratio = err / np.maximum(A[k], 1e-300)
+        print("[gpu] grad %s: max err / magnitude sum %.3g, p99 %.3g, median %.3g"
+              % (k, ratio.max(), np.quantile(ratio, 0.99), np.median(ratio)))
+        assert np.all(err <= BF16_BOUND * A[k] + 1e-12 * np.abs(R[k]).max()), k
+        assert np.median(ratio) < 1e-4, k
     # the padding of the first and last layers receives no gradient
     gf = g.cpu().numpy()
     K0 = (n_in + 31) // 32 * 32
     assert np.all(gf[n_in * H:K0 * H] == 0.0)
+
+
+def test_adam_steps_match_the_oracle(ctx):
+    """Five Adam steps of vfisv_mlp_train_step on one batch against the
+    oracle's adam_step applied, step by step, to the GPU's gradient at the
+    same weights: every float32 weight within float32 rounding of the
+    float64 update (the update itself is lr * m-hat / (sqrt(v-hat) + eps),
+    at most ~lr per step)."""
+    n_in = 24
+    net, flat, mean, std = _random_net(ctx, n_in, 9)
+    rng = np.random.default_rng(10)
+    B = 512
+    dev = ctx.device
+    x = torch.tensor((rng.normal(size=(B, n_in)) * std + mean).astype(np.float32), device=dev)
+    t = torch.tensor(rng.normal(size=(B, 10)).astype(np.float32), device=dev)
+    rows = torch.arange(B, dtype=torch.int32, device=dev)
+    lr = 1e-3
+    m = {"w": np.zeros(flat.size)}
+    v = {"w": np.zeros(flat.size)}
+    w_prev = net.get_params().astype(np.float64)
+    for step in range(1, 6):
+        g, _ = net.gradient(x, t)
+        g = g.cpu().numpy().astype(np.float64)
+        net.train_step(x, t, rows, lr)
+        w_gpu = net.get_params().astype(np.float64)
+        ref = omlp.adam_step({"w": w_prev}, {"w": g}, m, v, step, lr)["w"]
+        err = np.abs(w_gpu - ref)
+        moved = np.abs(w_gpu - w_prev)
+        print("[gpu] adam step %d: max |dw| %.3g, max err %.3g" % (step, moved.max(), err.max()),
+              flush=True)
+        assert moved.max() > 0.5 * lr  # the step is taken
+        # float32 weight rounding + float32 moments (relative 1e-6 of the step)
+        assert np.all(err <= 2.0 ** -23 * np.abs(ref) + 1e-5 * lr), step
+        w_prev = w_gpu
 
 
 def test_input_width_limit(ctx):
