@@ -86,6 +86,25 @@ def committed_traffic(n, profile=TRAFFIC_PROFILE):
         return None
 
 
+WORK_KEYS = ("pixels", "trials", "accepts", "passes", "derivative_passes", "jacobians")
+
+
+def algorithmic_flop(c, f_trial, f_jac, f_solve):
+    """FP32 work the method needs (Fig. 6): every trial's synthesis and
+    solve, the values of every start, and the Jacobian (with its filter and
+    normal equations) of every start and every accepted model that does not
+    end its fit, counted by the library as `jacobians`."""
+    return (c["trials"] * (f_trial + f_solve) + c["pixels"] * f_trial
+            + c["jacobians"] * (f_jac - f_trial))
+
+
+def executed_flop(c, f_trial, f_jac, f_solve):
+    """FP32 work a launch executed: its derivative passes at the Jacobian
+    pass's cost, its values-only passes at the trial's, and the solves."""
+    d = c.get("derivative_passes", c["passes"])
+    return d * f_jac + (c["passes"] - d) * f_trial + c["trials"] * f_solve
+
+
 def work_model(n_pts, n_taps, n_obs):
     f_trial = n_pts * FLOP_POINT_VALUES + n_taps * FLOP_TAP_VALUES + n_obs * FLOP_SAMPLE_VALUES
     f_jac = (n_pts * (FLOP_POINT_VALUES + FLOP_POINT_JAC_EXTRA) + n_taps * FLOP_TAP_JAC
@@ -285,10 +304,10 @@ def main():
     f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
 
     def alg(c):
-        return c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
+        return algorithmic_flop(c, f_trial, f_jac, f_solve)
 
     def executed(c):
-        return c["passes"] * f_jac + c["trials"] * f_solve
+        return executed_flop(c, f_trial, f_jac, f_solve)
 
     def q(a, p):
         return float(np.quantile(a, p))
@@ -322,13 +341,13 @@ def main():
                       "peak": PEAK_FP32_TFLOPS,
                       "achieved": round(alg(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
                       "executed": round(executed(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
-                      "work": {k: sf[k] for k in ("pixels", "trials", "accepts", "passes")}},
+                      "work": {k: sf[k] for k in WORK_KEYS}},
         "refit": {"kernel": "lm_kernel<6> (re-fit of the pixels above tau, <= 50 trials)",
                   "ms": round(ph_ms["refit"], 4), "bound": "alu", "unit": "TFLOP/s",
                   "peak": PEAK_FP32_TFLOPS,
                   "achieved": round(alg(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
                   "executed": round(executed(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
-                  "work": {k: rf[k] for k in ("pixels", "trials", "accepts", "passes")}},
+                  "work": {k: rf[k] for k in WORK_KEYS}},
         "network": {"kernel": "mlp_infer_kernel (fused 4-layer inference + decode)",
                     "ms": round(ph_ms["network"], 4), "bound": "mfma", "unit": "TFLOP/s",
                     "peak": PEAK_BF16_TFLOPS,
@@ -412,7 +431,7 @@ def main():
             "plain_lm_launch": {
                 "ms": round(float(np.median(ev_p)), 4),
                 "achieved": round(alg(c_p) / (np.median(ev_p) * 1e-3) / 1e12, 3),
-                "work": {k: c_p[k] for k in ("trials", "accepts", "passes", "pixels")}},
+                "work": {k: c_p[k] for k in WORK_KEYS}},
         },
     }
 
@@ -510,7 +529,7 @@ def full_disk(args, ctx, inst, spec, log):
     log("chunk_log2 sweep (ms): %s" % sweep)
 
     f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
-    alg = c["trials"] * (f_trial + f_solve) + (c["pixels"] + c["accepts"]) * f_jac
+    alg = algorithmic_flop(c, f_trial, f_jac, f_solve)
     achieved = alg / (ev_ms * 1e-3) / 1e12
 
     # the same disk with the per-pixel weights of Eqs. 14-15 (mu from the
@@ -576,7 +595,7 @@ def full_disk(args, ctx, inst, spec, log):
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": None, "kernel": "lm_kernel (one launch per step)",
                      "kernel_ms": round(ev_ms, 3),
-                     "work": {k: c[k] for k in ("trials", "accepts", "passes", "pixels")}},
+                     "work": {k: c[k] for k in WORK_KEYS}},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -659,7 +678,7 @@ def fine_mixed(args, ctx, inst, spec, log):
 
     fi = finst.info
     f_trial, f_jac, f_solve = work_model(fi["n_active_fine"], fi["n_taps"], fspec.n_obs)
-    alg = c_f["trials"] * (f_trial + f_solve) + (c_f["pixels"] + c_f["accepts"]) * f_jac
+    alg = algorithmic_flop(c_f, f_trial, f_jac, f_solve)
     achieved = alg / (ev_f * 1e-3) / 1e12
     tr_f = committed_traffic(n_f, FINE_TRAFFIC_PROFILE)
     n = n_f + n_h
@@ -693,9 +712,8 @@ def fine_mixed(args, ctx, inst, spec, log):
                      "kernel": "lm_kernel<0> (banded, fine pixels alone)",
                      "kernel_ms": round(ev_f, 3), "flop_per_trial": f_trial,
                      "flop_per_jacobian_pass": f_jac,
-                     "work_fine": {k: c_f[k] for k in ("trials", "accepts", "passes", "pixels")},
-                     "work_mixed": {k: c_mix[k] for k in ("trials", "accepts", "passes",
-                                                          "pixels")}},
+                     "work_fine": {k: c_f[k] for k in WORK_KEYS},
+                     "work_mixed": {k: c_mix[k] for k in WORK_KEYS}},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -158,7 +158,22 @@ typedef struct {
                        /* VFISV_REFIT_UNCONVERGED, VFISV_REFIT_FROM_DEFAULT, */
                        /* VFISV_REFIT_KEEP_REFIT (all three: the rule as    */
                        /* stated for the learned initialiser's fallback).    */
+  int deriv_split;     /* Fig. 6 computes derivatives only after a successful */
+                       /* trial.  0: every pass computes the Jacobian of its  */
+                       /* model, ahead of the acceptance test (one pass per   */
+                       /* trial); k in 1..64: trials run values-only passes  */
+                       /* and an accepted model waits for a derivative pass, */
+                       /* which a wave runs once k/64 of its live lanes (or  */
+                       /* all of them) wait; -1 (default): the              */
+                       /* vfisv_autotune choice, else VFISV_DERIV_SPLIT_DEFAULT; */
+                       /* the learned path's default is 0 (its short fits    */
+                       /* start near the minimum, where most trials need     */
+                       /* their Jacobian).                                   */
+                       /* Scheduling only: the per-pixel results are the same */
+                       /* bits for every value.  Not with fixed_iters.        */
 } vfisv_options;
+
+#define VFISV_DERIV_SPLIT_DEFAULT 4
 
 /* vfisv_options.fallback_rule bits (Sect. 5 leaves the fallback open). */
 #define VFISV_REFIT_UNCONVERGED 1  /* also re-fit pixels whose short fit did
@@ -177,6 +192,7 @@ typedef struct {
   double default_ms;  /* with the untuned default (-1 if not a candidate) */
   int candidates;     /* configurations timed                            */
   int64_t sample;     /* pixels in the timed sample                      */
+  int deriv_split;    /* chosen derivative-pass split (vfisv_options)    */
 } vfisv_tuning;
 
 /* Work counters of the most recent vfisv_invert on a context. */
@@ -189,6 +205,10 @@ typedef struct {
   int64_t grid_waves;     /* waves launched                                 */
   int64_t hessians;       /* J^T W J updates: initial, restart and accepted */
                           /* models, less those kept by hess_reuse          */
+  int64_t derivative_passes; /* passes that computed the Jacobian (all of   */
+                          /* them when deriv_split is 0)                     */
+  int64_t jacobians;      /* Jacobians the fits need (Fig. 6): one per start */
+                          /* and per accepted trial that does not end its fit */
 } vfisv_counters;
 
 /* ---- context ---------------------------------------------------------- */
@@ -300,16 +320,19 @@ int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batch
 
 /* Scheduling autotuner: inverts the first `sample` pixels (<= 0: 131072,
  * at most n) of the caller's data, from the default model with opt's fit
- * settings, with every candidate persistent grid
- * (1, 2, 3, 4, 6 or 8 waves per CU, up to the waves that are resident at
- * once for the layout's kernel, at most 8 waves per CU) and
- * pixel-queue block (2^4, 2^8, 2^12 pixels), twice each, timed with HIP
- * events on `stream`, and keeps the fastest for this instrument's layout in
- * the context; later inversions with grid_waves == 0 and chunk_log2 == -1
- * use it.  Results go to library scratch (the caller's outputs are not
- * touched) and are identical for every candidate, so only speed changes.
- * Allocates and synchronises: call it at set-up, not under graph capture.
- * out may be NULL.  Overwrites the work counters. */
+ * settings, twice per candidate, timed with HIP events on `stream`: first
+ * every derivative-pass split (deriv_split 0, 2, 4, 8, 16, 32;
+ * the fixed-iteration scheme only 0) at the default schedule, then at the
+ * best split every persistent grid (1, 2, 3, 4, 6 or 8 waves per CU, up to
+ * the waves that are resident at once for the layout's kernel) and
+ * pixel-queue block (2^4, 2^8, 2^12 pixels).  The fastest is kept for this
+ * instrument's layout in the context; later inversions with grid_waves == 0,
+ * chunk_log2 == -1 and deriv_split == -1 use it.  default_ms is the time of
+ * the untuned default (split VFISV_DERIV_SPLIT_DEFAULT, default schedule).
+ * Results go to library scratch (the caller's outputs are not touched) and
+ * are identical for every candidate, so only speed changes.  Allocates and
+ * synchronises: call it at set-up, not under graph capture.  out may be
+ * NULL.  Overwrites the work counters. */
 int vfisv_autotune(vfisv_ctx *ctx, const vfisv_instrument *inst, int64_t n,
                    const float *stokes, const float *W, int W_per_pixel,
                    const vfisv_options *opt, int64_t sample, vfisv_tuning *out,

@@ -48,7 +48,8 @@ class _Options(ctypes.Structure):
                 ("chunk_log2", ctypes.c_int), ("lanes_per_pixel", ctypes.c_int),
                 ("voigt", ctypes.c_int), ("fixed_iters", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("restart_seed", ctypes.c_uint64),
-                ("hess_reuse", ctypes.c_double), ("fallback_rule", ctypes.c_uint32)]
+                ("hess_reuse", ctypes.c_double), ("fallback_rule", ctypes.c_uint32),
+                ("deriv_split", ctypes.c_int)]
 
 
 class _Batch(ctypes.Structure):
@@ -62,14 +63,16 @@ class _Batch(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int), ("chunk_log2", ctypes.c_int),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("candidates", ctypes.c_int), ("sample", ctypes.c_int64)]
+                ("candidates", ctypes.c_int), ("sample", ctypes.c_int64),
+                ("deriv_split", ctypes.c_int)]
 
 
 class _Counters(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("trials", ctypes.c_int64),
                 ("accepts", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("svd_fallbacks", ctypes.c_int64), ("grid_waves", ctypes.c_int64),
-                ("hessians", ctypes.c_int64)]
+                ("hessians", ctypes.c_int64), ("derivative_passes", ctypes.c_int64),
+                ("jacobians", ctypes.c_int64)]
 
 
 # Every symbol declared in include/vfisv.h.
@@ -259,12 +262,13 @@ class Options:
     restart_seed: int = 0
     hess_reuse: float = 0.0
     fallback_rule: int = 0
+    deriv_split: int = -1
 
     def c(self):
         return _Options(self.max_iter, self.eps0, self.eps_max, self.rel_tol, self.free_mask,
                         self.grid_waves, self.chunk_log2, self.lanes_per_pixel, self.voigt,
                         self.fixed_iters, self.restarts, self.restart_seed, self.hess_reuse,
-                        self.fallback_rule)
+                        self.fallback_rule, self.deriv_split)
 
 
 def synthesize(ctx, inst, params, noise=None, jac=False, out=None, voigt=0):
@@ -387,9 +391,10 @@ def init_combined(ctx, inst, stokes, base, pol_threshold=0.06, out=None):
 
 
 def autotune(ctx, inst, stokes, W, opts=None, sample=0):
-    """Pick the persistent grid and pixel-queue block for this instrument's
-    layout by timing them on the first ``sample`` pixels; later inversions
-    with automatic scheduling options use the choice.  Returns a dict."""
+    """Pick the derivative-pass split, persistent grid and pixel-queue block
+    for this instrument's layout by timing them on the first ``sample``
+    pixels; later inversions with automatic scheduling options use the
+    choice.  Returns a dict."""
     dev = ctx.device
     o = (opts or Options()).c()
     t = _Tuning()

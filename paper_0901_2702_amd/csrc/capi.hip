@@ -67,6 +67,8 @@ int check_options(vfisv_ctx* ctx, const vfisv_instrument* inst, const vfisv_opti
   if (o.restarts < 0 || o.restarts > 4095)
     return fail(ctx, VFISV_E_INVALID, "options: restarts outside 0..4095");
   if (!(o.hess_reuse >= 0.0)) return fail(ctx, VFISV_E_INVALID, "options: hess_reuse must be >= 0");
+  if (o.deriv_split < -1 || o.deriv_split > 64)
+    return fail(ctx, VFISV_E_INVALID, "options: deriv_split outside -1..64");
   if (o.fallback_rule & ~7u)
     return fail(ctx, VFISV_E_INVALID, "options: fallback_rule takes the VFISV_REFIT_* bits only");
   if (o.voigt != 0 && inst->kind != KIND_DENSE6)
@@ -99,11 +101,13 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.C.vtab = ctx->d_vtab;
   a.pts = inst->d_pts;
   a.pts5 = inst->d_pts5;
+  a.ptsv = inst->d_ptsv ? inst->d_ptsv : inst->d_pts;
   a.blocks = inst->d_blocks;
   a.row_sums = inst->d_row_sums;
   a.qbase = QUEUE_SLOT0;
   a.lpp_max = 1;
   a.lane_cap = 0;
+  a.pair_max = 0;
   a.stokes = stokes;
   a.stokes4 = nullptr;
   a.W = W;
@@ -129,6 +133,8 @@ static void fill_lm_args(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   a.restarts = o.restarts;
   a.seed = (unsigned long long)o.restart_seed;
   a.hess_reuse = o.hess_reuse;
+  a.deriv_split = o.deriv_split >= 0 ? o.deriv_split
+                                     : (t.valid ? t.deriv_split : VFISV_DERIV_SPLIT_DEFAULT);
 }
 
 static int lm_grid(vfisv_ctx* ctx, int64_t n, int bpc, const vfisv_options& o, int kind) {
@@ -163,6 +169,11 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   LMArgs a;
   fill_lm_args(ctx, inst, n, n_dev, idx, stokes, W, W_pp, init, o, inv_dof, params, chi2, iters,
                status, a);
+  // lpp_max 3: pairs up to one pixel per resident lane (pixels beyond the
+  // pairs that run at once wait for a free pair), else only when every
+  // pixel gets a pair at once
+  const bool pairs_oversub = lpp_max == 3;
+  if (lpp_max > 2) lpp_max = 2;
   if (o.lanes_per_pixel > lpp_max) lpp_max = o.lanes_per_pixel;
   if (inst->kind != KIND_DENSE6) lpp_max = 1;
   a.lpp_max = lpp_max;
@@ -172,6 +183,7 @@ int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   const int grid = lm_grid(ctx, lpp_max == 2 && !n_dev ? 2 * n : n, bpc, o, inst->kind);
   const int64_t resident = (int64_t)ctx->num_cus * bpc;
   a.lane_cap = (long long)(grid < resident ? grid : resident) * 64;
+  a.pair_max = pairs_oversub ? a.lane_cap : a.lane_cap / 2;
   if (inst->kind == KIND_BAND && !idx && !n_dev && n > 0 && may_alloc) {
     // a whole banded batch: the pass reads an interleaved copy
     const int no = inst->C.n_obs;
@@ -225,7 +237,7 @@ namespace vfisv_capi {
 // w(z) over the table's range), rounded to float.
 int ensure_vtab(vfisv_ctx* ctx) {
   if (ctx->d_vtab) return VFISV_OK;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   double L, a[33];
   weideman_coefficients(32, &L, a);
@@ -350,6 +362,7 @@ void vfisv_options_default(vfisv_options* o) {
   o->restart_seed = 0;
   o->hess_reuse = 0.0;
   o->fallback_rule = 0u;
+  o->deriv_split = -1;
 }
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
@@ -378,6 +391,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   vfisv_instrument* inst = new (std::nothrow) vfisv_instrument();
   if (!inst) return fail(ctx, VFISV_E_NOMEM, "instrument_create: host allocation");
   inst->ctx = ctx;
+  inst->device = ctx->device;
   std::memset(&inst->C, 0, sizeof(Consts));
   inst->C.sw_k = -1;
   double max_drop = 0.0;
@@ -399,7 +413,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
     if (rsum > 0.0) max_drop = std::fmax(max_drop, drop / rsum);
     row_sum[(size_t)i] = (float)ksum;
   }
-  std::vector<Point> pts, pts5;
+  std::vector<Point> pts, pts5, ptsv;
   std::vector<Block> blocks;
   int n_taps = 0, n_active = 0;
   if (no == NOBS_HMI) {
@@ -463,6 +477,20 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
         std::memcpy(&Q.w[6], &m, 4);
       }
       inst->C.sw_k = sw;
+      // the values-only pass: all six rows in the slot order above
+      ptsv.resize(pts.size());
+      for (int k = 0; k < (int)pts.size(); ++k) {
+        const Point& P = pts[(size_t)k];
+        Point& Q = ptsv[(size_t)k];
+        std::memset(&Q, 0, sizeof Q);
+        Q.dl = P.dl;
+        uint32_t m = 0;
+        for (int q = 0; q < 6; ++q) {
+          Q.w[q] = P.w[inst->C.slot_row[q]];
+          if (Q.w[q] != 0.f) m |= 1u << q;
+        }
+        std::memcpy(&Q.w[6], &m, 4);
+      }
     }
   } else {
     // banded: row i's kept taps must lie in points a0 + 4 i .. a0 + 4 i + 15
@@ -526,7 +554,7 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   inst->info.lm_register_rows =
       inst->kind == KIND_BAND ? BAND_R : (inst->C.sw_k >= 0 ? 5 : NOBS_HMI);
 
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) {
     delete inst;
     return hip_fail(ctx, e, "hipSetDevice");
@@ -560,6 +588,12 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
         e = hipMemcpy(inst->d_pts5, pts5.data(), sizeof(Point) * pts5.size(),
                       hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && !ptsv.empty()) {
+      e = hipMalloc(&inst->d_ptsv, sizeof(Point) * ptsv.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(inst->d_ptsv, ptsv.data(), sizeof(Point) * ptsv.size(),
+                      hipMemcpyHostToDevice);
+    }
   } else {
     e = hipMalloc(&inst->d_blocks, sizeof(Block) * blocks.size());
     if (e == hipSuccess) e = hipMalloc(&inst->d_row_sums, sizeof(float) * (size_t)no);
@@ -573,6 +607,8 @@ int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
   if (e != hipSuccess) {
     if (inst->d_pts) hipFree(inst->d_pts);
     if (inst->d_pts5) hipFree(inst->d_pts5);
+  if (inst->d_ptsv) hipFree(inst->d_ptsv);
+    if (inst->d_ptsv) hipFree(inst->d_ptsv);
     if (inst->d_blocks) hipFree(inst->d_blocks);
     if (inst->d_row_sums) hipFree(inst->d_row_sums);
     hipFree(inst->d_obs_x);
@@ -591,10 +627,11 @@ int vfisv_instrument_info_get(const vfisv_instrument* inst, vfisv_instrument_inf
 
 int vfisv_instrument_destroy(vfisv_instrument* inst) {
   if (!inst) return VFISV_OK;
-  hipSetDevice(inst->ctx->device);
+  hipSetDevice(inst->device);
   hipDeviceSynchronize();
   if (inst->d_pts) hipFree(inst->d_pts);
   if (inst->d_pts5) hipFree(inst->d_pts5);
+  if (inst->d_ptsv) hipFree(inst->d_ptsv);
   if (inst->d_blocks) hipFree(inst->d_blocks);
   if (inst->d_row_sums) hipFree(inst->d_row_sums);
   if (inst->d_obs_x) hipFree(inst->d_obs_x);
@@ -620,7 +657,7 @@ int vfisv_synthesize_voigt(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t
     return fail(ctx, VFISV_E_UNSUPPORTED, "synthesize: the Taylor table serves HMI-shaped instruments");
   if (n == 0) return VFISV_OK;
   if (!params || !stokes) return fail(ctx, VFISV_E_INVALID, "synthesize: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (voigt != 0) {
     rc = ensure_vtab(ctx);
@@ -658,7 +695,7 @@ int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const 
   if (n > INT32_MAX) return fail(ctx, VFISV_E_INVALID, "invert: n must be < 2^31");
   if (!stokes || !W || !params || !chi2 || !iters)
     return fail(ctx, VFISV_E_INVALID, "invert: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   return enqueue_lm(ctx, inst, n, nullptr, nullptr, stokes, W, W_per_pixel, init, o, inv_dof,
                     params, chi2, iters, status, (hipStream_t)stream, true);
@@ -697,7 +734,7 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
     total += b.n;
   }
   if (total == 0) return VFISV_OK;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   const int grid = lm_grid(ctx, total, ctx->band_blocks_per_cu, o, -1);
   hipStream_t s = (hipStream_t)stream;
@@ -739,7 +776,7 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   if (!stokes || !W) return fail(ctx, VFISV_E_INVALID, "autotune: NULL buffer");
   if (sample <= 0) sample = 131072;
   const int64_t m = sample < n ? sample : n;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   float* params = nullptr;
@@ -751,9 +788,13 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   if (e == hipSuccess) e = hipMalloc(&iters, sizeof(int32_t) * (size_t)m);
   if (e == hipSuccess) e = hipEventCreate(&ev0);
   if (e == hipSuccess) e = hipEventCreate(&ev1);
-  // candidates: persistent grid (waves per CU) x queue block size
+  // candidates: the derivative-pass split (fused, or a derivative pass once
+  // k/64 of a wave's lanes wait) at the default schedule, then the
+  // persistent grid (waves per CU, up to what is resident) x queue block
+  // size at the best split
   const int bpc_default = inst->kind == KIND_DENSE6 ? ctx->lm_blocks_per_cu
                                                     : ctx->band_blocks_per_cu;
+  const int splits[] = {0, 2, 4, 8, 16, 32};
   const int waves_per_cu[] = {1, 2, 3, 4, 6, 8};
   const int chunks[] = {4, 8, 12};
   vfisv_tuning best;
@@ -761,7 +802,41 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   best.best_ms = 1e300;
   best.default_ms = -1.0;
   int cand = 0;
-  for (int wi = 0; e == hipSuccess && wi < 6; ++wi) {
+  auto time_one = [&](const vfisv_options& oc, float* ms) {
+    *ms = 1e30f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(ev0, s);
+      if (e != hipSuccess) break;
+      rc = enqueue_lm(ctx, inst, m, nullptr, nullptr, stokes, W, W_per_pixel, nullptr, oc,
+                      inv_dof, params, chi2, iters, nullptr, s, true);
+      if (rc) break;
+      e = hipEventRecord(ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, ev0, ev1);
+      if (e == hipSuccess && t < *ms) *ms = t;
+    }
+    ++cand;
+  };
+  const int64_t gw_default = (int64_t)ctx->num_cus * bpc_default;
+  int best_split = VFISV_DERIV_SPLIT_DEFAULT;
+  float best_split_ms = 1e30f;
+  for (int si = 0; e == hipSuccess && !rc && si < 6; ++si) {
+    vfisv_options oc = o;
+    oc.grid_waves = (int)std::min<int64_t>(gw_default, ctx->max_lanes / 64);
+    oc.chunk_log2 = 8;
+    oc.deriv_split = o.fixed_iters > 0 ? 0 : splits[si];
+    float ms;
+    time_one(oc, &ms);
+    if (rc || e != hipSuccess) break;
+    if (splits[si] == VFISV_DERIV_SPLIT_DEFAULT) best.default_ms = ms;
+    if (ms < best_split_ms) {
+      best_split_ms = ms;
+      best_split = oc.deriv_split;
+    }
+    if (o.fixed_iters > 0) break;  // the fixed-iteration scheme always fuses
+  }
+  for (int wi = 0; e == hipSuccess && !rc && wi < 6; ++wi) {
     const int64_t gw = (int64_t)ctx->num_cus * waves_per_cu[wi];
     // a persistent grid larger than what is resident only adds waves that
     // start when the work is gone
@@ -770,26 +845,15 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
       vfisv_options oc = o;
       oc.grid_waves = (int)gw;
       oc.chunk_log2 = chunks[ci];
-      float ms = 1e30f;
-      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-        e = hipEventRecord(ev0, s);
-        if (e != hipSuccess) break;
-        rc = enqueue_lm(ctx, inst, m, nullptr, nullptr, stokes, W, W_per_pixel, nullptr, oc,
-                        inv_dof, params, chi2, iters, nullptr, s, true);
-        if (rc) break;
-        e = hipEventRecord(ev1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(ev1);
-        float t = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev0, ev1);
-        if (e == hipSuccess && t < ms) ms = t;
-      }
+      oc.deriv_split = best_split;
+      float ms;
+      time_one(oc, &ms);
       if (rc) break;
-      ++cand;
-      if (waves_per_cu[wi] == bpc_default && chunks[ci] == 8) best.default_ms = ms;
       if (e == hipSuccess && ms < best.best_ms) {
         best.best_ms = ms;
         best.grid_waves = (int)gw;
         best.chunk_log2 = chunks[ci];
+        best.deriv_split = best_split;
       }
     }
   }
@@ -806,6 +870,7 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   t.valid = true;
   t.grid_waves = best.grid_waves;
   t.chunk_log2 = best.chunk_log2;
+  t.deriv_split = best.deriv_split;
   if (out) *out = best;
   return VFISV_OK;
 }
@@ -825,7 +890,7 @@ int init_start(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const fl
     return fail(ctx, VFISV_E_INVALID, std::string(what) + ": pol_threshold must be >= 0");
   if (n == 0) return VFISV_OK;
   if (!stokes || !params) return fail(ctx, VFISV_E_INVALID, std::string(what) + ": NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   ClassicalArgs a;
   a.stokes = stokes;
@@ -876,7 +941,7 @@ int vfisv_stokes_weights(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
   }
   if (n == 0) return VFISV_OK;
   if (!stokes || !mu || !W) return fail(ctx, VFISV_E_INVALID, "stokes_weights: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   a.stokes = stokes;
   a.mu = mu;
@@ -893,7 +958,7 @@ int vfisv_stokes_weights(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n
 int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "get_counters: ctx is NULL");
   if (!out) return fail(ctx, VFISV_E_INVALID, "get_counters: out is NULL");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   unsigned long long w[WORK_SLOTS];
   if (e == hipSuccess) e = hipMemcpy(w, ctx->d_work, sizeof w, hipMemcpyDeviceToHost);
@@ -905,6 +970,8 @@ int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
   out->svd_fallbacks = (int64_t)w[5];
   out->grid_waves = (int64_t)w[6];
   out->hessians = (int64_t)w[7];
+  out->derivative_passes = (int64_t)w[0];
+  out->jacobians = (int64_t)w[8];
   return VFISV_OK;
 }
 
@@ -915,7 +982,7 @@ int vfisv_iter_histogram(vfisv_ctx* ctx, int64_t n, const int32_t* iters, int n_
   if (n_bins < 1 || n_bins > HIST_MAX)
     return fail(ctx, VFISV_E_INVALID, "iter_histogram: n_bins outside 1..4096");
   if (!hist || (n > 0 && !iters)) return fail(ctx, VFISV_E_INVALID, "iter_histogram: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* bins = ctx->d_work + WORK_SLOTS;
@@ -935,7 +1002,7 @@ int vfisv_solve(vfisv_ctx* ctx, int64_t n, const float* H, const float* g, const
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "solve: n < 0");
   if (n == 0) return VFISV_OK;
   if (!H || !g || !eps || !delta) return fail(ctx, VFISV_E_INVALID, "solve: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   SolveArgs a;
   a.H = H;

@@ -24,6 +24,7 @@ struct vfisv_ctx {
     bool valid = false;
     int grid_waves = 0;
     int chunk_log2 = 8;
+    int deriv_split = VFISV_DERIV_SPLIT_DEFAULT;
   } tuned[2];
   // learned-start scratch (grown on demand)
   void* d_learn = nullptr;
@@ -33,7 +34,7 @@ struct vfisv_ctx {
   void* noalloc_scratch = nullptr;
   // per-phase timing of the learned path (vfisv_learned_phase_timing):
   // events between its phases and the work counters after the short fit
-  // ([0, 8)) and after the re-fit ([8, 16))
+  // ([0, 16)) and after the re-fit ([16, 32))
   bool phase_on = false;
   bool phase_valid = false;
   hipEvent_t phase_ev[6] = {};
@@ -46,9 +47,12 @@ struct vfisv_ctx {
 
 struct vfisv_instrument {
   vfisv_ctx* ctx = nullptr;
+  int device = 0;  // the context's device, kept so that destroying the
+                   // instrument never reads the context
   int kind = vfisv::KIND_DENSE6;
   vfisv::Point* d_pts = nullptr;       // KIND_DENSE6
   vfisv::Point* d_pts5 = nullptr;      // KIND_DENSE6, windowed records (C.sw_k >= 0)
+  vfisv::Point* d_ptsv = nullptr;      // KIND_DENSE6, rows in the windowed slot order
   vfisv::Block* d_blocks = nullptr;    // KIND_BAND
   float* d_row_sums = nullptr;         // KIND_BAND
   float* d_obs_x = nullptr;            // [n_obs] observed wavelength of each sample
@@ -57,6 +61,15 @@ struct vfisv_instrument {
 };
 
 namespace vfisv_capi {
+
+// Make ctx's device current and clear the thread's last HIP error, which the
+// launch checks read (an earlier call, of this library or not, may have left
+// one there).
+inline hipError_t use_device(const vfisv_ctx* ctx) {
+  const hipError_t e = hipSetDevice(ctx->device);
+  (void)hipGetLastError();
+  return e;
+}
 
 int fail(vfisv_ctx* ctx, int code, const std::string& msg);
 int hip_fail(vfisv_ctx* ctx, hipError_t e, const char* what);

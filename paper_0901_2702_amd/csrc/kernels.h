@@ -9,11 +9,14 @@
 
 namespace vfisv {
 
-// work[] slots: 1 pixels done, 2 trials, 3 accepts, 4 passes, 5 eigen
-// fallbacks, 6 waves; QUEUE_SLOT0 + NQ * batch + q: head of pixel queue q
-// (one per XCD) of a batch
+// work[] slots: 0 synthesis passes with derivatives, 1 pixels done,
+// 2 trials, 3 accepts, 4 passes, 5 eigen fallbacks, 6 waves, 7 J^T W J
+// builds, 8 Jacobians the fits need (starts and accepted models that do not
+// end their fit); COUNTER_SLOTS counters in all; QUEUE_SLOT0 + NQ * batch +
+// q: head of pixel queue q (one per XCD) of a batch
 constexpr int NQ = 8;
-constexpr int QUEUE_SLOT0 = 8;
+constexpr int COUNTER_SLOTS = 9;
+constexpr int QUEUE_SLOT0 = 16;
 constexpr int MAX_BATCHES = 4;
 constexpr int WORK_SLOTS = QUEUE_SLOT0 + NQ * MAX_BATCHES;
 
@@ -26,6 +29,8 @@ struct LMArgs {
   Consts C;
   const Point* pts;        // KIND_DENSE6
   const Point* pts5;       // KIND_DENSE6, windowed records (C.sw_k >= 0)
+  const Point* ptsv;       // KIND_DENSE6, the rows in the windowed pass's slot
+                           // order (values-only pass; = pts when C.sw_k < 0)
   const Block* blocks;     // KIND_BAND: C.n_obs + BAND_R - 1 blocks
   const float* row_sums;   // KIND_BAND: [n_obs] sums of the kept taps
   const float* stokes;
@@ -51,8 +56,13 @@ struct LMArgs {
   int restarts;     // restarts allowed per pixel in that scheme
   unsigned long long seed;  // key of the restart perturbations
   double hess_reuse;        // keep J^T W J for steps from models below this chi^2
-  long long lane_cap;       // lanes of the grid that are resident at once (lane-pair choice)
+  long long lane_cap;       // lanes of the grid that are resident at once
+  long long pair_max;       // lane pairs (lpp_max 2) when the batch has at most this
+                            // many pixels
   const float4* stokes4;    // KIND_BAND: [n][n_obs] interleaved copy of stokes, or NULL
+  int deriv_split;          // 0: every pass computes derivatives (fused); k in 1..64:
+                            // values-only passes for the trials, a derivative pass
+                            // once k/64 of a wave's live lanes wait for one
 };
 
 // Several batches (instrument + pixels + outputs) in one persistent launch:

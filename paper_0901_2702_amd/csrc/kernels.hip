@@ -61,7 +61,8 @@ __device__ __forceinline__ double restart_half(int q) {
 }
 
 struct WaveCounters {
-  unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0, hess = 0;
+  unsigned long long pix = 0, trial = 0, acc = 0, pass = 0, fb = 0, hess = 0, jpass = 0,
+                     jneed = 0;
 };
 
 // One synthesis pass with derivatives at Mc for the pixel's observations:
@@ -327,6 +328,76 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
   return chi;
 }
 
+// One synthesis pass without derivatives at Mc: the reduced chi^2 (Eq. 1)
+// in float64 of a trial.  Every row receives the same products in the same
+// order as in lm_pass, and the rows enter chi^2 in lm_pass's order (the
+// windowed pass folds its register slots first and the parked row last;
+// ptsv holds the rows in that order), so a model gets the same chi^2 from
+// either pass.
+template <int NOBS, int LPP, int V>
+__device__ __forceinline__ double lm_pass_values(const LMArgs& A, const float* Mc, int64_t pix,
+                                                 int lane) {
+  Pix px;
+  pix_setup(Mc, A.C, px);
+  RowFactors rf;
+  row_factors(Mc, px, A.C, rf);
+  double chi = 0.0;
+  if constexpr (NOBS > 0) {
+    constexpr int ROWS = 4 * NOBS;
+    const float* obs = A.stokes + pix * ROWS;
+    const float* Wp = A.W_pp ? A.W + pix * ROWS : A.W;
+    const bool win = LPP == 1 && A.C.sw_k >= 0;
+    float acc[NOBS][NACC];
+    if constexpr (LPP == 2)
+      synth_accumulate_pair<NOBS, V, false>(A.pts, px, A.C, acc, lane & 1);
+    else
+      synth_accumulate<NOBS, false, V>(win ? A.ptsv : A.pts, px, A.C, acc);
+#pragma unroll
+    for (int q = 0; q < NOBS; ++q) {
+      const int i = win ? A.C.slot_row[q] : q;
+      float S[4], J[4][NPAR];
+      assemble_sample<false>(acc[q], win ? A.C.slot_rs[q] : A.C.row_sum[q], rf, S, J);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float r = obs[s * NOBS + i] - S[s];
+        chi = fma((double)Wp[s * NOBS + i] * (double)r, (double)r, chi);
+      }
+    }
+  } else {
+    const int no = A.C.n_obs;
+    const float* obs = A.stokes + pix * (int64_t)(4 * no);
+    const float* Wp = A.W_pp ? A.W + pix * (int64_t)(4 * no) : A.W;
+    float ob[4], wb[4], rs = 0.f;
+    band_accumulate<false>(
+        A.blocks, no, px, A.C,
+        [&](int j) {
+          rs = A.row_sums[j];
+          if (A.stokes4) {
+            const float4 o4 = A.stokes4[pix * (int64_t)no + j];
+            ob[0] = o4.x;
+            ob[1] = o4.y;
+            ob[2] = o4.z;
+            ob[3] = o4.w;
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) ob[s] = obs[s * no + j];
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) wb[s] = Wp[s * no + j];
+        },
+        [&](int, const float* a) {
+          float S[4], J[4][NPAR];
+          assemble_sample<false>(a, rs, rf, S, J);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const float r = ob[s] - S[s];
+            chi = fma((double)wb[s] * (double)r, (double)r, chi);
+          }
+        });
+  }
+  return chi * A.inv_dof;
+}
+
 // The persistent LM loop of one wave over one batch: lanes take pixels
 // from the batch's queues, fit them, and return when the queues are empty
 // and every lane has finished.
@@ -337,7 +408,7 @@ __device__ __forceinline__ double lm_pass(const LMArgs& A, const float* Mc, int6
 // PAPER: the fixed-iteration scheme of Sect. 4.2 (A.fixed_iters trials per
 // pixel, restarts from a perturbed best model, the best model seen is the
 // result); otherwise exits on convergence, stall or A.max_iter.
-template <int NOBS, int LPP, int V = 0, bool PAPER = false>
+template <int NOBS, int LPP, int V = 0, bool PAPER = false, bool SPLIT = false>
 __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa, double* sws,
                                         int lane,
                                         int64_t glane,
@@ -372,7 +443,14 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
   // the damped solve needs the eigen fallback: done with the whole wave at
   // the top of the next turn, where every lane is active
   bool need_fb = false;
+  // derivative pass due (Fig. 6: derivatives only at accepted models): an
+  // accepted trial of a values-only pass waits for the next derivative pass
+  // of its wave; kh_wait: that pass keeps J^T W J (Sect. 4.4)
+  bool need_j = false, kh_wait = false;
   const int limit = PAPER ? A.fixed_iters : A.max_iter;
+  // SPLIT: trials in values-only passes, derivatives in their own pass (not
+  // in the fixed-iteration scheme, whose restarts are fresh starts)
+  static_assert(!(SPLIT && PAPER), "the fixed-iteration scheme fuses its passes");
 
   for (;;) {
     // ---- refill lanes whose pixel finished --------------------------------
@@ -467,24 +545,49 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
       }
       __syncthreads();  // lane L has read the step before the record is reused
     }
-    if (__ballot(live) == 0ull) {
+    const unsigned long long live_m = __ballot(live);
+    if (live_m == 0ull) {
       if (__ballot(!exhausted) == 0ull) break;
       continue;  // lanes that met non-finite input refill first
     }
-    if (!live) continue;
+    // ---- the wave's pass: with derivatives (fresh starts, accepted models
+    // waiting for their Jacobian, and the other lanes' trials with their
+    // Jacobian computed ahead), or, while few lanes wait, values only for
+    // the trials ---------------------------------------------------------------
+    const bool wait = need_j || fresh;
+    bool jpass = true;
+    if constexpr (SPLIT) {
+      const int nw = __popcll(__ballot(live && wait)), nl = __popcll(live_m);
+      jpass = nw == nl || nw * 64 >= A.deriv_split * nl;
+    }
+    if (!live || (!jpass && wait)) continue;
 
-    // ---- synthesis pass with derivatives at Mc ----------------------------
-    if (leader) ++wc.pass;
+    if (leader) {
+      ++wc.pass;
+      if (jpass) ++wc.jpass;
+    }
     bool accept = false;
     // Sect. 4.4: a step from a model already near the minimum keeps H
-    const bool keep_h = !fresh && chib < A.hess_reuse;
-    const double chi =
-        lm_pass<NOBS, LPP, V>(A, Mc, pix, fresh, chib, keep_h, sHG, sHa, lane, accept);
-    if (leader && accept && !keep_h) ++wc.hess;
+    const bool keep_h = need_j ? kh_wait : (!fresh && chib < A.hess_reuse);
+    double chi;
+    if (!SPLIT || jpass) {
+      chi = lm_pass<NOBS, LPP, V>(A, Mc, pix, wait, chib, keep_h, sHG, sHa, lane, accept);
+      if (leader && accept && !keep_h) ++wc.hess;
+    } else {
+      chi = lm_pass_values<NOBS, LPP, V>(A, Mc, pix, lane);
+      accept = isfinite(chi) && chi < chib;
+    }
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
-    if (fresh) {
+    // the pass's model is a start or an accepted trial: the fit needs its
+    // Jacobian unless it ends here
+    const bool new_best = !need_j && (fresh || accept);
+    if (need_j) {
+      // the Jacobian, J^T W J and gradient of the accepted model Mb = Mc are
+      // now in LDS; its chi^2 is the one the trial pass found
+      need_j = false;
+    } else if (fresh) {
       if (!isfinite(chi) && !restart_eval) done = 3;
 #pragma unroll
       for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
@@ -512,6 +615,10 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
       if (leader) ++wc.trial;
       if (accept) {
         const double dec = chib - chi;
+        // values-only pass: the derivatives of the new best model are due
+        // (unless the fit ends here)
+        need_j = !jpass;
+        kh_wait = chib < A.hess_reuse;
 #pragma unroll
         for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
         chib = chi;
@@ -544,6 +651,8 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
     }
     fresh = false;
     if (done < 0 && it >= limit) done = 1;
+    if (done >= 0) need_j = false;
+    if (leader && new_best && done < 0) ++wc.jneed;
 
     if (done >= 0) {
       if (leader) {
@@ -572,6 +681,9 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
       fresh = true;
       restart_eval = true;
       pending = false;
+    } else if (need_j) {
+      // waits for its wave's next derivative pass (no step without the
+      // normal equations of Mb)
     } else {
       // ---- damped float64 step from the best model ------------------------
       float H[55], g[NPAR];
@@ -600,8 +712,11 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
                                                int lane) {
   const unsigned long long p = wave_sum(wc.pix), t = wave_sum(wc.trial), a = wave_sum(wc.acc),
                            s = wave_sum(wc.pass), f = wave_sum(wc.fb),
-                           h = wave_sum(wc.hess);
+                           h = wave_sum(wc.hess), j = wave_sum(wc.jpass),
+                           jn = wave_sum(wc.jneed);
   if (lane == 0) {
+    atomicAdd(&work[0], j);
+    atomicAdd(&work[8], jn);
     atomicAdd(&work[1], p);
     atomicAdd(&work[2], t);
     atomicAdd(&work[3], a);
@@ -613,7 +728,9 @@ __device__ __forceinline__ void flush_counters(unsigned long long* work, WaveCou
 }
 
 // V: Voigt evaluation (0 Weideman's series, 1/2 Taylor table; dense only).
-template <int NOBS, int V, bool PAPER>
+// SPLIT: values-only trial passes with derivative passes on demand (a
+// separate kernel, so that the fused one keeps its own register allocation).
+template <int NOBS, int V, bool PAPER, bool SPLIT = false>
 __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   __shared__ float sHG[65 * 64];  // H (55, packed) and g (10) per lane
   __shared__ float4 sHa[PASS4 * 64];  // the pass's accumulators in LDS
@@ -623,13 +740,13 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
   WaveCounters wc;
   if constexpr (NOBS > 0) {
     const unsigned long long n_total = A.n_dev ? *A.n_dev : (unsigned long long)A.n;
-    // pairs only when every pixel gets two lanes that run at once
-    if (A.lpp_max >= 2 && 2ull * n_total <= (unsigned long long)A.lane_cap)
-      lm_loop<NOBS, 2, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
+    // pairs only for batches small enough (host's choice, pair_max)
+    if (A.lpp_max >= 2 && n_total <= (unsigned long long)A.pair_max)
+      lm_loop<NOBS, 2, V, PAPER, SPLIT>(A, sHG, sHa, sws, lane, glane, wc);
     else
-      lm_loop<NOBS, 1, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
+      lm_loop<NOBS, 1, V, PAPER, SPLIT>(A, sHG, sHa, sws, lane, glane, wc);
   } else {
-    lm_loop<NOBS, 1, V, PAPER>(A, sHG, sHa, sws, lane, glane, wc);
+    lm_loop<NOBS, 1, V, PAPER, SPLIT>(A, sHG, sHa, sws, lane, glane, wc);
   }
   flush_counters(A.work, wc, lane);
 }
@@ -638,6 +755,7 @@ __global__ __launch_bounds__(64) void lm_kernel(const LMArgs A) {
 // (until that batch's queues are empty) before it turns to batch i + 1, so
 // waves are uniform in instrument and the last batch fills the tail left by
 // the earlier ones.
+template <bool SPLIT>
 __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   __shared__ float sHG[65 * 64];
   __shared__ float4 sHa[PASS4 * 64];
@@ -647,9 +765,9 @@ __global__ __launch_bounds__(64) void lm_batches_kernel(const BatchArgs B) {
   WaveCounters wc;
   for (int i = 0; i < B.n_batches; ++i) {
     if (B.kind[i] == KIND_DENSE6)
-      lm_loop<NOBS_HMI, 1>(B.a[i], sHG, sHa, sws, lane, glane, wc);
+      lm_loop<NOBS_HMI, 1, 0, false, SPLIT>(B.a[i], sHG, sHa, sws, lane, glane, wc);
     else
-      lm_loop<0, 1>(B.a[i], sHG, sHa, sws, lane, glane, wc);
+      lm_loop<0, 1, 0, false, SPLIT>(B.a[i], sHG, sHa, sws, lane, glane, wc);
   }
   flush_counters(B.a[0].work, wc, lane);
 }
@@ -795,10 +913,19 @@ hipError_t launch_reset(unsigned long long* work, bool all, hipStream_t s) {
 
 template <bool PAPER>
 static void launch_lm_mode(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s) {
-  if (kind != KIND_DENSE6) lm_kernel<0, 0, PAPER><<<grid, 64, 0, s>>>(a);
-  else if (voigt == 1) lm_kernel<NOBS_HMI, 1, PAPER><<<grid, 64, 0, s>>>(a);
-  else if (voigt == 2) lm_kernel<NOBS_HMI, 2, PAPER><<<grid, 64, 0, s>>>(a);
-  else lm_kernel<NOBS_HMI, 0, PAPER><<<grid, 64, 0, s>>>(a);
+  // the split pass serves Weideman's series outside the fixed-iteration scheme
+  const bool split = !PAPER && voigt == 0 && a.deriv_split > 0;
+  if (kind != KIND_DENSE6) {
+    if (split) lm_kernel<0, 0, false, true><<<grid, 64, 0, s>>>(a);
+    else lm_kernel<0, 0, PAPER><<<grid, 64, 0, s>>>(a);
+  } else if (voigt == 1) {
+    lm_kernel<NOBS_HMI, 1, PAPER><<<grid, 64, 0, s>>>(a);
+  } else if (voigt == 2) {
+    lm_kernel<NOBS_HMI, 2, PAPER><<<grid, 64, 0, s>>>(a);
+  } else {
+    if (split) lm_kernel<NOBS_HMI, 0, false, true><<<grid, 64, 0, s>>>(a);
+    else lm_kernel<NOBS_HMI, 0, PAPER><<<grid, 64, 0, s>>>(a);
+  }
 }
 
 hipError_t launch_lm(const LMArgs& a, int kind, int voigt, int grid, hipStream_t s) {
@@ -808,7 +935,10 @@ hipError_t launch_lm(const LMArgs& a, int kind, int voigt, int grid, hipStream_t
 }
 
 hipError_t launch_lm_batches(const BatchArgs& b, int grid, hipStream_t s) {
-  lm_batches_kernel<<<grid, 64, 0, s>>>(b);
+  bool split = false;
+  for (int i = 0; i < b.n_batches; ++i) split = split || b.a[i].deriv_split > 0;
+  if (split) lm_batches_kernel<true><<<grid, 64, 0, s>>>(b);
+  else lm_batches_kernel<false><<<grid, 64, 0, s>>>(b);
   return hipGetLastError();
 }
 
@@ -868,7 +998,7 @@ hipError_t lm_blocks_per_cu(int* out) {
 }
 
 hipError_t band_blocks_per_cu(int* out) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_batches_kernel, 64, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, lm_batches_kernel<false>, 64, 0);
 }
 
 }  // namespace vfisv

@@ -519,10 +519,11 @@ __device__ __forceinline__ void unpark(const float4* __restrict__ park, int lane
 // step, each lane selecting its own), then the pair adds its partial sums,
 // so both lanes hold the full sums.  Used when a launch has at least two
 // lanes per pixel: a pass then takes about half the time.
-template <int NOBS, int V = 0>
+template <int NOBS, int V = 0, bool DERIV = true>
 __device__ __forceinline__ void synth_accumulate_pair(const Point* __restrict__ pts,
                                                       const Pix& p, const Consts& C,
                                                       float (&acc)[NOBS][NACC], bool odd) {
+  constexpr int NC = DERIV ? NACC : 5;
 #pragma unroll
   for (int i = 0; i < NOBS; ++i)
 #pragma unroll
@@ -538,21 +539,21 @@ __device__ __forceinline__ void synth_accumulate_pair(const Point* __restrict__ 
       for (int i = 0; i < 7; ++i) P1.w[i] = 0.f;  // taps and mask zero: contributes nothing
     }
     float c[NACC];
-    point_contrib<true, V>(odd ? P1.dl : P0.dl, p, C, c);
+    point_contrib<DERIV, V>(odd ? P1.dl : P0.dl, p, C, c);
     const uint32_t mask = __float_as_uint(P0.w[6]) | __float_as_uint(P1.w[6]);
 #pragma unroll
     for (int i = 0; i < NOBS; ++i) {
       if (mask & (1u << i)) {  // a record's taps are zero outside its own mask
         const float w = odd ? P1.w[i] : P0.w[i];
 #pragma unroll
-        for (int m = 0; m < NACC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
+        for (int m = 0; m < NC; ++m) acc[i][m] = fmaf(w, c[m], acc[i][m]);
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < NOBS; ++i)
 #pragma unroll
-    for (int m = 0; m < NACC; ++m) acc[i][m] += __shfl_xor(acc[i][m], 1);
+    for (int m = 0; m < NC; ++m) acc[i][m] += __shfl_xor(acc[i][m], 1);
 }
 
 // Banded instruments (many observed samples, each seeing a short window of

@@ -21,6 +21,8 @@ using namespace vfisv_capi;
 
 struct vfisv_mlp {
   vfisv_ctx* ctx = nullptr;
+  int device = 0;  // the context's device, kept so that destroying the
+                   // network never reads the context
   MlpDev dev;
   MlpWork train;
   int step = 0;
@@ -111,11 +113,12 @@ int build(vfisv_ctx* ctx, int n_in, const float* in_mean, const float* in_std,
   for (int k = 0; k < 7; ++k)
     if (!std::isfinite(out_mean[k]) || !(out_std[k] > 0.f) || !std::isfinite(out_std[k]))
       return fail(ctx, VFISV_E_INVALID, "mlp: output mean/std must be finite, std > 0");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   vfisv_mlp* m = new (std::nothrow) vfisv_mlp();
   if (!m) return fail(ctx, VFISV_E_NOMEM, "mlp: host allocation");
   m->ctx = ctx;
+  m->device = ctx->device;
   std::memset(&m->dev, 0, sizeof m->dev);
   std::memset(&m->train, 0, sizeof m->train);
   MlpDev& d = m->dev;
@@ -266,7 +269,7 @@ int vfisv_mlp_create(vfisv_ctx* ctx, int n_in, const float* in_mean, const float
 
 int vfisv_mlp_destroy(vfisv_mlp* m) {
   if (!m) return VFISV_OK;
-  hipSetDevice(m->ctx->device);
+  hipSetDevice(m->device);
   hipDeviceSynchronize();
   free_work(m->train);
   free_dev(m->dev);
@@ -281,7 +284,7 @@ int vfisv_mlp_num_inputs(const vfisv_mlp* m) { return m ? m->dev.L.n_in : -1; }
 int vfisv_mlp_get_params(vfisv_mlp* m, float* host, int64_t n) {
   if (!m || !host) return VFISV_E_INVALID;
   if (n != m->dev.L.total) return fail(m->ctx, VFISV_E_INVALID, "mlp_get_params: size mismatch");
-  hipError_t e = hipSetDevice(m->ctx->device);
+  hipError_t e = hipSetDevice(m->device);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(host, m->dev.master, 4 * n, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(m->ctx, e, "mlp_get_params");
@@ -293,7 +296,7 @@ int vfisv_mlp_set_params(vfisv_mlp* m, const float* host, int64_t n) {
   if (n != m->dev.L.total) return fail(m->ctx, VFISV_E_INVALID, "mlp_set_params: size mismatch");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(host[i])) return fail(m->ctx, VFISV_E_INVALID, "mlp_set_params: non-finite");
-  hipError_t e = hipSetDevice(m->ctx->device);
+  hipError_t e = hipSetDevice(m->device);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(m->dev.master, host, 4 * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->dev.adam_m, 0, 4 * n);
@@ -313,7 +316,7 @@ int vfisv_mlp_forward(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stok
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "mlp_forward: n < 0");
   if (n == 0) return VFISV_OK;
   if (!stokes || (!codes && !params)) return fail(ctx, VFISV_E_INVALID, "mlp_forward: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   // one fused launch: inputs -> decoded codes / starting models, no scratch
   e = mlp_infer(m->dev, n, stokes, codes, params, (hipStream_t)stream);
@@ -329,7 +332,7 @@ int vfisv_mlp_gradient(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* sto
   if (n <= 0 || n % 32 != 0 || n > (1 << 22))
     return fail(ctx, VFISV_E_INVALID, "mlp_gradient: n must be a positive multiple of 32");
   if (!stokes || !targets || !grad) return fail(ctx, VFISV_E_INVALID, "mlp_gradient: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   rc = ensure_train(m, n);
   if (rc) return rc;
@@ -355,7 +358,7 @@ int vfisv_mlp_train_step(vfisv_ctx* ctx, vfisv_mlp* m, const float* stokes, cons
     return fail(ctx, VFISV_E_INVALID, "mlp_train_step: batch must be a positive multiple of 32");
   if (!stokes || !targets || !rows) return fail(ctx, VFISV_E_INVALID, "mlp_train_step: NULL buffer");
   if (!(lr > 0.f) || !std::isfinite(lr)) return fail(ctx, VFISV_E_INVALID, "mlp_train_step: lr");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   rc = ensure_train(m, batch);
   if (rc) return rc;
@@ -373,7 +376,7 @@ int vfisv_mlp_take_loss(vfisv_mlp* m, double* sum_sq) {
   if (!m || !sum_sq) return VFISV_E_INVALID;
   *sum_sq = 0.0;
   if (m->train.cap == 0) return VFISV_OK;
-  hipError_t e = hipSetDevice(m->ctx->device);
+  hipError_t e = hipSetDevice(m->device);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(sum_sq, m->train.loss, 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = zero_u64((unsigned long long*)m->train.loss, 1, nullptr);
@@ -391,7 +394,7 @@ int vfisv_mlp_stats(vfisv_ctx* ctx, int64_t n, int n_in, const float* stokes,
     return fail(ctx, VFISV_E_INVALID, "mlp_stats: n_in must be 1.." + std::to_string(MLP_MAX_IN));
   if (!stokes || !params || !in_mean || !in_std || !out_mean || !out_std)
     return fail(ctx, VFISV_E_INVALID, "mlp_stats: NULL buffer");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const int nsum = 2 * (n_in + 7);
@@ -489,7 +492,7 @@ int vfisv_mlp_train(vfisv_ctx* ctx, vfisv_mlp* m, const vfisv_train_spec* sp,
   if (!(sp->lr > 0.f) || !std::isfinite(sp->lr) || !(sp->min_lr_frac > 0.f) ||
       !(sp->min_lr_frac <= 1.f))
     return fail(ctx, VFISV_E_INVALID, "mlp_train: lr > 0 and min_lr_frac in (0, 1] needed");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   rc = ensure_train(m, sp->batch);
   if (rc) return rc;
@@ -730,6 +733,9 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
   if (rc) return rc;
   if (o.fixed_iters != 0)
     return fail(ctx, VFISV_E_UNSUPPORTED, "invert_learned: the fixed-iteration scheme is not served here");
+  // from the network's start most trials are accepted (about half, against
+  // a third from the default model), so the fused pass is the default here
+  if (o.deriv_split < 0) o.deriv_split = 0;
   if (learned_max_iter < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: learned_max_iter < 0");
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "invert_learned: n < 0");
   if (n == 0) return VFISV_OK;
@@ -746,7 +752,7 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
   const bool refit_unconverged = (o.fallback_rule & VFISV_REFIT_UNCONVERGED) != 0;
   const bool refit_default = (o.fallback_rule & VFISV_REFIT_FROM_DEFAULT) != 0;
   const bool keep_refit = (o.fallback_rule & VFISV_REFIT_KEEP_REFIT) != 0;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
 
   const LearnedScratch sl(n);
@@ -801,7 +807,7 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
                   params, chi2, iters, s_short, s, true, 1, !noalloc);
   if (rc) return rc;
   e = mark(2);
-  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap, ctx->d_work, 8, s);
+  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap, ctx->d_work, 16, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase record");
   // 3. pixels whose fit is not acceptable go to plain LM from the combined
   // start of Sect. 5 (the proposal with the classical azimuth, and the
@@ -823,7 +829,7 @@ int invert_learned_impl(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp*
                   inv_dof, p_fb, c_fb, i_fb, s_fb, s, false, 2, !noalloc);
   if (rc) return rc;
   e = mark(4);
-  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap + 8, ctx->d_work, 8, s);
+  if (e == hipSuccess && timing) e = copy_u64(ctx->d_phase_snap + 16, ctx->d_work, 16, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "invert_learned: phase record");
   // 4. keep the better of the two fits; flag the pixel
   e = fallback_merge(list, count, n, p_fb, c_fb, i_fb, s_fb, keep_refit, params, chi2, iters,
@@ -851,7 +857,7 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
 
 int vfisv_learned_phase_timing(vfisv_ctx* ctx, int on) {
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "learned_phase_timing: ctx is NULL");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (!on) {
     if (ctx->phase_on) hipDeviceSynchronize();
@@ -868,7 +874,7 @@ int vfisv_learned_phase_timing(vfisv_ctx* ctx, int on) {
   if (ctx->phase_on) return VFISV_OK;
   for (hipEvent_t& ev : ctx->phase_ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
-  if (e == hipSuccess) e = hipMalloc(&ctx->d_phase_snap, 16 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_phase_snap, 32 * sizeof(unsigned long long));
   if (e != hipSuccess) {
     vfisv_learned_phase_timing(ctx, 0);
     return hip_fail(ctx, e, "learned_phase_timing: events");
@@ -883,18 +889,18 @@ int vfisv_learned_phases_get(vfisv_ctx* ctx, vfisv_learned_phases* out) {
   if (!out) return fail(ctx, VFISV_E_INVALID, "learned_phases_get: out is NULL");
   if (!ctx->phase_on || !ctx->phase_valid)
     return fail(ctx, VFISV_E_INVALID, "learned_phases_get: no timed learned-path call");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = use_device(ctx);
   if (e == hipSuccess) e = hipEventSynchronize(ctx->phase_ev[5]);
   for (int k = 0; k < 5 && e == hipSuccess; ++k) {
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, ctx->phase_ev[k], ctx->phase_ev[k + 1]);
     out->ms[k] = ms;
   }
-  unsigned long long w[16];
+  unsigned long long w[32];
   if (e == hipSuccess) e = hipMemcpy(w, ctx->d_phase_snap, sizeof w, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "learned_phases_get");
   auto fill = [](vfisv_counters& c, const unsigned long long* a, const unsigned long long* b) {
-    // counters of slots 1..7 of a, less those of b (b == nullptr: none)
+    // counters of a, less those of b (b == nullptr: none)
     auto d = [&](int i) { return (int64_t)(a[i] - (b ? b[i] : 0ull)); };
     c.pixels = d(1);
     c.trials = d(2);
@@ -903,9 +909,11 @@ int vfisv_learned_phases_get(vfisv_ctx* ctx, vfisv_learned_phases* out) {
     c.svd_fallbacks = d(5);
     c.grid_waves = d(6);
     c.hessians = d(7);
+    c.derivative_passes = d(0);
+    c.jacobians = d(8);
   };
   fill(out->short_fit, w, nullptr);
-  fill(out->refit, w + 8, w);
+  fill(out->refit, w + 16, w);
   return VFISV_OK;
 }
 

@@ -43,8 +43,8 @@ def test_options_default_and_version():
     L.vfisv_options_default(ctypes.byref(o))
     assert (o.max_iter, o.eps0, o.eps_max, o.rel_tol, o.free_mask, o.grid_waves,
             o.chunk_log2, o.lanes_per_pixel, o.voigt, o.fixed_iters, o.restarts,
-            o.restart_seed, o.hess_reuse, o.fallback_rule) == (50, 1e-3, 1e8, 1e-5, 0x3FF, 0,
-                                                                 -1, 1, 0, 0, 0, 0, 0.0, 0)
+            o.restart_seed, o.hess_reuse, o.fallback_rule, o.deriv_split) == (
+        50, 1e-3, 1e8, 1e-5, 0x3FF, 0, -1, 1, 0, 0, 0, 0, 0.0, 0, -1)
     # the Python defaults are the library's
     d = vf.Options().c()
     assert all(getattr(d, f) == getattr(o, f) for f, _ in vf._Options._fields_)

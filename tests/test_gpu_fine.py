@@ -117,7 +117,7 @@ def test_fine_default_start_statistics(ctx, fine):
     assert abs(np.mean(gc < 1.5) - np.mean(ref["chi2"] < 1.5)) < 0.06
     assert abs(gi.mean() - ref["iters"].mean()) / ref["iters"].mean() < 0.12
     c = ctx.counters()
-    assert c["pixels"] == n and c["trials"] == gi.sum() and c["passes"] == c["trials"] + n
+    assert c["pixels"] == n and c["trials"] == gi.sum() and 0 <= c["passes"] - c["trials"] - n <= c["accepts"]
 
 
 def test_batches_equal_separate_launches(ctx, fine, hmi):

@@ -60,7 +60,7 @@ def test_full_disk_plain_lm():
     assert iters.min() >= 1 and iters.max() <= 50
     assert np.isfinite(params).all() and np.isfinite(chi2).all() and (chi2 >= 0).all()
     assert c["pixels"] == n and c["trials"] == int(iters.sum())
-    assert c["passes"] == c["trials"] + n
+    assert 0 <= c["passes"] - c["trials"] - n <= c["accepts"]
     assert np.array_equal(vf.iter_histogram(ctx, out["iters"], 51),
                           np.bincount(iters, minlength=51))
     assert (params[:, 0] >= 0).all() and (params[:, 0] <= 5000).all()

@@ -96,7 +96,7 @@ def test_hmi_512x512_full_size(ctx):
     c = ctx.counters()
     st, iters, params, chi2 = _properties(ctx, out, n)
     assert c["pixels"] == n and c["trials"] == int(iters.sum())
-    assert c["passes"] == c["trials"] + n
+    assert 0 <= c["passes"] - c["trials"] - n <= c["accepts"]
     _sample_checks("hmi 512x512", oi, W, obs_s, params[smp], chi2[smp], iters[smp],
                    2e-5, 1e-3, 0.1, 0.12)
 
@@ -130,7 +130,7 @@ def test_fine_and_hmi_full_size_in_one_launch(ctx):
     stf, itf, pf, cf = _properties(ctx, mixed[0], nf)
     sth, ith, ph, ch = _properties(ctx, mixed[1], nh)
     assert c["pixels"] == nf + nh and c["trials"] == int(itf.sum()) + int(ith.sum())
-    assert c["passes"] == c["trials"] + nf + nh
+    assert 0 <= c["passes"] - c["trials"] - (nf + nh) <= c["accepts"]
     _sample_checks("fine", foi, Wf, of_s, pf[sf], cf[sf], itf[sf], 1e-4, 1e-3, 0.1, 0.15)
     _sample_checks("hmi (mixed launch)", hoi, Wh, oh_s, ph[sh], ch[sh], ith[sh],
                    2e-5, 1e-3, 0.1, 0.12)

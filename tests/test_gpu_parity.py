@@ -337,12 +337,13 @@ def test_scheduling_does_not_change_results(ctx, hmi):
     ref = {k: v.cpu().numpy() for k, v in ref.items()}
     c = ctx.counters()
     assert c["pixels"] == 3000 and c["trials"] == ref["iters"].sum()
-    assert c["passes"] == c["trials"] + 3000
-    for gw, cl in ((1, 8), (3, 0), (17, 3), (500, 8), (0, 20), (0, 6)):
-        out = vf.invert(ctx, inst, o, W, opts=vf.Options(grid_waves=gw, chunk_log2=cl))
+    assert 0 <= c["passes"] - c["trials"] - 3000 <= c["accepts"]
+    for gw, cl, ds in ((1, 8, 0), (3, 0, 8), (17, 3, 64), (500, 8, 1), (0, 20, 32), (0, 6, -1)):
+        out = vf.invert(ctx, inst, o, W, opts=vf.Options(grid_waves=gw, chunk_log2=cl,
+                                                         deriv_split=ds))
         c = ctx.counters()
         assert c["grid_waves"] == min(gw or 10 ** 9, (3000 + 63) // 64)
-        assert c["pixels"] == 3000 and c["passes"] == c["trials"] + 3000
+        assert c["pixels"] == 3000 and 0 <= c["passes"] - c["trials"] - 3000 <= c["accepts"]
         for k in ref:
             assert np.array_equal(out[k].cpu().numpy(), ref[k]), (gw, cl, k)
 
@@ -405,7 +406,7 @@ def test_lane_pairs_follow_the_oracle(ctx, hmi):
     out = vf.invert(ctx, inst, o, Wd, opts=vf.Options(lanes_per_pixel=2))
     c = ctx.counters()
     gc, gi = out["chi2"].cpu().numpy(), out["iters"].cpu().numpy()
-    assert c["pixels"] == n and c["trials"] == gi.sum() and c["passes"] == c["trials"] + n
+    assert c["pixels"] == n and c["trials"] == gi.sum() and 0 <= c["passes"] - c["trials"] - n <= c["accepts"]
     assert np.isin(out["status"].cpu().numpy(), (0, 1, 2)).all()
     ref = oracle.invert(oi, obs, W)
     a, b = np.median(gc), np.median(ref["chi2"])
@@ -473,7 +474,7 @@ def test_fixed_iterations_with_restarts_follow_the_oracle(ctx, hmi):
         np.testing.assert_array_equal(out["status"].cpu().numpy(), ref["status"])
         np.testing.assert_array_equal(out["iters"].cpu().numpy(), ref["iters"])
         c = ctx.counters()
-        assert c["trials"] == ref["iters"].sum() and c["passes"] == c["trials"] + n
+        assert c["trials"] == ref["iters"].sum() and 0 <= c["passes"] - c["trials"] - n <= c["accepts"]
     # without restarts: LM without its convergence exit, bit for bit
     a = vf.invert(ctx, inst, o, Wd, opts=vf.Options(fixed_iters=30))
     b = vf.invert(ctx, inst, o, Wd, opts=vf.Options(max_iter=30, rel_tol=0.0))
