@@ -24,67 +24,126 @@ namespace vfisv {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ __forceinline__ float gelu(float z) {
-  return 0.5f * z * (1.f + erff(z * 0.70710678118654752f));
+// GELU(z) = z Phi(z) with the exact (erf) normal CDF Phi, evaluated
+// branch-free from erfc(|z| / sqrt 2) by the rational-exponential
+// approximation of Abramowitz & Stegun 7.1.26 (Hastings):
+//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+//   t = 1 / (1 + p x),
+// absolute error below 1.5e-7 -- under a thousandth of the bfloat16 step the
+// activations are rounded to.  Phi(z) = 1 - erfc(x) / 2 for z >= 0 and
+// erfc(x) / 2 for z < 0 (so the negative tail keeps its relative accuracy);
+// the halves are folded into the coefficients.  The device library's erff
+// branches on |x| (divergent lanes, two polynomials) and took twice the
+// instructions of the network's epilogues.
+struct PhiPdf {
+  float Phi;  // Phi(z)
+  float e;    // exp(-z^2 / 2)
+};
+__device__ __forceinline__ PhiPdf phi_pdf(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = frcp(fmaf(0.3275911f, x, 1.f));
+  float p = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
+  p = fmaf(t, p, 0.5f * 1.421413741f);
+  p = fmaf(t, p, 0.5f * -0.284496736f);
+  p = fmaf(t, p, 0.5f * 0.254829592f);
+  // exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2)
+  const float e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);
+  const float h = t * p * e;  // erfc(x) / 2
+  return PhiPdf{z >= 0.f ? 1.f - h : h, e};
 }
+__device__ __forceinline__ float gelu(float z) { return z * phi_pdf(z).Phi; }
+// d/dz [z Phi(z)] = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  const PhiPdf f = phi_pdf(z);
+  return fmaf(z * 0.39894228040143268f, f.e, f.Phi);
 }
 
 // ---- GEMM ------------------------------------------------------------------
-// One wave computes a 64 x (16 NB) tile of C over the Kd range
-// [z * k_chunk, min((z + 1) * k_chunk, Kd)).  Kd and k_chunk are multiples
-// of 32.  MFMA 16x16x32 lane layout: lane l feeds A row (l & 15) and B
-// column (l & 15) with k = 8 (l >> 4) .. +7, and receives C rows
-// 4 (l >> 4) .. +3 of column (l & 15).
-template <int NB, class Epi>
+// One wave computes a 32 x 32 tile of C (2 x 2 MFMA tiles of 16 x 16) over
+// the Kd range [z * k_chunk, min((z + 1) * k_chunk, Kd)); Kd and k_chunk are
+// multiples of 32.  The fragments of KC k-steps are loaded before the first
+// MFMA of the group, so that one memory latency serves KC k-steps (the
+// 256-deep products of the hidden layers take one group).  MFMA 16x16x32
+// lane layout: lane l feeds A row (l & 15) and B column (l & 15) with
+// k = 8 (l >> 4) .. +7, and receives C rows 4 (l >> 4) .. +3 of column
+// (l & 15); the epilogue gets those four rows at once.
+constexpr int GT = 2;   // 16 x 16 MFMA tiles per wave along each of M and N
+constexpr int GKC = 8;  // k-steps loaded per group
+template <class Epi>
 __global__ __launch_bounds__(64) void gemm_abt(const bf16* __restrict__ A, int64_t lda,
                                                const bf16* __restrict__ Bt, int64_t ldb,
                                                int64_t M, int N, int64_t Kd, int64_t k_chunk,
                                                Epi epi) {
   const int l = threadIdx.x;
-  const int64_t m0 = (int64_t)blockIdx.x * 64;
-  const int n0 = blockIdx.y * 16 * NB;
+  const int64_t m0 = (int64_t)blockIdx.x * 16 * GT;
+  const int n0 = blockIdx.y * 16 * GT;
   const int64_t kbeg = (int64_t)blockIdx.z * k_chunk;
   const int64_t kend = kbeg + k_chunk < Kd ? kbeg + k_chunk : Kd;
   const int lr = l & 15, lk = (l >> 4) * 8;
-  f32x4 acc[4][NB];
+  f32x4 acc[GT][GT];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < GT; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < GT; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   bf16x8 zero;
 #pragma unroll
   for (int i = 0; i < 8; ++i) zero[i] = (bf16)0.f;
-  for (int64_t k = kbeg; k < kend; k += 32) {
-    bf16x8 a[4], b[NB];
+  const bf16* arow[GT];
+  const bf16* bcol[GT];
+  bool aok[GT], bok[GT];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int64_t row = m0 + rb * 16 + lr;
-      a[rb] = row < M ? *(const bf16x8*)(A + row * lda + k + lk) : zero;
+  for (int t = 0; t < GT; ++t) {
+    const int64_t row = m0 + t * 16 + lr;
+    const int col = n0 + t * 16 + lr;
+    aok[t] = row < M;
+    bok[t] = col < N;
+    arow[t] = A + (aok[t] ? row : 0) * lda + lk;
+    bcol[t] = Bt + (int64_t)(bok[t] ? col : 0) * ldb + lk;
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 32 * GKC) {
+    bf16x8 a[GKC][GT], b[GKC][GT];
+#pragma unroll
+    for (int kc = 0; kc < GKC; ++kc) {
+      const int64_t k = k0 + 32 * kc;
+      const bool kin = k < kend;
+#pragma unroll
+      for (int t = 0; t < GT; ++t) {
+        a[kc][t] = kin && aok[t] ? *(const bf16x8*)(arow[t] + k) : zero;
+        b[kc][t] = kin && bok[t] ? *(const bf16x8*)(bcol[t] + k) : zero;
+      }
     }
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
-      const int col = n0 + cb * 16 + lr;
-      b[cb] = col < N ? *(const bf16x8*)(Bt + (int64_t)col * ldb + k + lk) : zero;
+    for (int kc = 0; kc < GKC; ++kc) {
+      if (k0 + 32 * kc >= kend) break;  // wave-uniform
+#pragma unroll
+      for (int rb = 0; rb < GT; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < GT; ++cb)
+          acc[rb][cb] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc][rb], b[kc][cb], acc[rb][cb], 0, 0, 0);
     }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
   }
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < GT; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t row = m0 + rb * 16 + (l >> 4) * 4 + j;
-        const int col = n0 + cb * 16 + lr;
-        if (row < M && col < N) epi(row, col, acc[rb][cb][j], blockIdx.z);
-      }
+    for (int cb = 0; cb < GT; ++cb) {
+      const int64_t row0 = m0 + rb * 16 + (l >> 4) * 4;
+      const int col = n0 + cb * 16 + lr;
+      if (row0 < M && col < N) epi(row0, col, acc[rb][cb], blockIdx.z);
+    }
+}
+
+// Epilogues receive the four rows row0 .. row0 + 3 (M is a multiple of 32,
+// so all four exist) of one column.  Transposed copies store the four
+// consecutive values with one 8-byte write.
+__device__ __forceinline__ void store4_bf16(bf16* p, float v0, float v1, float v2, float v3) {
+  typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+  bf16x4 v;
+  v[0] = (bf16)v0;
+  v[1] = (bf16)v1;
+  v[2] = (bf16)v2;
+  v[3] = (bf16)v3;
+  *(bf16x4*)p = v;
 }
 
 struct EpiHidden {  // z = acc + b; y = gelu(z)
@@ -93,20 +152,25 @@ struct EpiHidden {  // z = acc + b; y = gelu(z)
   bf16* Yt;
   float* Z;
   int64_t ld, ldt;
-  __device__ void operator()(int64_t row, int col, float acc, int) const {
-    const float z = acc + bias[col];
-    if (Z) Z[row * ld + col] = z;
-    const bf16 y = (bf16)gelu(z);
-    Y[row * ld + col] = y;
-    if (Yt) Yt[(int64_t)col * ldt + row] = y;
+  __device__ void operator()(int64_t row0, int col, f32x4 acc, int) const {
+    float y[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = acc[j] + bias[col];
+      if (Z) Z[(row0 + j) * ld + col] = z;
+      y[j] = gelu(z);
+      Y[(row0 + j) * ld + col] = (bf16)y[j];
+    }
+    if (Yt) store4_bf16(Yt + (int64_t)col * ldt + row0, y[0], y[1], y[2], y[3]);
   }
 };
 
 struct EpiOut {  // linear output layer
   const float* bias;
   float* Y4;
-  __device__ void operator()(int64_t row, int col, float acc, int) const {
-    Y4[row * MLP_OUT + col] = acc + bias[col];
+  __device__ void operator()(int64_t row0, int col, f32x4 acc, int) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Y4[(row0 + j) * MLP_OUT + col] = acc[j] + bias[col];
   }
 };
 
@@ -115,10 +179,14 @@ struct EpiBwdX {  // dz_prev = (dZ . W^T) * gelu'(z_prev)
   bf16* dZ;
   bf16* dZt;
   int64_t ld, ldt;
-  __device__ void operator()(int64_t row, int col, float acc, int) const {
-    const bf16 d = (bf16)(acc * gelu_grad(Zp[row * ld + col]));
-    dZ[row * ld + col] = d;
-    dZt[(int64_t)col * ldt + row] = d;
+  __device__ void operator()(int64_t row0, int col, f32x4 acc, int) const {
+    float d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      d[j] = acc[j] * gelu_grad(Zp[(row0 + j) * ld + col]);
+      dZ[(row0 + j) * ld + col] = (bf16)d[j];
+    }
+    store4_bf16(dZt + (int64_t)col * ldt + row0, d[0], d[1], d[2], d[3]);
   }
 };
 
@@ -126,17 +194,19 @@ struct EpiDW {  // partial weight gradient, [split][out][in]
   float* part;
   int64_t split_stride;
   int ldo;
-  __device__ void operator()(int64_t row, int col, float acc, int z) const {
-    part[(int64_t)z * split_stride + row * ldo + col] = acc;
+  __device__ void operator()(int64_t row0, int col, f32x4 acc, int z) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[(int64_t)z * split_stride + (row0 + j) * ldo + col] = acc[j];
   }
 };
 
-template <int NB, class Epi>
+template <class Epi>
 static hipError_t gemm(const bf16* A, int64_t lda, const bf16* Bt, int64_t ldb, int64_t M, int N,
                        int64_t Kd, int splits, const Epi& e, hipStream_t s) {
   const int64_t chunk = ((Kd + splits - 1) / splits + 31) / 32 * 32;
-  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 16 * NB - 1) / (16 * NB)), (unsigned)splits);
-  gemm_abt<NB, Epi><<<grid, 64, 0, s>>>(A, lda, Bt, ldb, M, N, Kd, chunk, e);
+  dim3 grid((unsigned)((M + 16 * GT - 1) / (16 * GT)), (unsigned)((N + 16 * GT - 1) / (16 * GT)),
+            (unsigned)splits);
+  gemm_abt<Epi><<<grid, 64, 0, s>>>(A, lda, Bt, ldb, M, N, Kd, chunk, e);
   return hipGetLastError();
 }
 
@@ -320,6 +390,11 @@ __global__ void decode_kernel(const float* __restrict__ Y4, int64_t M,
 // the results equal those of the layer-by-layer path.
 constexpr int FT = 64;
 constexpr int LDH = MLP_H + 8;
+// waves per inference workgroup; each owns IW_COLS of a hidden layer's 256
+// columns for the tile's 64 rows (eight waves keep the registers per wave
+// low enough for four waves per SIMD, which hide the weight loads' latency)
+constexpr int IW = 8;
+constexpr int IW_CB = MLP_H / (16 * IW);  // 16-column MFMA tiles per wave
 
 struct MlpInferArgs {
   const float* stokes;
@@ -341,46 +416,72 @@ __device__ __forceinline__ void fused_hidden(bf16* buf, int ldin, int Kd, const 
   const bf16* in = buf;
   const int K = KS > 0 ? KS : Kd;
   const int lr = l & 15, lk = (l >> 4) * 8;
-  f32x4 acc[4][4];
+  f32x4 acc[4][IW_CB];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll(KS > 0 ? KS / 32 : 2)
-  for (int k = 0; k < K; k += 32) {
-    bf16x8 a[4], b[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      b[cb] = *(const bf16x8*)(W + (int64_t)(wave * 64 + cb * 16 + lr) * K + k + lk);
+    for (int cb = 0; cb < IW_CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16* wrow = W + (int64_t)(wave * 16 * IW_CB + lr) * K + lk;
+  auto mfma_step = [&](const bf16x8 (&b)[IW_CB], int k) {
+    bf16x8 a[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) a[rb] = *(const bf16x8*)(in + (rb * 16 + lr) * ldin + k + lk);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < IW_CB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  };
+  if constexpr (KS > 0) {
+    // the weights (read from L2 by every row tile) two k-steps ahead of
+    // their MFMAs
+    constexpr int NK = KS / 32, PF = 2;
+    bf16x8 b[NK][IW_CB];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      if (s == 0) {
+#pragma unroll
+        for (int q = 0; q < PF && q < NK; ++q)
+#pragma unroll
+          for (int cb = 0; cb < IW_CB; ++cb)
+            b[q][cb] = *(const bf16x8*)(wrow + (int64_t)cb * 16 * K + 32 * q);
+      }
+      if (s + PF < NK) {
+#pragma unroll
+        for (int cb = 0; cb < IW_CB; ++cb)
+          b[s + PF][cb] = *(const bf16x8*)(wrow + (int64_t)cb * 16 * K + 32 * (s + PF));
+      }
+      mfma_step(b[s], 32 * s);
+    }
+  } else {
+    for (int k = 0; k < K; k += 32) {
+      bf16x8 b[IW_CB];
+#pragma unroll
+      for (int cb = 0; cb < IW_CB; ++cb) b[cb] = *(const bf16x8*)(wrow + (int64_t)cb * 16 * K + k);
+      mfma_step(b, k);
+    }
   }
   __syncthreads();  // every wave has read the layer's inputs
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < IW_CB; ++cb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = rb * 16 + (l >> 4) * 4 + j;
-        const int col = wave * 64 + cb * 16 + lr;
+        const int col = wave * 16 * IW_CB + cb * 16 + lr;
         buf[row * LDH + col] = (bf16)gelu(acc[rb][cb][j] + bias[col]);
       }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void mlp_infer_kernel(const MlpInferArgs a) {
+__global__ __launch_bounds__(IW * 64) void mlp_infer_kernel(const MlpInferArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int ldx = a.K0 + 8;
   bf16* buf = (bf16*)smem;  // [FT][max(K0 + 8, LDH)]
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
   const int64_t row0 = (int64_t)blockIdx.x * FT;
-  for (int idx = tid; idx < FT * a.K0; idx += 256) {
+  for (int idx = tid; idx < FT * a.K0; idx += IW * 64) {
     const int r = idx / a.K0, k = idx - r * a.K0;
     const int64_t row = row0 + r;
     float x = 0.f;
@@ -392,27 +493,32 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const MlpInferArgs a) {
   fused_hidden<MLP_H>(buf, LDH, MLP_H, a.Wt[1], a.bias[1], wave, l);
   fused_hidden<MLP_H>(buf, LDH, MLP_H, a.Wt[2], a.bias[2], wave, l);
   float* y4 = (float*)smem;  // [FT][MLP_OUT + 1], over the tile once it is read
-  {  // output layer: rows [16 wave, 16 wave + 16), 32 columns
+  {  // output layer: waves 0-3 take rows [16 wave, 16 wave + 16), 32 columns
     const int lr = l & 15, lk = (l >> 4) * 8;
+    const bool mine = wave < FT / 16;  // wave-uniform
     f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    if (mine) {
 #pragma unroll
-    for (int k = 0; k < MLP_H; k += 32) {
-      const bf16x8 av = *(const bf16x8*)(buf + (wave * 16 + lr) * LDH + k + lk);
+      for (int k = 0; k < MLP_H; k += 32) {
+        const bf16x8 av = *(const bf16x8*)(buf + (wave * 16 + lr) * LDH + k + lk);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const bf16x8 bv = *(const bf16x8*)(a.Wt[3] + (int64_t)(cb * 16 + lr) * MLP_H + k + lk);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < 2; ++cb) {
+          const bf16x8 bv = *(const bf16x8*)(a.Wt[3] + (int64_t)(cb * 16 + lr) * MLP_H + k + lk);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[cb], 0, 0, 0);
+        }
       }
     }
     __syncthreads();  // the tile is read; its space takes the outputs
+    if (mine) {
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = wave * 16 + (l >> 4) * 4 + j;
-        const int col = cb * 16 + lr;
-        y4[row * (MLP_OUT + 1) + col] = acc[cb][j] + a.bias[3][col];
-      }
+        for (int j = 0; j < 4; ++j) {
+          const int row = wave * 16 + (l >> 4) * 4 + j;
+          const int col = cb * 16 + lr;
+          y4[row * (MLP_OUT + 1) + col] = acc[cb][j] + a.bias[3][col];
+        }
+    }
   }
   __syncthreads();
   if (tid < FT) {
@@ -459,7 +565,7 @@ hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* c
       (const void*)mlp_infer_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MLP_LDS_MAX);
   if (attr != hipSuccess) return attr;
   const size_t lds = mlp_infer_lds_bytes(L.K0);
-  mlp_infer_kernel<<<(unsigned)((M + FT - 1) / FT), 256, lds, s>>>(a);
+  mlp_infer_kernel<<<(unsigned)((M + FT - 1) / FT), IW * 64, lds, s>>>(a);
   return hipGetLastError();
 }
 
@@ -550,13 +656,13 @@ hipError_t mlp_forward(const MlpDev& net, MlpWork& w, int64_t M, const float* st
   for (int l = 0; l < 3; ++l) {
     EpiHidden ep{net.master + L.ob[l], w.Y[l], train ? w.Yt[l] : nullptr,
                  train ? w.Z[l] : nullptr, MLP_H, w.cap};
-    e = gemm<4>(X, ldx, net.Wt[l], L.in_dim[l], M, MLP_H, L.in_dim[l], 1, ep, s);
+    e = gemm(X, ldx, net.Wt[l], L.in_dim[l], M, MLP_H, L.in_dim[l], 1, ep, s);
     if (e != hipSuccess) return e;
     X = w.Y[l];
     ldx = MLP_H;
   }
   EpiOut eo{net.master + L.ob[3], w.Y4};
-  return gemm<2>(X, ldx, net.Wt[3], MLP_H, M, MLP_OUT, MLP_H, 1, eo, s);
+  return gemm(X, ldx, net.Wt[3], MLP_H, M, MLP_OUT, MLP_H, 1, eo, s);
 }
 
 hipError_t mlp_decode(const MlpDev& net, const float* Y4, int64_t M, float* codes, float* params,
@@ -706,14 +812,14 @@ hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* t
     // weight gradient: dWt[out][in] = dZ^T[out][B] . X^T[in][B]^T
     const bf16* Xt = l == 0 ? w.X0t : w.Yt[l - 1];
     EpiDW ed{w.dW + off, stride, in};
-    e = gemm<4>(w.dZt[l], w.cap, Xt, w.cap, out, in, M, MLP_SPLITK, ed, s);
+    e = gemm(w.dZt[l], w.cap, Xt, w.cap, out, in, M, MLP_SPLITK, ed, s);
     if (e != hipSuccess) return e;
     bias_grad_kernel<<<out, 256, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (l > 0) {  // input gradient through W and the previous GELU
       EpiBwdX eb{w.Z[l - 1], w.dZ[l - 1], w.dZt[l - 1], MLP_H, w.cap};
-      e = gemm<4>(w.dZ[l], out, net.Wk[l], out, M, in, out, 1, eb, s);
+      e = gemm(w.dZ[l], out, net.Wk[l], out, M, in, out, 1, eb, s);
       if (e != hipSuccess) return e;
     }
   }
