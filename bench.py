@@ -124,6 +124,12 @@ def main():
     ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--net", default="",
+                    help="network file: loaded when it exists (no training), else the trained "
+                         "network is saved there (for profiling runs of the learned step)")
+    ap.add_argument("--profile-learned", action="store_true",
+                    help="run only W + K eager learned steps and print their phase times; with "
+                         "--net, no training: the launches rocprofv3 counters are taken on")
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
     ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity",
@@ -184,21 +190,31 @@ def main():
         return hess_reuse(args, ctx, inst, spec, log)
 
     # ---- training (untimed) -----------------------------------------------
-    t0 = time.perf_counter()
-    S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
-                                           wl.CONFIGS["learned_train"]["seed"], wl.draw_params,
-                                           wl.draw_noise)
-    S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
-                                           wl.CONFIGS["learned_control"]["seed"], wl.draw_params,
-                                           wl.draw_noise)
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    log("training data %.1f s" % t_data)
-    net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
-                               batch=4096, lr=2e-3, log=log)
-    net_stats = tinfo["stats"]
-    del S_tr
-    torch.cuda.empty_cache()
+    if args.net and os.path.exists(args.net):
+        net = learned.Mlp.load(ctx, args.net)
+        tinfo = {"seconds": 0.0, "history": [], "best_epoch": -1, "best_control_mse": -1.0,
+                 "steps": 0, "loaded_from": args.net}
+        t_data = 0.0
+        log("network loaded from %s" % args.net)
+    else:
+        t0 = time.perf_counter()
+        S_tr, P_tr = learned.make_training_set(ctx, inst, args.train_samples,
+                                               wl.CONFIGS["learned_train"]["seed"],
+                                               wl.draw_params, wl.draw_noise)
+        S_ct, P_ct = learned.make_training_set(ctx, inst, args.control_samples,
+                                               wl.CONFIGS["learned_control"]["seed"],
+                                               wl.draw_params, wl.draw_noise)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        log("training data %.1f s" % t_data)
+        net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
+                                   batch=4096, lr=2e-3, log=log)
+        del S_tr
+        torch.cuda.empty_cache()
+        if args.net:
+            net.save(args.net)
+            log("network saved to %s" % args.net)
+    net_stats = net.get_norm()
 
     # ---- held-out batch -----------------------------------------------------
     n = args.n
@@ -215,6 +231,21 @@ def main():
                     chi2=torch.empty(n, device=dev, dtype=torch.float64),
                     iters=torch.empty(n, device=dev, dtype=torch.int32),
                     status=torch.empty(n, device=dev, dtype=torch.int32))
+
+    if args.profile_learned:
+        out = alloc()
+        learned.phase_timing(ctx, True)
+        runs = []
+        for i in range(args.warmup + args.steps):
+            learned.invert_learned(ctx, inst, net, obs2, W, learned_max_iter=args.learned_max_iter,
+                                   out=out)
+            if i >= args.warmup:
+                runs.append(learned.learned_phases(ctx))
+        print(json.dumps({"mode": "profile-learned", "pixels": n, "steps": args.steps,
+                          "phases_ms": [r["ms"] for r in runs],
+                          "short_fit": runs[-1]["short_fit"], "refit": runs[-1]["refit"]}),
+              flush=True)
+        return
 
     out_l, out_p, out_s = alloc(), alloc(), alloc()
     opts = vf.Options()

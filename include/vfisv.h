@@ -537,10 +537,18 @@ int vfisv_mlp_train(vfisv_ctx *ctx, vfisv_mlp *mlp, const vfisv_train_spec *spec
                     vfisv_train_report *report, double *train_mse, double *control_mse,
                     void *stream);
 
-/* Versioned binary file (magic, version, sizes, normalisation, parameters,
- * FNV-1a checksum).  load rejects other versions and bad checksums. */
+/* Versioned binary file: magic, version, sizes, normalisation, parameters
+ * and (version 2) the optimiser state -- the Adam step count and both
+ * moment vectors, so that a loaded network trains on where the saved one
+ * stopped -- then an FNV-1a checksum of all of it.  load reads versions 1
+ * (optimiser state zero) and 2 and rejects others and bad checksums. */
 int vfisv_mlp_save(vfisv_mlp *mlp, const char *path);
 int vfisv_mlp_load(vfisv_ctx *ctx, const char *path, vfisv_mlp **out);
+
+/* The network's input and output normalisation (host arrays [n_in], [n_in],
+ * [7], [7]), as given to vfisv_mlp_create or read by vfisv_mlp_load. */
+int vfisv_mlp_get_norm(const vfisv_mlp *mlp, float *in_mean, float *in_std, float *out_mean,
+                       float *out_std);
 
 /* Learned-start inversion: the network proposes each pixel's starting
  * model, LM runs at most learned_max_iter trials from it, and every pixel

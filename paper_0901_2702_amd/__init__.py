@@ -83,7 +83,7 @@ EXPORTS = ("vfisv_create", "vfisv_destroy", "vfisv_last_error", "vfisv_version",
            "vfisv_mlp_get_params", "vfisv_mlp_set_params", "vfisv_mlp_forward",
            "vfisv_mlp_gradient", "vfisv_mlp_train_step", "vfisv_mlp_take_loss", "vfisv_mlp_save",
            "vfisv_mlp_load", "vfisv_invert_learned", "vfisv_invert_learned_noalloc",
-           "vfisv_chi2_quantile", "vfisv_learned_phase_timing", "vfisv_learned_phases_get",
+           "vfisv_chi2_quantile", "vfisv_mlp_get_norm", "vfisv_learned_phase_timing", "vfisv_learned_phases_get",
            "vfisv_iter_histogram",
            "vfisv_invert_batches", "vfisv_autotune", "vfisv_synthesize_voigt",
            "vfisv_init_classical", "vfisv_init_combined", "vfisv_stokes_weights")

@@ -34,7 +34,9 @@ namespace {
 // polarisation level below which the weak-field B and gamma replace the
 // network's in the combined start (Sect. 5)
 constexpr float COMBINED_POL_THRESHOLD = 0.06f;
-constexpr uint32_t FILE_VERSION = 1;
+// version 1: normalisation and parameters; version 2 adds the optimiser
+// state (Adam moments and step count) so that training resumes where it was
+constexpr uint32_t FILE_VERSION = 2;
 const char FILE_MAGIC[8] = {'V', 'F', 'I', 'S', 'V', 'M', 'L', 'P'};
 
 template <class T>
@@ -585,13 +587,18 @@ int vfisv_mlp_train(vfisv_ctx* ctx, vfisv_mlp* m, const vfisv_train_spec* sp,
 int vfisv_mlp_save(vfisv_mlp* m, const char* path) {
   if (!m || !path) return VFISV_E_INVALID;
   const MlpLayout& L = m->dev.L;
-  std::vector<float> params(L.total);
+  const size_t nt = (size_t)L.total;
+  std::vector<float> params(nt), am(nt), av(nt);
   int rc = vfisv_mlp_get_params(m, params.data(), L.total);
   if (rc) return rc;
+  hipError_t e = hipMemcpy(am.data(), m->dev.adam_m, 4 * nt, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(av.data(), m->dev.adam_v, 4 * nt, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(m->ctx, e, "mlp_save: optimiser state");
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(m->ctx, VFISV_E_INVALID, std::string("mlp_save: cannot open ") + path);
   const uint32_t n_in = (uint32_t)L.n_in;
   const uint64_t total = (uint64_t)L.total;
+  const int64_t step = m->step;
   uint64_t h = 1469598103934665603ull;
   h = fnv1a(h, &n_in, 4);
   h = fnv1a(h, &total, 8);
@@ -600,13 +607,18 @@ int vfisv_mlp_save(vfisv_mlp* m, const char* path) {
   h = fnv1a(h, m->out_mean.data(), 28);
   h = fnv1a(h, m->out_std.data(), 28);
   h = fnv1a(h, params.data(), 4 * total);
+  h = fnv1a(h, &step, 8);
+  h = fnv1a(h, am.data(), 4 * total);
+  h = fnv1a(h, av.data(), 4 * total);
   bool ok = std::fwrite(FILE_MAGIC, 1, 8, f) == 8 && std::fwrite(&FILE_VERSION, 4, 1, f) == 1 &&
             std::fwrite(&n_in, 4, 1, f) == 1 && std::fwrite(&total, 8, 1, f) == 1 &&
             std::fwrite(m->in_mean.data(), 4, n_in, f) == n_in &&
             std::fwrite(m->in_std.data(), 4, n_in, f) == n_in &&
             std::fwrite(m->out_mean.data(), 4, 7, f) == 7 &&
             std::fwrite(m->out_std.data(), 4, 7, f) == 7 &&
-            std::fwrite(params.data(), 4, total, f) == total && std::fwrite(&h, 8, 1, f) == 1;
+            std::fwrite(params.data(), 4, total, f) == total && std::fwrite(&step, 8, 1, f) == 1 &&
+            std::fwrite(am.data(), 4, total, f) == total &&
+            std::fwrite(av.data(), 4, total, f) == total && std::fwrite(&h, 8, 1, f) == 1;
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(m->ctx, VFISV_E_INVALID, "mlp_save: write failed");
   return VFISV_OK;
@@ -621,21 +633,30 @@ int vfisv_mlp_load(vfisv_ctx* ctx, const char* path, vfisv_mlp** out) {
   char magic[8];
   uint32_t ver = 0, n_in = 0;
   uint64_t total = 0, h_file = 0;
+  int64_t step = 0;
   bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, FILE_MAGIC, 8) == 0 &&
-            std::fread(&ver, 4, 1, f) == 1 && ver == FILE_VERSION &&
+            std::fread(&ver, 4, 1, f) == 1 && (ver == 1 || ver == FILE_VERSION) &&
             std::fread(&n_in, 4, 1, f) == 1 && n_in >= 1 && n_in <= MLP_MAX_IN &&
             std::fread(&total, 8, 1, f) == 1 && (int64_t)total == mlp_layout((int)n_in).total;
-  std::vector<float> im, is, om(7), os(7), params;
+  std::vector<float> im, is, om(7), os(7), params, am, av;
   if (ok) {
     im.resize(n_in);
     is.resize(n_in);
     params.resize(total);
     ok = std::fread(im.data(), 4, n_in, f) == n_in && std::fread(is.data(), 4, n_in, f) == n_in &&
          std::fread(om.data(), 4, 7, f) == 7 && std::fread(os.data(), 4, 7, f) == 7 &&
-         std::fread(params.data(), 4, total, f) == total && std::fread(&h_file, 8, 1, f) == 1;
+         std::fread(params.data(), 4, total, f) == total;
   }
+  if (ok && ver >= 2) {
+    am.resize(total);
+    av.resize(total);
+    ok = std::fread(&step, 8, 1, f) == 1 && step >= 0 &&
+         std::fread(am.data(), 4, total, f) == total &&
+         std::fread(av.data(), 4, total, f) == total;
+  }
+  ok = ok && std::fread(&h_file, 8, 1, f) == 1;
   std::fclose(f);
-  if (!ok) return fail(ctx, VFISV_E_INVALID, "mlp_load: not a network file of this version");
+  if (!ok) return fail(ctx, VFISV_E_INVALID, "mlp_load: not a network file of a known version");
   uint64_t h = 1469598103934665603ull;
   h = fnv1a(h, &n_in, 4);
   h = fnv1a(h, &total, 8);
@@ -644,8 +665,36 @@ int vfisv_mlp_load(vfisv_ctx* ctx, const char* path, vfisv_mlp** out) {
   h = fnv1a(h, om.data(), 28);
   h = fnv1a(h, os.data(), 28);
   h = fnv1a(h, params.data(), 4 * total);
+  if (ver >= 2) {
+    h = fnv1a(h, &step, 8);
+    h = fnv1a(h, am.data(), 4 * total);
+    h = fnv1a(h, av.data(), 4 * total);
+  }
   if (h != h_file) return fail(ctx, VFISV_E_INVALID, "mlp_load: checksum mismatch");
-  return build(ctx, (int)n_in, im.data(), is.data(), om.data(), os.data(), params.data(), 0, out);
+  int rc = build(ctx, (int)n_in, im.data(), is.data(), om.data(), os.data(), params.data(), 0, out);
+  if (rc || ver < 2) return rc;
+  // the optimiser state: training continues with the same moments and step
+  vfisv_mlp* m = *out;
+  hipError_t e = hipMemcpy(m->dev.adam_m, am.data(), 4 * (size_t)total, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->dev.adam_v, av.data(), 4 * (size_t)total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    vfisv_mlp_destroy(m);
+    *out = nullptr;
+    return hip_fail(ctx, e, "mlp_load: optimiser state");
+  }
+  m->step = (int)step;
+  return VFISV_OK;
+}
+
+int vfisv_mlp_get_norm(const vfisv_mlp* m, float* in_mean, float* in_std, float* out_mean,
+                       float* out_std) {
+  if (!m || !in_mean || !in_std || !out_mean || !out_std) return VFISV_E_INVALID;
+  std::memcpy(in_mean, m->in_mean.data(), sizeof(float) * m->in_mean.size());
+  std::memcpy(in_std, m->in_std.data(), sizeof(float) * m->in_std.size());
+  std::memcpy(out_mean, m->out_mean.data(), sizeof(float) * 7);
+  std::memcpy(out_std, m->out_std.data(), sizeof(float) * 7);
+  return VFISV_OK;
 }
 
 }  // extern "C"

@@ -54,6 +54,7 @@ def _L():
                                            _vp]
         L.vfisv_mlp_take_loss.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.vfisv_mlp_save.argtypes = [_vp, ctypes.c_char_p]
+        L.vfisv_mlp_get_norm.argtypes = [_vp, fp, fp, fp, fp]
         L.vfisv_mlp_load.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]
         fp_ = ctypes.POINTER(ctypes.c_float)
         dp_ = ctypes.POINTER(ctypes.c_double)
@@ -127,6 +128,15 @@ class Mlp:
             raise ValueError("stokes must be [n, %d] for this network, got shape %s"
                              % (self.n_in, tuple(stokes.shape)))
         return n
+
+    def get_norm(self):
+        """(in_mean, in_std, out_mean, out_std) as float32 numpy arrays."""
+        n = self.n_in
+        arrs = [np.empty(n, np.float32), np.empty(n, np.float32), np.empty(7, np.float32),
+                np.empty(7, np.float32)]
+        ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) for a in arrs]
+        self.ctx._check(_L().vfisv_mlp_get_norm(self._h, *ptrs), "vfisv_mlp_get_norm")
+        return arrs
 
     def get_params(self):
         a = np.empty(self.num_params, np.float32)

@@ -199,16 +199,55 @@ def test_input_width_limit(ctx):
         learned.Mlp(ctx, 1249, np.zeros(1249), np.ones(1249), np.zeros(7), np.ones(7))
 
 
+def _fnv1a(h, b):
+    for x in b:
+        h ^= x
+        h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
 def test_save_load_round_trip(ctx):
+    """The file keeps normalisation, parameters and the optimiser state: a
+    loaded network's next training step equals the saved one's bit for bit;
+    a version-1 file (written here from the documented layout) loads with
+    the optimiser state at zero; a flipped byte is refused."""
+    import struct
     net, flat, mean, std = _random_net(ctx, 24, 5)
+    dev = ctx.device
+    rng = np.random.default_rng(6)
+    x = torch.tensor((rng.normal(size=(256, 24)) * std + mean).astype(np.float32), device=dev)
+    t = torch.tensor(rng.normal(size=(256, 10)).astype(np.float32), device=dev)
+    rows = torch.arange(256, dtype=torch.int32, device=dev)
+    for _ in range(3):
+        net.train_step(x, t, rows, 1e-3)
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "net.bin")
         net.save(path)
         net2 = learned.Mlp.load(ctx, path)
         np.testing.assert_array_equal(net2.get_params(), net.get_params())
-        x = torch.randn(300, 24, device=ctx.device)
-        np.testing.assert_array_equal(net.forward(x)[0].cpu().numpy(),
-                                      net2.forward(x)[0].cpu().numpy())
+        for a, b in zip(net2.get_norm(), net.get_norm()):
+            np.testing.assert_array_equal(a, b)
+        xx = torch.randn(300, 24, device=dev)
+        np.testing.assert_array_equal(net.forward(xx)[0].cpu().numpy(),
+                                      net2.forward(xx)[0].cpu().numpy())
+        net.train_step(x, t, rows, 1e-3)
+        net2.train_step(x, t, rows, 1e-3)
+        np.testing.assert_array_equal(net2.get_params(), net.get_params())
+        # version 1: no optimiser state
+        p = net.get_params()
+        im, is_, om, os_ = net.get_norm()
+        body = (struct.pack("<I", 24) + struct.pack("<Q", p.size) + im.tobytes() + is_.tobytes()
+                + om.tobytes() + os_.tobytes() + p.tobytes())
+        h = _fnv1a(1469598103934665603, body)
+        path1 = os.path.join(d, "v1.bin")
+        with open(path1, "wb") as f:
+            f.write(b"VFISVMLP" + struct.pack("<I", 1) + body + struct.pack("<Q", h))
+        net3 = learned.Mlp.load(ctx, path1)
+        fresh = learned.Mlp(ctx, 24, im, is_, om, os_)
+        fresh.set_params(p)  # zero optimiser state
+        net3.train_step(x, t, rows, 1e-3)
+        fresh.train_step(x, t, rows, 1e-3)
+        np.testing.assert_array_equal(net3.get_params(), fresh.get_params())
         with open(path, "r+b") as f:
             f.seek(100)
             b = f.read(1)
