@@ -23,6 +23,15 @@ from the default model, keeping the re-fit).
 Observations are synthesised on the device by the library's forward model
 from host-drawn (seeded numpy) parameters and noise; the network is trained
 before the timed region (its time is reported separately).
+
+Roofline: the dominant launch is the short fit.  Its float32 work is what the
+method needs by the oracle's operation census (python -m oracle.census:
+per trial synthesis, per Jacobian with its normal equations, per chi^2 and
+per solve, counted as the oracle runs) times the launch's own counters
+(trials, starts, Jacobians), over the launch's HIP-event time; the float64
+work (chi^2, solves) is reported apart.  Executed float32 FLOP and HBM bytes
+come from committed rocprofv3 counter runs while the kernel sources are
+unchanged since.
 """
 import argparse
 import json
@@ -39,16 +48,10 @@ PEAK_BF16_TFLOPS = 2500.0
 # Network inference per pixel: 2 (24*256 + 2*256*256 + 256*10) FLOP.
 MLP_FLOP_PER_PIXEL = 2 * (24 * 256 + 2 * 256 * 256 + 256 * 10)
 
-# Algorithmic float32 work per unit, counted from the formula sequence of the
-# synthesis: per synthesis point, per filter tap, per observed sample, plus
-# the float64 solve.
-FLOP_POINT_VALUES = 317      # 3 Faddeeva (86 each), absorption matrix, UR, mixing
-FLOP_POINT_JAC_EXTRA = 379   # Eqs. 8-9, element and parameter tangents
-FLOP_TAP_VALUES = 8          # 4 normalised Stokes values per tap
-FLOP_TAP_JAC = 58            # 29 accumulators per tap
-FLOP_SAMPLE_VALUES = 25      # assemble 4 values + 4 weighted squared residuals
-FLOP_SAMPLE_JAC = 115 + 4 * 140  # assemble 4 Jacobian rows + normal equations
-FLOP_SOLVE_FP64 = 1100       # equilibration, 10x10 Cholesky, substitutions, projection
+# Work per unit of the method (one trial synthesis, one Jacobian, one chi^2,
+# one damped solve), counted by the oracle's operation census
+# (python -m oracle.census writes this file).
+FLOP_CENSUS = os.path.join(ROOT, "profiles", "flop_census.md")
 
 
 # HBM traffic of one plain-LM launch, from the committed rocprofv3 counter runs
@@ -57,6 +60,7 @@ FLOP_SOLVE_FP64 = 1100       # equilibration, 10x10 Cholesky, substitutions, pro
 # value recorded with the counters; otherwise the figure is stale and null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_plain_traffic.md")
 LEARNED_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_learned_short_traffic.md")
+LEARNED_SQ_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_hmi_1M_learned_sq_counters.md")
 FINE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lm_kernel_fine_1M_traffic.md")
 KERNEL_SOURCES = ("paper_0901_2702_amd/csrc/kernels.hip", "paper_0901_2702_amd/csrc/kernels.h",
                   "paper_0901_2702_amd/csrc/me_device.h")
@@ -69,6 +73,20 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def committed_values(profile, n):
+    """The machine-readable record of a committed counter profile, or None
+    when it was taken on other kernel sources or another batch size."""
+    try:
+        with open(profile) as fh:
+            kv = dict(line.strip("- `\n").split(": ", 1) for line in fh
+                      if line.startswith("- `") and ": " in line)
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv["pixels"]) != n:
+            return None
+        return {k: float(v) for k, v in kv.items() if k not in ("kernel_source_sha256", "pixels")}
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def committed_traffic(n, profile=TRAFFIC_PROFILE):
@@ -89,27 +107,44 @@ def committed_traffic(n, profile=TRAFFIC_PROFILE):
 WORK_KEYS = ("pixels", "trials", "accepts", "passes", "derivative_passes", "jacobians")
 
 
-def algorithmic_flop(c, f_trial, f_jac, f_solve):
-    """FP32 work the method needs (Fig. 6): every trial's synthesis and
-    solve, the values of every start, and the Jacobian (with its filter and
-    normal equations) of every start and every accepted model that does not
-    end its fit, counted by the library as `jacobians`."""
-    return (c["trials"] * (f_trial + f_solve) + c["pixels"] * f_trial
-            + c["jacobians"] * (f_jac - f_trial))
+class Census:
+    """Per-unit operation counts of one instrument from the oracle's census:
+    trial = one synthesis of the observed samples, values only (float32 in
+    the kernels); jac = its derivatives and the normal equations (float32),
+    at a start or an accepted model; chi2 = one chi^2 (float64), per
+    synthesis; solve = one damped solve and step (float64), per trial."""
 
+    def __init__(self, name, info):
+        with open(FLOP_CENSUS) as fh:
+            kv = dict(line.strip("- `\n").split(": ", 1) for line in fh
+                      if line.startswith("- `") and ": " in line)
+        pts, taps = int(kv[name + ".points"]), int(kv[name + ".taps"])
+        if (pts, taps) != (info["n_active_fine"], info["n_taps"]):
+            raise SystemExit("the operation census counts %d points and %d taps for %s, the "
+                             "instrument has %d and %d: run python -m oracle.census"
+                             % (pts, taps, name, info["n_active_fine"], info["n_taps"]))
+        self.trial = float(kv[name + ".synthesis_values"])
+        self.jac = float(kv[name + ".synthesis_derivatives"]) + float(
+            kv[name + ".normal_equations"])
+        self.chi2 = float(kv[name + ".chi2"])
+        self.solve = float(kv[name + ".solve"])
 
-def executed_flop(c, f_trial, f_jac, f_solve):
-    """FP32 work a launch executed: its derivative passes at the Jacobian
-    pass's cost, its values-only passes at the trial's, and the solves."""
-    d = c.get("derivative_passes", c["passes"])
-    return d * f_jac + (c["passes"] - d) * f_trial + c["trials"] * f_solve
+    def fp32(self, c):
+        """Float32 work the method needs (Fig. 6): the values of every start
+        and every trial, and the Jacobian with its normal equations at every
+        start and every accepted model that does not end its fit (the
+        library's `jacobians` counter)."""
+        return (c["trials"] + c["pixels"]) * self.trial + c["jacobians"] * self.jac
 
+    def fp64(self, c):
+        """Float64 work: chi^2 of every synthesis the method needs and every
+        damped solve."""
+        return (c["trials"] + c["pixels"]) * self.chi2 + c["trials"] * self.solve
 
-def work_model(n_pts, n_taps, n_obs):
-    f_trial = n_pts * FLOP_POINT_VALUES + n_taps * FLOP_TAP_VALUES + n_obs * FLOP_SAMPLE_VALUES
-    f_jac = (n_pts * (FLOP_POINT_VALUES + FLOP_POINT_JAC_EXTRA) + n_taps * FLOP_TAP_JAC
-             + n_obs * (FLOP_SAMPLE_VALUES + FLOP_SAMPLE_JAC))
-    return f_trial, f_jac, FLOP_SOLVE_FP64
+    def record(self):
+        return {"fp32_per_trial": round(self.trial, 1), "fp32_per_jacobian": round(self.jac, 1),
+                "fp64_per_chi2": round(self.chi2, 1), "fp64_per_solve": round(self.solve, 1),
+                "source": os.path.relpath(FLOP_CENSUS, ROOT)}
 
 
 def main():
@@ -332,13 +367,15 @@ def main():
     ls, ps = out_l["status"].cpu().numpy(), out_p["status"].cpu().numpy()
     fb = (ls & vf.FALLBACK_USED) != 0
 
-    f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
+    census = Census("hmi", inst.info)
+    alg = census.fp32
+    # executed float32 FLOP per launch from the committed SQ counter runs
+    # (2 per FMA, 1 per MUL, ADD or transcendental, 64 lanes per wave
+    # instruction), while the kernel sources are unchanged since
+    sq = committed_values(LEARNED_SQ_PROFILE, n) or {}
 
-    def alg(c):
-        return algorithmic_flop(c, f_trial, f_jac, f_solve)
-
-    def executed(c):
-        return executed_flop(c, f_trial, f_jac, f_solve)
+    def rate(flop, ms):
+        return None if flop is None else round(flop / (ms * 1e-3) / 1e12, 3)
 
     def q(a, p):
         return float(np.quantile(a, p))
@@ -371,13 +408,15 @@ def main():
                       "ms": round(ph_ms["short_fit"], 4), "bound": "alu", "unit": "TFLOP/s",
                       "peak": PEAK_FP32_TFLOPS,
                       "achieved": round(alg(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
-                      "executed": round(executed(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
+                      "executed": rate(sq.get("short_fit"), ph_ms["short_fit"]),
+                      "fp64": round(census.fp64(sf) / (ph_ms["short_fit"] * 1e-3) / 1e12, 3),
                       "work": {k: sf[k] for k in WORK_KEYS}},
         "refit": {"kernel": "lm_kernel<6> (re-fit of the pixels above tau, <= 50 trials)",
                   "ms": round(ph_ms["refit"], 4), "bound": "alu", "unit": "TFLOP/s",
                   "peak": PEAK_FP32_TFLOPS,
                   "achieved": round(alg(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
-                  "executed": round(executed(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
+                  "executed": rate(sq.get("refit"), ph_ms["refit"]),
+                  "fp64": round(census.fp64(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
                   "work": {k: rf[k] for k in WORK_KEYS}},
         "network": {"kernel": "mlp_infer_kernel (fused 4-layer inference + decode)",
                     "ms": round(ph_ms["network"], 4), "bound": "mfma", "unit": "TFLOP/s",
@@ -456,8 +495,8 @@ def main():
             "kernel": dom["kernel"] + ", the dominant launch of the learned step",
             "kernel_ms": dom["ms"],
             "executed_tflops": dom["executed"],
-            "flop_per_trial": f_trial, "flop_per_jacobian_pass": f_jac,
-            "flop64_per_solve": f_solve,
+            "fp64_tflops": dom["fp64"],
+            "census": census.record(),
             "launches": launches,
             "plain_lm_launch": {
                 "ms": round(float(np.median(ev_p)), 4),
@@ -559,9 +598,8 @@ def full_disk(args, ctx, inst, spec, log):
         sweep[str(cl)] = round(timed(obs, out, vf.Options(chunk_log2=cl), 2)[1], 3)
     log("chunk_log2 sweep (ms): %s" % sweep)
 
-    f_trial, f_jac, f_solve = work_model(inst.info["n_active_fine"], inst.info["n_taps"], n_obs)
-    alg = algorithmic_flop(c, f_trial, f_jac, f_solve)
-    achieved = alg / (ev_ms * 1e-3) / 1e12
+    census = Census("hmi", inst.info)
+    achieved = census.fp32(c) / (ev_ms * 1e-3) / 1e12
 
     # the same disk with the per-pixel weights of Eqs. 14-15 (mu from the
     # disk geometry)
@@ -708,9 +746,8 @@ def fine_mixed(args, ctx, inst, spec, log):
     log("mixed %.2f ms, fine alone %.2f ms, HMI alone %.2f ms" % (ms_mix, ms_f, ms_h))
 
     fi = finst.info
-    f_trial, f_jac, f_solve = work_model(fi["n_active_fine"], fi["n_taps"], fspec.n_obs)
-    alg = algorithmic_flop(c_f, f_trial, f_jac, f_solve)
-    achieved = alg / (ev_f * 1e-3) / 1e12
+    census = Census("fine", fi)
+    achieved = census.fp32(c_f) / (ev_f * 1e-3) / 1e12
     tr_f = committed_traffic(n_f, FINE_TRAFFIC_PROFILE)
     n = n_f + n_h
     result = {
@@ -741,8 +778,7 @@ def fine_mixed(args, ctx, inst, spec, log):
                          tr_f, algorithmic_bytes=n_f * (4 * fspec.n_obs * 4 + 56),
                          source=os.path.relpath(FINE_TRAFFIC_PROFILE, ROOT)),
                      "kernel": "lm_kernel<0> (banded, fine pixels alone)",
-                     "kernel_ms": round(ev_f, 3), "flop_per_trial": f_trial,
-                     "flop_per_jacobian_pass": f_jac,
+                     "kernel_ms": round(ev_f, 3), "census": census.record(),
                      "work_fine": {k: c_f[k] for k in WORK_KEYS},
                      "work_mixed": {k: c_mix[k] for k in WORK_KEYS}},
     }

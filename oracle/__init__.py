@@ -49,41 +49,46 @@ def lib():
     if _LIB is None:
         if not os.path.exists(_build.LIB):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
-        L.orc_faddeeva_batch.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp]
-        L.orc_zeeman_constant.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.orc_zeeman_constant.restype = ctypes.c_double
-        L.orc_synth_fine.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
-        L.orc_voigt_taylor_batch.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp]
-        L.orc_voigt_taylor_batch.restype = None
-        L.orc_voigt_table_node.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
-        L.orc_voigt_table_node.restype = None
-        L.orc_forward.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
-        L.orc_project.argtypes = [_dp]
-        L.orc_eps_decrease.argtypes = [ctypes.c_double]
-        L.orc_eps_decrease.restype = ctypes.c_double
-        L.orc_eps_increase.argtypes = [ctypes.c_double]
-        L.orc_eps_increase.restype = ctypes.c_double
-        L.orc_solve.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_uint32, _dp]
-        L.orc_solve.restype = ctypes.c_int
-        L.orc_default_init.argtypes = [_dp]
-        L.orc_lm_pixel.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
-                                   _fp, _fp, _dp, ctypes.c_int64, _dp, _dp, _ip, _ip,
-                                   ctypes.POINTER(_Counters)]
-        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
-        L.orc_splitmix64.restype = ctypes.c_uint64
-        L.orc_restart_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
-                                          ctypes.c_int]
-        L.orc_restart_uniform.restype = ctypes.c_double
-        L.orc_invert.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
-                                 ctypes.c_int64, _fp, _fp, ctypes.c_int, _dp, _dp, _dp,
-                                 _ip, _ip, ctypes.POINTER(_Counters), ctypes.c_int]
-        L.orc_invert.restype = ctypes.c_int
-        L.orc_forward_batch.argtypes = [ctypes.POINTER(_Instrument), ctypes.c_int64, _dp,
-                                        _dp, ctypes.c_int]
-        L.orc_forward_batch.restype = ctypes.c_int
-        _LIB = L
+        _LIB = bind(_build.LIB)
     return _LIB
+
+
+def bind(path):
+    """Load an oracle library and declare its C signatures."""
+    L = ctypes.CDLL(path)
+    L.orc_faddeeva_batch.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp]
+    L.orc_zeeman_constant.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_zeeman_constant.restype = ctypes.c_double
+    L.orc_synth_fine.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
+    L.orc_voigt_taylor_batch.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp]
+    L.orc_voigt_taylor_batch.restype = None
+    L.orc_voigt_table_node.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.orc_voigt_table_node.restype = None
+    L.orc_forward.argtypes = [ctypes.POINTER(_Instrument), _dp, _dp, _dp]
+    L.orc_project.argtypes = [_dp]
+    L.orc_eps_decrease.argtypes = [ctypes.c_double]
+    L.orc_eps_decrease.restype = ctypes.c_double
+    L.orc_eps_increase.argtypes = [ctypes.c_double]
+    L.orc_eps_increase.restype = ctypes.c_double
+    L.orc_solve.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_uint32, _dp]
+    L.orc_solve.restype = ctypes.c_int
+    L.orc_default_init.argtypes = [_dp]
+    L.orc_lm_pixel.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
+                               _fp, _fp, _dp, ctypes.c_int64, _dp, _dp, _ip, _ip,
+                               ctypes.POINTER(_Counters)]
+    L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_restart_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                      ctypes.c_int]
+    L.orc_restart_uniform.restype = ctypes.c_double
+    L.orc_invert.argtypes = [ctypes.POINTER(_Instrument), ctypes.POINTER(_Options),
+                             ctypes.c_int64, _fp, _fp, ctypes.c_int, _dp, _dp, _dp,
+                             _ip, _ip, ctypes.POINTER(_Counters), ctypes.c_int]
+    L.orc_invert.restype = ctypes.c_int
+    L.orc_forward_batch.argtypes = [ctypes.POINTER(_Instrument), ctypes.c_int64, _dp,
+                                    _dp, ctypes.c_int]
+    L.orc_forward_batch.restype = ctypes.c_int
+    return L
 
 
 def _d(a):

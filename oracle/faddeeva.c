@@ -111,6 +111,9 @@ static void w_asymptotic(double x, double y, double *H, double *F) {
   const double complex iz2 = 1.0 / (z * z);
   const double complex s = 1.0 + iz2 * (0.5 + iz2 * (0.75 + iz2 * 1.875));
   const double complex w = (I / ORC_SQRT_PI) * s / z;
+  /* census: z^2 (5), its reciprocal (5), the Horner sum (2 + 1 + 6 + 1 + 6
+   * + 1), the factor i/sqrt(pi) (2), the division by z (11) */
+  ORC_COUNT(ORC_CEN_VOIGT, 40);
   *H = creal(w);
   *F = cimag(w);
 }
@@ -126,6 +129,8 @@ void orc_voigt_taylor(int order, double u, double a, double *H, double *F) {
   pthread_once(&vt_once, vt_build);
   const int i = (int)lround(x / ORC_VT_STEP);
   long jl = lround(a / ORC_VT_STEP);
+  ORC_COUNT(ORC_CEN_VOIGT, 2);
+  ORC_COUNT(ORC_CEN_SPECIAL, 2);
   if (jl < 0) jl = 0;
   if (jl > ORC_VT_NA - 1) jl = ORC_VT_NA - 1;
   const int j = (int)jl;
@@ -137,12 +142,17 @@ void orc_voigt_taylor(int order, double u, double a, double *H, double *F) {
   const double du = x - u0, da = a - a0;
   double Ht = h + al * da + be * du;
   double Ft = f + be * da - al * du;
+  /* census: the node (2), alpha (6), beta (5), the offsets (2), H and F (4 + 4) */
+  ORC_COUNT(ORC_CEN_VOIGT, 2 + 6 + 5 + 2 + 4 + 4);
   if (order >= 2) {
     /* Eqs. 10-11: the second derivatives are multiples of these two */
     const double P = h + a0 * al + u0 * be;
     const double Q = f + a0 * be - u0 * al;
     Ht += P * (da * da - du * du) + 2.0 * Q * da * du;
     Ft += Q * (da * da - du * du) - 2.0 * P * da * du;
+    /* census: P and Q (4 + 4), da^2 - du^2 and da du once each (3 + 1), the
+     * two second-order terms (5 + 5) */
+    ORC_COUNT(ORC_CEN_VOIGT, 22);
   }
   *H = Ht;
   *F = sgn * Ft;

@@ -79,13 +79,16 @@ static int cholesky(int n, double *A) {
   for (int j = 0; j < n; ++j) {
     double d = A[j * n + j];
     for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    ORC_COUNT(ORC_CEN_SOLVE, 2 * j);
     if (!(d > 0.0) || !isfinite(d)) return 1;
     const double ljj = sqrt(d);
+    ORC_COUNT(ORC_CEN_SPECIAL, 1);
     A[j * n + j] = ljj;
     for (int i = j + 1; i < n; ++i) {
       double s = A[i * n + j];
       for (int k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
       A[i * n + j] = s / ljj;
+      ORC_COUNT(ORC_CEN_SOLVE, 2 * j + 1);
     }
   }
   return 0;
@@ -154,6 +157,10 @@ int orc_solve(const double *H, const double *g, double eps, uint32_t free_mask,
     C[i * n + i] += eps; /* (1 + eps) on the equilibrated unit diagonal */
     b[i] = sc[i] * g[idx[i]];
   }
+  /* census: n reciprocals (and square roots), one triangle of C (2 each),
+   * the damping and the scaled gradient */
+  ORC_COUNT(ORC_CEN_SOLVE, n + n * (n + 1) + n + n);
+  ORC_COUNT(ORC_CEN_SPECIAL, n);
 
   double L[NP * NP], y[NP];
   memcpy(L, C, sizeof(double) * n * n);
@@ -169,6 +176,7 @@ int orc_solve(const double *H, const double *g, double eps, uint32_t free_mask,
       for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * y[k];
       y[i] = s / L[i * n + i];
     }
+    ORC_COUNT(ORC_CEN_SOLVE, 2 * (n * (n - 1) + n)); /* the two substitutions */
   } else {
     used_fallback = 1;
     double A[NP * NP], V[NP * NP];
@@ -187,6 +195,7 @@ int orc_solve(const double *H, const double *g, double eps, uint32_t free_mask,
     }
   }
   for (int i = 0; i < n; ++i) delta[idx[i]] = sc[i] * y[i];
+  ORC_COUNT(ORC_CEN_SOLVE, n);
   return used_fallback;
 }
 
@@ -209,15 +218,27 @@ static double chi2_and_normal(int rows, const float *obs, const float *W, const 
     const double res = (double)obs[r] - S[r];
     const double w = (double)W[r];
     chi += w * res * res;
+    ORC_COUNT(ORC_CEN_CHI2, 4);
     if (J) {
       const double *j = J + (size_t)r * NP;
+      /* census: w r once; per non-zero J entry a multiply-add into g and w J
+       * once; per pair of non-zero entries of one triangle a multiply-add */
+      ORC_COUNT(ORC_CEN_NORMAL, 1);
       for (int p = 0; p < NP; ++p) {
         g[p] += w * res * j[p];
         if (H)
           for (int q = 0; q < NP; ++q) H[p * NP + q] += w * j[p] * j[q];
+        if (j[p] != 0.0) {
+          ORC_COUNT(ORC_CEN_NORMAL, 2);
+          if (H) {
+            ORC_COUNT(ORC_CEN_NORMAL, 1);
+            for (int q = p; q < NP; ++q) ORC_COUNT(ORC_CEN_NORMAL, 2 * (j[q] != 0.0));
+          }
+        }
       }
     }
   }
+  ORC_COUNT(ORC_CEN_CHI2, 1);
   return chi / dof;
 }
 
@@ -375,6 +396,7 @@ void orc_lm_pixel(const orc_instrument *inst, const orc_options *opt,
       cnt->solves++;
       if (sres == 1) cnt->svd_fallbacks++;
       for (int p = 0; p < NP; ++p) Mt[p] = M[p] + delta[p];
+      ORC_COUNT(ORC_CEN_SOLVE, NP);
       orc_project(Mt);
       /* trial: values only (Fig. 6) */
       orc_forward(inst, Mt, S, NULL);

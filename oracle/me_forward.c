@@ -41,6 +41,22 @@ typedef struct {
   double d[NP];
 } dual;
 
+#ifdef ORC_CENSUS
+uint64_t orc_census[ORC_CEN_N];
+void orc_census_take(uint64_t *out) {
+  memcpy(out, orc_census, sizeof orc_census);
+  memset(orc_census, 0, sizeof orc_census);
+}
+#endif
+
+/* Census of one gradient component of a sum (x + y), a product (x y') + x' y)
+ * or a quotient ((x' - r y') / y): operations on components that are not
+ * identically zero. */
+#define NZ(x) ((x) != 0.0)
+#define CEN_SUM(x, y) ORC_COUNT(ORC_CEN_GRADIENT, NZ(x) && NZ(y))
+#define CEN_PROD(x, y) ORC_COUNT(ORC_CEN_GRADIENT, NZ(x) + NZ(y) + (NZ(x) && NZ(y)))
+#define CEN_QUOT(x, y) ORC_COUNT(ORC_CEN_GRADIENT, (NZ(x) || NZ(y)) ? 1 + NZ(y) + (NZ(x) && NZ(y)) : 0)
+
 /* nd = number of live gradient components (0 = values only, NP = all). */
 static dual d_const(double v) {
   dual r;
@@ -56,49 +72,78 @@ static dual d_var(double v, int idx, double seed) {
 static dual d_add(dual a, dual b, int nd) {
   dual r;
   r.v = a.v + b.v;
-  for (int k = 0; k < nd; ++k) r.d[k] = a.d[k] + b.d[k];
+  ORC_COUNT(ORC_CEN_VALUE, 1);
+  for (int k = 0; k < nd; ++k) {
+    CEN_SUM(a.d[k], b.d[k]);
+    r.d[k] = a.d[k] + b.d[k];
+  }
   return r;
 }
 static dual d_sub(dual a, dual b, int nd) {
   dual r;
   r.v = a.v - b.v;
-  for (int k = 0; k < nd; ++k) r.d[k] = a.d[k] - b.d[k];
+  ORC_COUNT(ORC_CEN_VALUE, 1);
+  for (int k = 0; k < nd; ++k) {
+    CEN_SUM(a.d[k], b.d[k]);
+    r.d[k] = a.d[k] - b.d[k];
+  }
   return r;
 }
 static dual d_mul(dual a, dual b, int nd) {
   dual r;
   r.v = a.v * b.v;
-  for (int k = 0; k < nd; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  ORC_COUNT(ORC_CEN_VALUE, 1);
+  for (int k = 0; k < nd; ++k) {
+    CEN_PROD(a.d[k], b.d[k]);
+    r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  }
   return r;
 }
 static dual d_div(dual a, dual b, int nd) {
   dual r;
   r.v = a.v / b.v;
-  for (int k = 0; k < nd; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+  ORC_COUNT(ORC_CEN_VALUE, 1);
+  for (int k = 0; k < nd; ++k) {
+    CEN_QUOT(a.d[k], b.d[k]);
+    r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+  }
   return r;
 }
 static dual d_scale(dual a, double c, int nd) {
   dual r;
   r.v = a.v * c;
-  for (int k = 0; k < nd; ++k) r.d[k] = a.d[k] * c;
+  ORC_COUNT(ORC_CEN_VALUE, 1);
+  for (int k = 0; k < nd; ++k) {
+    ORC_COUNT(ORC_CEN_GRADIENT, NZ(a.d[k]));
+    r.d[k] = a.d[k] * c;
+  }
   return r;
 }
 static dual d_addc(dual a, double c) {
   a.v += c;
+  ORC_COUNT(ORC_CEN_VALUE, 1);
   return a;
 }
 static dual d_sin(dual a, int nd) {
   dual r;
   r.v = sin(a.v);
   const double c = cos(a.v);
-  for (int k = 0; k < nd; ++k) r.d[k] = c * a.d[k];
+  ORC_COUNT(ORC_CEN_SPECIAL, nd > 0 ? 2 : 1);
+  for (int k = 0; k < nd; ++k) {
+    ORC_COUNT(ORC_CEN_GRADIENT, NZ(a.d[k]));
+    r.d[k] = c * a.d[k];
+  }
   return r;
 }
 static dual d_cos(dual a, int nd) {
   dual r;
   r.v = cos(a.v);
   const double s = -sin(a.v);
-  for (int k = 0; k < nd; ++k) r.d[k] = s * a.d[k];
+  ORC_COUNT(ORC_CEN_SPECIAL, nd > 0 ? 2 : 1);
+  for (int k = 0; k < nd; ++k) {
+    ORC_COUNT(ORC_CEN_GRADIENT, NZ(a.d[k]));
+    r.d[k] = s * a.d[k];
+  }
   return r;
 }
 
@@ -113,9 +158,13 @@ static void d_voigt(int variant, dual u, dual a, int nd, dual *H, dual *F) {
     orc_voigt_taylor(variant, u.v, a.v, &h, &f);
   const double al = -ORC_TWO_OVER_SQRT_PI + 2.0 * a.v * h + 2.0 * u.v * f;
   const double be = 2.0 * a.v * f - 2.0 * u.v * h;
+  ORC_COUNT(ORC_CEN_VOIGT_CALLS, 1);
+  if (nd > 0) ORC_COUNT(ORC_CEN_GRADIENT, 6 + 5);  /* alpha and beta, Eqs. 8-9 */
   H->v = h;
   F->v = f;
   for (int k = 0; k < nd; ++k) {
+    /* H' = alpha a' + beta u', F' = beta a' - alpha u': a product pair each */
+    ORC_COUNT(ORC_CEN_GRADIENT, 2 * (NZ(a.d[k]) + NZ(u.d[k]) + (NZ(a.d[k]) && NZ(u.d[k]))));
     H->d[k] = al * a.d[k] + be * u.d[k];
     F->d[k] = be * a.d[k] - al * u.d[k];
   }
@@ -132,6 +181,7 @@ double orc_zeeman_constant(double lambda0_A, double geff) {
 static void synth_point(double lambda0_mA, double cz, int voigt, const double *M, double dlam,
                         int nd, dual out[4]) {
   const double deg = ORC_PI / 180.0;
+  ORC_COUNT(ORC_CEN_VALUE, 2); /* the two angles in radians */
   dual B = d_var(M[ORC_B], ORC_B, 1.0);
   dual gam = d_var(M[ORC_GAMMA] * deg, ORC_GAMMA, deg);
   dual chi = d_var(M[ORC_PSI] * deg, ORC_PSI, deg);
@@ -237,11 +287,15 @@ void orc_forward(const orc_instrument *inst, const double *M, double *S, double 
       double acc = 0.0;
       for (int k = 0; k < nf; ++k) acc += Fi[k] * Sf[s * nf + k];
       S[s * no + i] = acc;
+      /* census: a multiply-add per tap that is not zero */
+      for (int k = 0; k < nf; ++k) ORC_COUNT(ORC_CEN_VALUE, 2 * NZ(Fi[k]));
       if (J) {
         for (int p = 0; p < NP; ++p) {
           double aj = 0.0;
           for (int k = 0; k < nf; ++k) aj += Fi[k] * dSf[((size_t)s * nf + k) * NP + p];
           J[((size_t)s * no + i) * NP + p] = aj;
+          for (int k = 0; k < nf; ++k)
+            ORC_COUNT(ORC_CEN_GRADIENT, 2 * (NZ(Fi[k]) && NZ(dSf[((size_t)s * nf + k) * NP + p])));
         }
       }
     }

@@ -151,6 +151,31 @@ int orc_invert(const orc_instrument *inst, const orc_options *opt, int64_t n,
                int32_t *iters, int32_t *status, orc_counters *cnt,
                int nthreads);
 
+/* Operation census (built only into liboracle_census.so, with ORC_CENSUS
+ * defined; oracle/census.py): the arithmetic of every routine is counted
+ * as it runs, one count per +, -, * or / on a double, in these categories.
+ * Gradient work counts only the components that are not identically zero
+ * (an operation whose derivative operands are both zero does nothing). */
+enum {
+  ORC_CEN_VALUE = 0,    /* synthesis and filter, values */
+  ORC_CEN_GRADIENT,     /* synthesis and filter, derivatives (Eqs. 8-9, chain rule) */
+  ORC_CEN_VOIGT_CALLS,  /* H, F evaluations */
+  ORC_CEN_VOIGT,        /* arithmetic of the Taylor-table evaluations (Eqs. 10-13) */
+  ORC_CEN_CHI2,         /* residuals and chi^2 (Eq. 1) */
+  ORC_CEN_NORMAL,       /* J^T W J (one triangle) and J^T W r */
+  ORC_CEN_SOLVE,        /* equilibration, damping, Cholesky, substitutions, step */
+  ORC_CEN_SPECIAL,      /* sqrt, sin, cos, rounding calls (not in the counts above) */
+  ORC_CEN_N
+};
+#ifdef ORC_CENSUS
+extern uint64_t orc_census[ORC_CEN_N];
+/* Copies the counters into out[ORC_CEN_N] and clears them. */
+void orc_census_take(uint64_t *out);
+#define ORC_COUNT(cat, n) (orc_census[(cat)] += (uint64_t)(n))
+#else
+#define ORC_COUNT(cat, n) ((void)0)
+#endif
+
 /* Batch forward synthesis (values only), for building synthetic inputs.
  * params: [n][10]; out: [n][4][n_obs]. */
 int orc_forward_batch(const orc_instrument *inst, int64_t n, const double *params,
