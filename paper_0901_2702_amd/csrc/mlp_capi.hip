@@ -208,12 +208,17 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
   return h;
 }
 
-// Regularised lower incomplete gamma function P(a, x): its power series
-// (Abramowitz & Stegun 6.5.29) below x = a + 1, above it 1 - Q(a, x) with Q
-// from Legendre's continued fraction (A&S 6.5.31), evaluated by the modified
-// Lentz method.
-double gamma_p(double a, double x) {
-  if (!(x > 0.0)) return 0.0;
+// Regularised incomplete gamma functions P(a, x) and Q(a, x) = 1 - P(a, x):
+// the power series of P (Abramowitz & Stegun 6.5.29) below x = a + 1, above
+// it Legendre's continued fraction for Q (A&S 6.5.31), evaluated by the
+// modified Lentz method; the other one by difference, so that each is
+// accurate where it is small.
+void gamma_pq(double a, double x, double* P, double* Q) {
+  if (!(x > 0.0)) {
+    *P = 0.0;
+    *Q = 1.0;
+    return;
+  }
   const double pre = std::exp(-x + a * std::log(x) - std::lgamma(a));
   if (x < a + 1.0) {
     double ap = a, term = 1.0 / a, sum = term;
@@ -223,7 +228,9 @@ double gamma_p(double a, double x) {
       sum += term;
       if (std::fabs(term) < std::fabs(sum) * 1e-17) break;
     }
-    return sum * pre;
+    *P = sum * pre;
+    *Q = 1.0 - *P;
+    return;
   }
   const double tiny = 1e-300;
   double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
@@ -239,18 +246,27 @@ double gamma_p(double a, double x) {
     h *= del;
     if (std::fabs(del - 1.0) < 1e-16) break;
   }
-  return 1.0 - pre * h;
+  *Q = pre * h;
+  *P = 1.0 - *Q;
 }
 
 // q-quantile of chi^2_dof / dof: the x with P(dof / 2, x dof / 2) = q, by
-// bisection (the CDF is increasing).
+// bisection (the CDF is increasing); above the median on Q = 1 - q, so that
+// upper quantiles keep their relative accuracy.
 double chi2_reduced_quantile(int dof, double q) {
   const double a = 0.5 * dof;
+  const bool upper = q > 0.5;
+  const double target = upper ? 1.0 - q : q;
+  auto below = [&](double x) {  // true while x lies below the quantile
+    double P, Q;
+    gamma_pq(a, x * a, &P, &Q);
+    return upper ? Q > target : P < target;
+  };
   double lo = 0.0, hi = 1.0 + 10.0 / std::sqrt((double)dof);
-  while (gamma_p(a, hi * a) < q) hi *= 2.0;
+  while (below(hi)) hi *= 2.0;
   for (int it = 0; it < 400 && hi - lo > 1e-14 * hi; ++it) {
     const double mid = 0.5 * (lo + hi);
-    if (gamma_p(a, mid * a) < q) lo = mid;
+    if (below(mid)) lo = mid;
     else hi = mid;
   }
   return 0.5 * (lo + hi);
