@@ -819,11 +819,19 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
     ++cand;
   };
   const int64_t gw_default = (int64_t)ctx->num_cus * bpc_default;
+  // A sample of m of the n pixels runs on a grid scaled by m / n, so that
+  // each lane inverts as many pixels as in the whole launch: the share of
+  // the launch that is its tail (where latency, not throughput, counts)
+  // then matches, and the choice made on the sample holds for the batch.
+  const double scale = (double)m / (double)n;
+  auto sample_grid = [&](int64_t gw) {
+    return (int)std::max<int64_t>(8, std::llround((double)gw * scale));
+  };
   int best_split = VFISV_DERIV_SPLIT_DEFAULT;
   float best_split_ms = 1e30f;
   for (int si = 0; e == hipSuccess && !rc && si < 6; ++si) {
     vfisv_options oc = o;
-    oc.grid_waves = (int)std::min<int64_t>(gw_default, ctx->max_lanes / 64);
+    oc.grid_waves = sample_grid(std::min<int64_t>(gw_default, ctx->max_lanes / 64));
     oc.chunk_log2 = 8;
     oc.deriv_split = o.fixed_iters > 0 ? 0 : splits[si];
     float ms;
@@ -836,6 +844,12 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
     }
     if (o.fixed_iters > 0) break;  // the fixed-iteration scheme always fuses
   }
+  if (e == hipSuccess && !rc) {  // the default schedule at the best split
+    best.best_ms = best_split_ms;
+    best.grid_waves = (int)std::min<int64_t>(gw_default, ctx->max_lanes / 64);
+    best.chunk_log2 = 8;
+    best.deriv_split = best_split;
+  }
   for (int wi = 0; e == hipSuccess && !rc && wi < 6; ++wi) {
     const int64_t gw = (int64_t)ctx->num_cus * waves_per_cu[wi];
     // a persistent grid larger than what is resident only adds waves that
@@ -843,7 +857,7 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
     if (gw > ctx->max_lanes / 64 || waves_per_cu[wi] > bpc_default) continue;
     for (int ci = 0; e == hipSuccess && ci < 3; ++ci) {
       vfisv_options oc = o;
-      oc.grid_waves = (int)gw;
+      oc.grid_waves = sample_grid(gw);
       oc.chunk_log2 = chunks[ci];
       oc.deriv_split = best_split;
       float ms;
