@@ -1,5 +1,5 @@
 // Learned initialiser on gfx950: a multilayer perceptron (K0 -> 256 -> 256 ->
-// 256 -> 32 (10 used), exact-erf GELU) evaluated and trained with bfloat16 MFMA
+// 256 -> 32 (10 used), GELU with the erf normal CDF) evaluated and trained with bfloat16 MFMA
 // (v_mfma_f32_16x16x32_bf16, float32 accumulation) and Adam on float32
 // master weights.
 //
