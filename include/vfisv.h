@@ -326,9 +326,11 @@ int vfisv_invert_batches(vfisv_ctx *ctx, const vfisv_batch *batches, int n_batch
  * best split every persistent grid (1, 2, 3, 4, 6 or 8 waves per CU, up to
  * the waves that are resident at once for the layout's kernel) and
  * pixel-queue block (2^4, 2^8, 2^12 pixels).  A sample of m of the n
- * pixels runs on each candidate grid scaled by m / n (at least 8 waves), so
- * that every lane inverts as many pixels as in the whole launch and the
- * tail weighs as much as it will there.  The fastest is kept for this
+ * pixels runs on each candidate grid scaled by m / n (at least 8 waves; at
+ * most 8 pixels per lane on the default grid, one factor for every
+ * candidate), so that every lane inverts as many pixels as
+ * in the whole launch and the tail weighs about as much as it will there.
+ * The fastest is kept for this
  * instrument's layout in the context; later inversions with grid_waves == 0,
  * chunk_log2 == -1 and deriv_split == -1 use it.  default_ms is the time of
  * the untuned default (split VFISV_DERIV_SPLIT_DEFAULT, default schedule).

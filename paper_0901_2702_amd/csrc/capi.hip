@@ -820,10 +820,13 @@ int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
   };
   const int64_t gw_default = (int64_t)ctx->num_cus * bpc_default;
   // A sample of m of the n pixels runs on a grid scaled by m / n, so that
-  // each lane inverts as many pixels as in the whole launch: the share of
-  // the launch that is its tail (where latency, not throughput, counts)
-  // then matches, and the choice made on the sample holds for the batch.
-  const double scale = (double)m / (double)n;
+  // each lane inverts as many pixels as in the whole launch (up to 8 per
+  // lane, which bounds a candidate's time): the share of the launch that is
+  // its tail (where latency, not throughput, counts) then matches, and the
+  // choice made on the sample holds for the batch.
+  // (one factor for every candidate, so that their ratios are kept)
+  const double scale =
+      std::min(1.0, std::max((double)m / (double)n, (double)m / (512.0 * (double)gw_default)));
   auto sample_grid = [&](int64_t gw) {
     return (int)std::max<int64_t>(8, std::llround((double)gw * scale));
   };
