@@ -44,7 +44,8 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         if p.returncode != 0:
             raise RuntimeError("hipcc failed: %s\n%s" % (" ".join(cmd), err))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = ([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+           + ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -367,6 +367,7 @@ void vfisv_options_default(vfisv_options* o) {
 
 int vfisv_instrument_create(vfisv_ctx* ctx, const vfisv_instrument_desc* d,
                             vfisv_instrument** out) {
+  vfisv::TraceRange trace_("vfisv_instrument_create");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "instrument_create: ctx is NULL");
   if (!d || !out) return fail(ctx, VFISV_E_INVALID, "instrument_create: NULL argument");
   *out = nullptr;
@@ -648,6 +649,7 @@ int vfisv_synthesize(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
 int vfisv_synthesize_voigt(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                            const float* params, const float* noise, float* stokes, float* jac,
                            int voigt, void* stream) {
+  vfisv::TraceRange trace_("vfisv_synthesize_voigt");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "synthesize: ctx is NULL");
   int rc = check_inst(ctx, inst, "synthesize");
   if (rc) return rc;
@@ -683,6 +685,7 @@ int vfisv_synthesize_voigt(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t
 int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const float* stokes,
                  const float* W, int W_per_pixel, const float* init, const vfisv_options* opt,
                  float* params, double* chi2, int32_t* iters, int32_t* status, void* stream) {
+  vfisv::TraceRange trace_("vfisv_invert");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert: ctx is NULL");
   int rc = check_inst(ctx, inst, "invert");
   if (rc) return rc;
@@ -703,6 +706,7 @@ int vfisv_invert(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const 
 
 int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batches,
                          const vfisv_options* opt, void* stream) {
+  vfisv::TraceRange trace_("vfisv_invert_batches");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "invert_batches: ctx is NULL");
   if (!batches) return fail(ctx, VFISV_E_INVALID, "invert_batches: batches is NULL");
   if (n_batches < 1 || n_batches > MAX_BATCHES)
@@ -765,6 +769,7 @@ int vfisv_invert_batches(vfisv_ctx* ctx, const vfisv_batch* batches, int n_batch
 int vfisv_autotune(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                    const float* stokes, const float* W, int W_per_pixel, const vfisv_options* opt,
                    int64_t sample, vfisv_tuning* out, void* stream) {
+  vfisv::TraceRange trace_("vfisv_autotune");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "autotune: ctx is NULL");
   int rc = check_inst(ctx, inst, "autotune");
   if (rc) return rc;
@@ -931,12 +936,14 @@ int init_start(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n, const fl
 
 int vfisv_init_classical(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                          const float* stokes, float* params, float* pol, void* stream) {
+  vfisv::TraceRange trace_("vfisv_init_classical");
   return init_start(ctx, inst, n, stokes, nullptr, 0.f, params, pol, stream, "init_classical");
 }
 
 int vfisv_init_combined(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                         const float* stokes, const float* base, float pol_threshold,
                         float* params, float* pol, void* stream) {
+  vfisv::TraceRange trace_("vfisv_init_combined");
   if (n > 0 && !base && ctx) return fail(ctx, VFISV_E_INVALID, "init_combined: base is NULL");
   return init_start(ctx, inst, n, stokes, base, pol_threshold, params, pol, stream,
                     "init_combined");
@@ -945,6 +952,7 @@ int vfisv_init_combined(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
 int vfisv_stokes_weights(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,
                          const float* stokes, const float* mu, const float* sigma, float* W,
                          void* stream) {
+  vfisv::TraceRange trace_("vfisv_stokes_weights");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "stokes_weights: ctx is NULL");
   int rc = check_inst(ctx, inst, "stokes_weights");
   if (rc) return rc;
@@ -994,6 +1002,7 @@ int vfisv_get_counters(vfisv_ctx* ctx, vfisv_counters* out) {
 
 int vfisv_iter_histogram(vfisv_ctx* ctx, int64_t n, const int32_t* iters, int n_bins,
                          int64_t* hist, void* stream) {
+  vfisv::TraceRange trace_("vfisv_iter_histogram");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "iter_histogram: ctx is NULL");
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "iter_histogram: n < 0");
   if (n_bins < 1 || n_bins > HIST_MAX)
@@ -1015,6 +1024,7 @@ int vfisv_iter_histogram(vfisv_ctx* ctx, int64_t n, const int32_t* iters, int n_
 
 int vfisv_solve(vfisv_ctx* ctx, int64_t n, const float* H, const float* g, const double* eps,
                 uint32_t free_mask, double* delta, int32_t* code, void* stream) {
+  vfisv::TraceRange trace_("vfisv_solve");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "solve: ctx is NULL");
   if (n < 0) return fail(ctx, VFISV_E_INVALID, "solve: n < 0");
   if (n == 0) return VFISV_OK;

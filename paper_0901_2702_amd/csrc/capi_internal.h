@@ -6,8 +6,22 @@
 
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kernels.h"
 #include "vfisv.h"
+
+namespace vfisv {
+// A named range around one C-ABI call, for tracers (roctx: rocprofv3
+// --marker-trace shows the calls beside their kernels).  Host-side only:
+// nothing is enqueued, so it is safe under graph capture.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace vfisv
 
 struct vfisv_ctx {
   int device = 0;

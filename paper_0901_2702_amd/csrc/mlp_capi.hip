@@ -328,6 +328,7 @@ int vfisv_mlp_set_params(vfisv_mlp* m, const float* host, int64_t n) {
 
 int vfisv_mlp_forward(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stokes, float* codes,
                       float* params, void* stream) {
+  vfisv::TraceRange trace_("vfisv_mlp_forward");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_forward: ctx is NULL");
   int rc = check_mlp(ctx, m, "mlp_forward");
   if (rc) return rc;
@@ -344,6 +345,7 @@ int vfisv_mlp_forward(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stok
 
 int vfisv_mlp_gradient(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* stokes,
                        const float* targets, float* grad, double* loss, void* stream) {
+  vfisv::TraceRange trace_("vfisv_mlp_gradient");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_gradient: ctx is NULL");
   int rc = check_mlp(ctx, m, "mlp_gradient");
   if (rc) return rc;
@@ -369,6 +371,7 @@ int vfisv_mlp_gradient(vfisv_ctx* ctx, vfisv_mlp* m, int64_t n, const float* sto
 
 int vfisv_mlp_train_step(vfisv_ctx* ctx, vfisv_mlp* m, const float* stokes, const float* targets,
                          const int32_t* rows, int batch, float lr, void* stream) {
+  vfisv::TraceRange trace_("vfisv_mlp_train_step");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_train_step: ctx is NULL");
   int rc = check_mlp(ctx, m, "mlp_train_step");
   if (rc) return rc;
@@ -406,6 +409,7 @@ int vfisv_mlp_take_loss(vfisv_mlp* m, double* sum_sq) {
 int vfisv_mlp_stats(vfisv_ctx* ctx, int64_t n, int n_in, const float* stokes,
                     const float* params, float* in_mean, float* in_std, float* out_mean,
                     float* out_std, void* stream) {
+  vfisv::TraceRange trace_("vfisv_mlp_stats");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_stats: ctx is NULL");
   if (n < 2) return fail(ctx, VFISV_E_INVALID, "mlp_stats: n must be >= 2");
   if (n_in < 1 || n_in > MLP_MAX_IN)
@@ -495,6 +499,7 @@ extern "C" {
 int vfisv_mlp_train(vfisv_ctx* ctx, vfisv_mlp* m, const vfisv_train_spec* sp,
                     vfisv_train_report* report, double* train_mse, double* control_mse,
                     void* stream) {
+  vfisv::TraceRange trace_("vfisv_mlp_train");
   if (!ctx) return fail(nullptr, VFISV_E_INVALID, "mlp_train: ctx is NULL");
   int rc = check_mlp(ctx, m, "mlp_train");
   if (rc) return rc;
@@ -916,6 +921,7 @@ int vfisv_invert_learned(vfisv_ctx* ctx, const vfisv_instrument* inst, vfisv_mlp
                          const vfisv_options* opt, int learned_max_iter, double chi2_accept,
                          float* params, double* chi2, int32_t* iters, int32_t* status,
                          void* stream) {
+  vfisv::TraceRange trace_("vfisv_invert_learned");
   return invert_learned_impl(ctx, inst, m, n, stokes, W, W_per_pixel, opt, learned_max_iter,
                              chi2_accept, params, chi2, iters, status, stream, false);
 }
@@ -993,6 +999,7 @@ int vfisv_invert_learned_noalloc(vfisv_ctx* ctx, const vfisv_instrument* inst, v
                                  const vfisv_options* opt, int learned_max_iter,
                                  double chi2_accept, float* params, double* chi2, int32_t* iters,
                                  int32_t* status, void* stream) {
+  vfisv::TraceRange trace_("vfisv_invert_learned_noalloc");
   return invert_learned_impl(ctx, inst, m, n, stokes, W, W_per_pixel, opt, learned_max_iter,
                              chi2_accept, params, chi2, iters, status, stream, true);
 }

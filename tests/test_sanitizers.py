@@ -101,8 +101,11 @@ def _sanitized_library():
         assert p.returncode == 0, "%s\n%s" % (" ".join(cmd), err[-4000:])
     tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + HOST_SAN[:4] + objs
-         + ["-o", tmp])
+         + ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", tmp])
     os.replace(tmp, lib)
+    for f in os.listdir(OUT):  # builds of earlier source states
+        if f.startswith("libvfisv_san_") and f.endswith(".so") and f != os.path.basename(lib):
+            os.remove(os.path.join(OUT, f))
     return lib
 
 
