@@ -530,6 +530,173 @@ __global__ __launch_bounds__(IW * 64) void mlp_infer_kernel(const MlpInferArgs a
   }
 }
 
+// Networks with at most 32 inputs (the HMI filtergrams: one k-step in the
+// first layer): a persistent grid of one 8-wave workgroup per CU whose waves
+// keep their columns' weights of the two 256 x 256 layers in registers
+// (128 per lane) and walk the 64-row tiles, so the weights are read from L2 once per
+// workgroup instead of once per tile.  The tile and the per-element MFMA
+// sequence (same instruction, same k order) are those of mlp_infer_kernel;
+// the hidden layers' GELU comes from a table (below), so an activation may
+// differ from mlp_infer_kernel's in its last bfloat16 bit where its value
+// lies within 6e-7 of a rounding midpoint.  Output layer: wave w takes rows
+// [16 (w / 2), 16 (w / 2) + 16) and columns [16 (w % 2), +16).
+// GELU by linear interpolation in a table of GELU at z = -6 + i / 512
+// (i < 6144, each entry {GELU(z_i), GELU(z_i+1) - GELU(z_i)}, built in LDS by
+// each workgroup from gelu()): interpolation error below (1/512)^2 / 8 times
+// max |GELU''| = 0.8, i.e. 4e-7, on top of gelu()'s 1.5e-7, against
+// 2^-9 relative for the bfloat16 the result is stored in; above z = 6
+// GELU(z) = z to 6e-9, below -6 the first entry (-6e-9) stands for ~0.
+// About ten vector instructions instead of gelu()'s thirteen plus two
+// transcendental ones, in the epilogue that bounds the resident kernel.
+constexpr int GELU_TAB_N = 6144;
+__device__ __forceinline__ float gelu_tab(const float2* __restrict__ tab, float z) {
+  const float x = fminf(fmaxf(fmaf(z, 512.f, 3072.f), 0.f), (float)(GELU_TAB_N - 1));
+  const float i = floorf(x);
+  const float2 e = tab[(int)i];
+  const float g = fmaf(x - i, e.y, e.x);
+  return z >= 6.f ? z : g;
+}
+
+__device__ __forceinline__ void resident_hidden_epilogue(bf16* buf, const f32x4 (&acc)[4][IW_CB],
+                                                         const float* __restrict__ bias,
+                                                         const float2* __restrict__ tab, int wave,
+                                                         int l) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < IW_CB; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + (l >> 4) * 4 + j;
+        const int col = wave * 16 * IW_CB + cb * 16 + (l & 15);
+        buf[row * LDH + col] = (bf16)gelu_tab(tab, acc[rb][cb][j] + bias[col]);
+      }
+}
+
+template <int NK>
+__device__ __forceinline__ void resident_hidden(bf16* buf, int ldin, const bf16x8 (&w)[NK][IW_CB],
+                                                const float* __restrict__ bias,
+                                                const float2* __restrict__ tab, int wave, int l) {
+  const int lr = l & 15, lk = (l >> 4) * 8;
+  f32x4 acc[4][IW_CB];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < IW_CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NK; ++s) {
+    bf16x8 av[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      av[rb] = *(const bf16x8*)(buf + (rb * 16 + lr) * ldin + 32 * s + lk);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < IW_CB; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], w[s][cb], acc[rb][cb], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read the layer's inputs
+  resident_hidden_epilogue(buf, acc, bias, tab, wave, l);
+  __syncthreads();
+}
+
+static_assert(IW == 8 && IW_CB == 2, "the resident kernel's output split assumes 8 waves");
+// LDS of the resident kernel: the 64-row tile (or the outputs over it), then
+// the GELU table
+constexpr size_t RESIDENT_TAB_OFFSET = sizeof(bf16) * FT * LDH;
+constexpr size_t RESIDENT_LDS = RESIDENT_TAB_OFFSET + sizeof(float2) * GELU_TAB_N;
+static_assert(sizeof(float) * FT * (MLP_OUT + 1) <= RESIDENT_TAB_OFFSET && RESIDENT_TAB_OFFSET % 16 == 0,
+              "the outputs fit over the tile");
+
+__global__ __launch_bounds__(IW * 64, 1) void mlp_infer_resident_kernel(const MlpInferArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int K0 = 32, NKH = MLP_H / 32;
+  constexpr int ldx = K0 + 8;
+  bf16* buf = (bf16*)smem;  // [FT][LDH]
+  float* y4 = (float*)smem;  // [FT][MLP_OUT + 1], over the tile once it is read
+  float2* tab = (float2*)(smem + RESIDENT_TAB_OFFSET);  // [GELU_TAB_N]
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = (l >> 4) * 8;
+  for (int i = tid; i < GELU_TAB_N; i += IW * 64) {
+    const float z0 = -6.f + (float)i * (1.f / 512.f), z1 = -6.f + (float)(i + 1) * (1.f / 512.f);
+    const float g0 = gelu(z0);
+    tab[i] = make_float2(g0, gelu(z1) - g0);
+  }
+  // (the table is complete before the first epilogue: the first tile's
+  // input barrier comes first)
+  // this wave's columns of every layer, as MFMA B fragments
+  // (hidden layers 1 and 2: 128 registers; the small first and output
+  // layers are read through the caches at each tile)
+  bf16x8 w1[NKH][IW_CB], w2[NKH][IW_CB];
+#pragma unroll
+  for (int cb = 0; cb < IW_CB; ++cb) {
+    const int col = wave * 16 * IW_CB + cb * 16 + lr;
+#pragma unroll
+    for (int s = 0; s < NKH; ++s) {
+      w1[s][cb] = *(const bf16x8*)(a.Wt[1] + (int64_t)col * MLP_H + 32 * s + lk);
+      w2[s][cb] = *(const bf16x8*)(a.Wt[2] + (int64_t)col * MLP_H + 32 * s + lk);
+    }
+  }
+  const int orb = wave >> 1, ocb = wave & 1;  // output-layer block of this wave
+  const int64_t n_tiles = (a.M + FT - 1) / FT;
+  // the inputs of the workgroup's next tile are loaded into registers while
+  // the current one is computed (4 values per lane), so that their latency
+  // is not exposed between the tiles
+  constexpr int NXL = FT * K0 / (IW * 64);
+  static_assert(NXL * IW * 64 == FT * K0, "whole input tiles");
+  float xin[NXL];
+  auto load_inputs = [&](int64_t t) {
+#pragma unroll
+    for (int q = 0; q < NXL; ++q) {
+      const int idx = tid + q * IW * 64;
+      const int r = idx / K0, k = idx - r * K0;
+      const int64_t row = t * FT + r;
+      xin[q] = (k < a.n_in && row < a.M) ? a.stokes[row * a.n_in + k] : 0.f;
+    }
+  };
+  if (blockIdx.x < n_tiles) load_inputs(blockIdx.x);
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t row0 = tile * FT;
+#pragma unroll
+    for (int q = 0; q < NXL; ++q) {
+      const int idx = tid + q * IW * 64;
+      const int r = idx / K0, k = idx - r * K0;
+      buf[r * ldx + k] = (bf16)(k < a.n_in ? (xin[q] - a.mean[k]) * a.istd[k] : 0.f);
+    }
+    if (tile + gridDim.x < n_tiles) load_inputs(tile + gridDim.x);
+    bf16x8 w0[1][IW_CB];
+#pragma unroll
+    for (int cb = 0; cb < IW_CB; ++cb)
+      w0[0][cb] = *(const bf16x8*)(a.Wt[0] + (int64_t)(wave * 16 * IW_CB + cb * 16 + lr) * K0 + lk);
+    __syncthreads();
+    resident_hidden<1>(buf, ldx, w0, a.bias[0], tab, wave, l);
+    resident_hidden<NKH>(buf, LDH, w1, a.bias[1], tab, wave, l);
+    resident_hidden<NKH>(buf, LDH, w2, a.bias[2], tab, wave, l);
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NKH; ++s) {
+      const bf16x8 av = *(const bf16x8*)(buf + (orb * 16 + lr) * LDH + 32 * s + lk);
+      const bf16x8 wv = *(const bf16x8*)(a.Wt[3] + (int64_t)(ocb * 16 + lr) * MLP_H + 32 * s + lk);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wv, acc, 0, 0, 0);
+    }
+    __syncthreads();  // the tile is read; its space takes the outputs
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = orb * 16 + (l >> 4) * 4 + j;
+      y4[row * (MLP_OUT + 1) + ocb * 16 + lr] = acc[j] + a.bias[3][ocb * 16 + lr];
+    }
+    __syncthreads();
+    if (tid < FT) {
+      const int64_t row = row0 + tid;
+      if (row < a.M)
+        decode_row(&y4[tid * (MLP_OUT + 1)], a.out_mean, a.out_std,
+                   a.codes ? a.codes + row * MLP_NCODE : nullptr,
+                   a.params ? a.params + row * NPAR : nullptr);
+    }
+    __syncthreads();  // the outputs are read before the next tile's inputs
+  }
+}
+
 static_assert(MLP_MAX_IN % 32 == 0 && FT * (MLP_MAX_IN + 8) * 2 <= MLP_LDS_MAX,
               "the widest input must fit a tile");
 
@@ -565,7 +732,30 @@ hipError_t mlp_infer(const MlpDev& net, int64_t M, const float* stokes, float* c
       (const void*)mlp_infer_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, MLP_LDS_MAX);
   if (attr != hipSuccess) return attr;
   const size_t lds = mlp_infer_lds_bytes(L.K0);
-  mlp_infer_kernel<<<(unsigned)((M + FT - 1) / FT), IW * 64, lds, s>>>(a);
+  const int64_t tiles = (M + FT - 1) / FT;
+  if (tiles < 1) return hipSuccess;
+  if (L.K0 == 32) {
+    // one workgroup per CU (the CU count of this device, queried once)
+    static int cus[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (cus[dev] == 0) {
+      int v = 0;
+      e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      cus[dev] = v > 0 ? v : 1;
+    }
+    static const hipError_t rattr =
+        hipFuncSetAttribute((const void*)mlp_infer_resident_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)RESIDENT_LDS);
+    if (rattr != hipSuccess) return rattr;
+    const int64_t grid = tiles < cus[dev] ? tiles : cus[dev];
+    mlp_infer_resident_kernel<<<(unsigned)grid, IW * 64, RESIDENT_LDS, s>>>(a);
+    return hipGetLastError();
+  }
+  mlp_infer_kernel<<<(unsigned)tiles, IW * 64, lds, s>>>(a);
   return hipGetLastError();
 }
 
