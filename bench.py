@@ -418,7 +418,7 @@ def main():
                   "executed": rate(sq.get("refit"), ph_ms["refit"]),
                   "fp64": round(census.fp64(rf) / (ph_ms["refit"] * 1e-3) / 1e12, 3),
                   "work": {k: rf[k] for k in WORK_KEYS}},
-        "network": {"kernel": "mlp_infer_kernel (fused 4-layer inference + decode)",
+        "network": {"kernel": "mlp_infer_resident_kernel (fused 4-layer inference + decode)",
                     "ms": round(ph_ms["network"], 4), "bound": "mfma", "unit": "TFLOP/s",
                     "peak": PEAK_BF16_TFLOPS,
                     "achieved": round(mlp_flop / (ph_ms["network"] * 1e-3) / 1e12, 3)},
