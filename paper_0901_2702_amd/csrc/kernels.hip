@@ -482,25 +482,10 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
         const unsigned long long pos =
             ((((k >> sh) << 3) + (unsigned long long)q) << sh) + (k & (ch - 1ull));
         pix = A.idx ? (int64_t)A.idx[pos] : (int64_t)pos;
-        const float* obs = A.stokes + pix * rows;
-        const float* Wp = A.W_pp ? A.W + pix * rows : A.W;
-        bool finite = true;
-        if constexpr (NOBS > 0) {
-#pragma unroll
-          for (int r = 0; r < 4 * NOBS; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
-        } else {
-          for (int r = 0; r < rows; ++r) finite = finite && isfinite(obs[r]) && isfinite(Wp[r]);
-        }
-        if (!finite) {
-          if (leader) {
-#pragma unroll
-            for (int q2 = 0; q2 < NPAR; ++q2) A.params[pix * NPAR + q2] = __builtin_nanf("");
-            A.chi2[pix] = __builtin_nan("");
-            A.iters[pix] = 0;
-            if (A.status) A.status[pix] = 3;
-            ++wc.pix;
-          }
-        } else {
+        // (the observations and weights are not read here: a non-finite one
+        // makes the first pass's chi^2 non-finite, and only then are they
+        // examined, so that a refill does not wait on their loads)
+        {
           double M0[NPAR];
           if (A.init) {
 #pragma unroll
@@ -548,7 +533,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
     const unsigned long long live_m = __ballot(live);
     if (live_m == 0ull) {
       if (__ballot(!exhausted) == 0ull) break;
-      continue;  // lanes that met non-finite input refill first
+      continue;  // (defensive: after a refill every lane is live or exhausted)
     }
     // ---- the wave's pass: with derivatives (fresh starts, accepted models
     // waiting for their Jacobian, and the other lanes' trials with their
@@ -570,9 +555,11 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
     // Sect. 4.4: a step from a model already near the minimum keeps H
     const bool keep_h = need_j ? kh_wait : (!fresh && chib < A.hess_reuse);
     double chi;
+    bool hess_counted = false;
     if (!SPLIT || jpass) {
       chi = lm_pass<NOBS, LPP, V>(A, Mc, pix, wait, chib, keep_h, sHG, sHa, lane, accept);
-      if (leader && accept && !keep_h) ++wc.hess;
+      hess_counted = leader && accept && !keep_h;
+      if (hess_counted) ++wc.hess;
     } else {
       chi = lm_pass_values<NOBS, LPP, V>(A, Mc, pix, lane);
       accept = isfinite(chi) && chi < chib;
@@ -580,6 +567,7 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
 
     // ---- Levenberg-Marquardt bookkeeping (Sect. 4.2, Table 2) -------------
     int done = -1;
+    bool bad_input = false;
     // the pass's model is a start or an accepted trial: the fit needs its
     // Jacobian unless it ends here
     const bool new_best = !need_j && (fresh || accept);
@@ -588,7 +576,20 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
       // now in LDS; its chi^2 is the one the trial pass found
       need_j = false;
     } else if (fresh) {
-      if (!isfinite(chi) && !restart_eval) done = 3;
+      if (!isfinite(chi) && !restart_eval) {
+        done = 3;
+        // a non-finite observation or weight, rather than a start whose
+        // synthesis is not finite: the pixel is not fitted at all (no
+        // model, no iterations) and its pass is not counted as work
+        const float* obs = A.stokes + pix * rows;
+        const float* Wp = A.W_pp ? A.W + pix * rows : A.W;
+        for (int r = 0; r < rows; ++r) bad_input = bad_input || !isfinite(obs[r]) || !isfinite(Wp[r]);
+        if (bad_input && leader) {
+          --wc.pass;
+          if (jpass) --wc.jpass;
+          if (hess_counted) --wc.hess;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < NPAR; ++q) Mb[q] = Mc[q];
       chib = chi;
@@ -656,11 +657,19 @@ __device__ __forceinline__ void lm_loop(const LMArgs& A, float* sHG, float4* sHa
 
     if (done >= 0) {
       if (leader) {
+        if (bad_input) {
 #pragma unroll
-        for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = PAPER ? Mg[q] : Mb[q];
-        A.chi2[pix] = PAPER ? chig : chib;
-        A.iters[pix] = it;
-        if (A.status) A.status[pix] = PAPER ? (done | (kr << 8)) : done;
+          for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = __builtin_nanf("");
+          A.chi2[pix] = __builtin_nan("");
+          A.iters[pix] = 0;
+          if (A.status) A.status[pix] = 3;
+        } else {
+#pragma unroll
+          for (int q = 0; q < NPAR; ++q) A.params[pix * NPAR + q] = PAPER ? Mg[q] : Mb[q];
+          A.chi2[pix] = PAPER ? chig : chib;
+          A.iters[pix] = it;
+          if (A.status) A.status[pix] = PAPER ? (done | (kr << 8)) : done;
+        }
         ++wc.pix;
       }
       live = false;
