@@ -155,7 +155,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--train-samples", type=int, default=10_000_000)
     ap.add_argument("--control-samples", type=int, default=250_000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=120,
+                    help="training epochs (cosine learning rate, best control epoch kept)")
+    ap.add_argument("--lr", type=float, default=4e-3, help="Adam's peak learning rate")
     ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
@@ -243,7 +245,7 @@ def main():
         t_data = time.perf_counter() - t0
         log("training data %.1f s" % t_data)
         net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
-                                   batch=4096, lr=2e-3, log=log)
+                                   batch=4096, lr=args.lr, log=log)
         del S_tr
         torch.cuda.empty_cache()
         if args.net:
@@ -402,6 +404,12 @@ def main():
     # rooflines of the learned step's launches: the short fit (the dominant
     # kernel), the re-fit, and the network (bf16 matrix cores)
     sf, rf = ph["short_fit"], ph["refit"]
+    # ... and taken on the same work: the network decides the trials of the
+    # short fit and which pixels are re-fitted
+    for key, c in (("short_fit", sf), ("refit", rf)):
+        w = sq.get(key + "_trials")
+        if w is None or abs(w - c["trials"]) > 0.01 * c["trials"]:
+            sq.pop(key, None)
     mlp_flop = n * MLP_FLOP_PER_PIXEL
     launches = {
         "short_fit": {"kernel": "lm_kernel<6> (learned start, <= %d trials)" % args.learned_max_iter,
@@ -901,7 +909,7 @@ def init_compare(args, ctx, inst, spec, log):
                                            wl.CONFIGS["learned_control"]["seed"], wl.draw_params,
                                            wl.draw_noise)
     net, tinfo = learned.train(ctx, inst, S_tr, P_tr, S_ct, P_ct, epochs=args.epochs,
-                               batch=4096, lr=2e-3, log=log)
+                               batch=4096, lr=args.lr, log=log)
     del S_tr
     torch.cuda.empty_cache()
     n = args.n

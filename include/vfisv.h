@@ -112,14 +112,16 @@ typedef struct {
                        /* results do not depend on grid_waves or chunk_log2 */
   int lanes_per_pixel; /* 1 (default) or 2: with 2, HMI-shaped pixels use a  */
                        /* pair of lanes each (half the synthesis points per */
-                       /* lane, ~1.8x faster passes) whenever the resident */
-                       /* grid can give every pixel two lanes (at most      */
-                       /* 32,768 pixels on MI355X: 1,024 waves of 64 lanes  */
-                       /* at one wave per SIMD); results then differ from   */
-                       /* the one-lane path by float32 rounding of the      */
-                       /* synthesis sums.                                   */
-                       /* The learned path's refit uses pairs when they fit; */
-                       /* vfisv_invert_batches keeps one lane per pixel.     */
+                       /* lane, ~1.7x faster passes) whenever the resident */
+                       /* grid can give every pixel two lanes, or all but   */
+                       /* at most a tenth of them, which wait for a free    */
+                       /* pair (at most 36,044 pixels on MI355X: 1,024      */
+                       /* waves of 64 lanes at one wave per SIMD); results  */
+                       /* then differ from the one-lane path by float32     */
+                       /* rounding of the synthesis sums, and do not depend */
+                       /* on the grid.  The learned path's refit uses pairs */
+                       /* by the same rule; vfisv_invert_batches keeps one  */
+                       /* lane per pixel.                                   */
   int voigt;           /* H and F (Sect. 3.2) by: 0 (default) Weideman's     */
                        /* 16-term rational series; 1 or 2 the Taylor table */
                        /* of Eqs. 10-13 (500 u x 100 a nodes at 0.05, built */

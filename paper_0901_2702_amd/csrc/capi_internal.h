@@ -102,9 +102,10 @@ int noalloc_scratch_setup(vfisv_ctx* ctx);
 // Enqueue the persistent LM kernel.  With idx != NULL the pixels are
 // idx[0 .. count), count read from n_dev on the device (n bounds the grid);
 // reset_all clears every work counter, otherwise only the queue heads.
-// lpp_max = 2 lets dense pixels use a pair of lanes each when the grid has
-// at least twice as many lanes as pixels (results then differ from the
-// one-lane path by float32 rounding of the synthesis sums).  may_alloc =
+// lpp_max = 2 lets dense pixels use a pair of lanes each when the resident
+// lanes give every pixel a pair, or at most a tenth of the pixels wait for
+// a free pair (results then differ from the one-lane path by float32
+// rounding of the synthesis sums).  may_alloc =
 // false: a whole banded batch is read in the API layout instead of through
 // the context's interleaved copy (same values, so the same results).
 int enqueue_lm(vfisv_ctx* ctx, const vfisv_instrument* inst, int64_t n,

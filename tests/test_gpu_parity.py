@@ -421,6 +421,39 @@ def test_lane_pairs_follow_the_oracle(ctx, hmi):
         vf.invert(ctx, inst, o, Wd, opts=vf.Options(lanes_per_pixel=3))
 
 
+def test_lane_pairs_waiting_for_a_free_pair(ctx, hmi):
+    """Pairs while at most a tenth of the pixels wait: on a 16-wave grid
+    (512 pairs) 560 pixels take pairs, 48 of them once an earlier pair has
+    finished, and every pixel's result equals the one it gets when all
+    pairs run at once (18 waves), bit for bit; 600 pixels (more than a
+    tenth waiting) take one lane each and equal the one-lane path."""
+    spec, inst, oi = hmi
+    P, obs = _observations(oi, spec, 600, 1100)
+    W = _dev(ctx, wl.weights(spec.n_obs))
+
+    def run(n, **kw):
+        out = vf.invert(ctx, inst, _dev(ctx, obs[:n]), W, opts=vf.Options(**kw))
+        return {k: v.cpu().numpy() for k, v in out.items()}, ctx.counters()
+
+    print("[gpu] pairs: all resident", flush=True)
+    ref, cref = run(560, lanes_per_pixel=2)
+    assert cref["grid_waves"] == 18
+    print("[gpu] pairs: 48 waiting", flush=True)
+    got, cgot = run(560, lanes_per_pixel=2, grid_waves=16)
+    assert cgot["grid_waves"] == 16
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    for k in ("pixels", "trials", "accepts", "passes", "hessians"):
+        assert cgot[k] == cref[k], k
+    one, _ = run(560)
+    assert np.mean(one["chi2"] != ref["chi2"]) > 0.5  # pairs did run
+    print("[gpu] pairs: 600 pixels on 16 waves", flush=True)
+    big, _ = run(600, lanes_per_pixel=2, grid_waves=16)
+    one, _ = run(600)
+    for k in one:
+        assert np.array_equal(big[k], one[k]), k
+
+
 @pytest.mark.parametrize("order", [1, 2])
 def test_taylor_table_follows_the_oracle(ctx, hmi, order):
     """Voigt by the Taylor table (Sect. 3.2, Eqs. 10-13): synthesis, start
