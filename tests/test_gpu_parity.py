@@ -219,7 +219,9 @@ def test_inversion_near_truth_same_minimum(ctx, hmi):
     rel = np.abs(gc - ref["chi2"]) / ref["chi2"]
     f1, f2 = np.mean(rel[at_min] < 1e-4), np.mean(rel[at_min] < 2e-2)
     print("[gpu] at minimum %d: chi2 within 1e-4 %.4f, within 2e-2 %.4f" % (at_min.sum(), f1, f2))
-    assert f1 > 0.94 and f2 > 0.99
+    # measured: 0.961 within 1e-4 and 0.9988 within 2e-2 of 863 pixels at the
+    # minimum (the GPU's per-pixel results do not depend on the schedule)
+    assert f1 > 0.955 and f2 > 0.998
     sig = np.array([_sigma(oi, ref["params"][k], W) for k in range(n)])
     d = np.abs(gp - ref["params"])
     d[:, 2] = np.minimum(d[:, 2], 180.0 - d[:, 2])
