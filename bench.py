@@ -160,7 +160,9 @@ def main():
     ap.add_argument("--lr", type=float, default=4e-3, help="Adam's peak learning rate")
     ap.add_argument("--learned-max-iter", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="pixels the oracle inverts for cpu_baseline (0: 65,536 for the "
+                         "learned line, 32,768 for the other workloads)")
     ap.add_argument("--net", default="",
                     help="network file: loaded when it exists (no training), else the trained "
                          "network is saved there (for profiling runs of the learned step)")
@@ -516,7 +518,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         from oracle import learned as olearned
-        m = min(args.cpu_sample, n)
+        m = min(args.cpu_sample or 65536, n)
         oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
         obs_cpu = (oracle.forward_batch(oi, P[:m]) + noise[:m]).astype(np.float32)
         stats = [net_stats[k] for k in range(4)]
@@ -676,7 +678,7 @@ def full_disk(args, ctx, inst, spec, log):
     }
     if not args.no_cpu_baseline:
         import oracle
-        m = min(args.cpu_sample, n)
+        m = min(args.cpu_sample or 32768, n)
         sel = np.linspace(0, n - 1, m).astype(np.int64)  # every (n/m)-th disk pixel
         oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
         obs_cpu = (oracle.forward_batch(oi, P[sel]) + noise[sel].astype(np.float64)) \
@@ -829,7 +831,7 @@ def parity(args, ctx, inst, spec, log):
     dev = ctx.device
     n = wl.CONFIGS["hmi_512x512"]["n"]
     seed = wl.CONFIGS["hmi_512x512"]["seed"]
-    m = min(args.cpu_sample, n)
+    m = min(args.cpu_sample or 32768, n)
     n_obs = spec.n_obs
     P = wl.draw_params(n, seed)
     oi = oracle.Instrument(spec.lambda0_A, spec.geff, spec.fine_offset_mA, spec.filter)
