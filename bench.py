@@ -172,14 +172,16 @@ def main():
     ap.add_argument("--plain-only", action="store_true",
                     help="time only plain LM on the held-out batch (no training); for profiling")
     ap.add_argument("--workload", choices=("learned", "full-disk", "fine-mixed", "parity",
-                                           "init-compare", "hess-reuse"),
+                                           "init-compare", "hess-reuse", "counter-calibration"),
                     default="learned",
                     help="learned: the learned-start vs plain LM line (default); full-disk: "
                          "plain LM over the 13.2M-pixel disk with clustered active regions; "
                          "fine-mixed: 1M fine-spectrum + 1M HMI pixels in one launch; "
                          "parity: per-parameter differences from the FP64 oracle on the "
                          "262,144-pixel HMI set; init-compare: default / classical / network "
-                         "starts; hess-reuse: plain LM with the Hessian kept near the minimum")
+                         "starts; hess-reuse: plain LM with the Hessian kept near the minimum; "
+                         "counter-calibration: elementwise float32 launches of known size, run "
+                         "under rocprofv3 --pmc to see how the SQ counters count instructions")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -215,6 +217,8 @@ def main():
         log("reference copy of %d MiB done" % args.copy_ref_mb)
         del src, dst
 
+    if args.workload == "counter-calibration":
+        return counter_calibration(args, ctx, log)
     if args.plain_only:
         return plain_only(args, ctx, inst, spec, log)
     if args.workload == "full-disk":
@@ -544,6 +548,34 @@ def main():
             "refit_rate": float(ref["refit"].mean()),
         }
     print(json.dumps(result), flush=True)
+
+
+def counter_calibration(args, ctx, log):
+    """Launches whose arithmetic is known, to see what one count of the SQ
+    counters stands for (run under `rocprofv3 --pmc SQ_INSTS_VALU_FMA_F32
+    SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F64 ...`):
+    d = b * c, d = b + c and d = a + b * c over 2^24 values, in float32 and in
+    float64, one operation per value each: 2^24 / 64 wave instructions
+    when each lane takes one value per instruction, half that when packed
+    instructions take two."""
+    import torch
+    dev = ctx.device
+    n = 1 << 24
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    for dt in (torch.float32, torch.float64):
+        a, b, c = (torch.rand(n, device=dev, generator=g, dtype=dt) for _ in range(3))
+        d = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(b, c, out=d)
+        torch.add(b, c, out=d)
+        torch.addcmul(a, b, c, out=d)
+        torch.cuda.synchronize()
+        del a, b, c, d
+    print(json.dumps({"mode": "counter-calibration", "values": n,
+                      "wave_instructions_at_one_value_per_lane": n // 64,
+                      "launches": ["mul", "add", "addcmul"],
+                      "dtypes": ["float32", "float64"]}), flush=True)
 
 
 def full_disk(args, ctx, inst, spec, log):
