@@ -535,7 +535,10 @@ __global__ __launch_bounds__(IW * 64) void mlp_infer_kernel(const MlpInferArgs a
 // keep their columns' weights of the two 256 x 256 layers in registers
 // (128 per lane) and walk the 64-row tiles, so the weights are read from L2 once per
 // workgroup instead of once per tile.  The tile and the per-element MFMA
-// sequence (same instruction, same k order) are those of mlp_infer_kernel;
+// sequence (same instruction, same k order) are those of mlp_infer_kernel,
+// with the hidden layers' operands swapped (the output transposed, so that
+// a lane's four results are consecutive columns of one row: one 8-byte LDS
+// write instead of four 2-byte ones; each element is the same dot product);
 // the hidden layers' GELU comes from a table (below), so an activation may
 // differ from mlp_infer_kernel's in its last bfloat16 bit where its value
 // lies within 6e-7 of a rounding midpoint.  Output layer: wave w takes rows
@@ -561,18 +564,26 @@ __device__ __forceinline__ void resident_hidden_epilogue(bf16* buf, const f32x4 
                                                          const float* __restrict__ bias,
                                                          const float2* __restrict__ tab, int wave,
                                                          int l) {
+  typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int cb = 0; cb < IW_CB; ++cb) {
+    const int col0 = wave * 16 * IW_CB + cb * 16 + (l >> 4) * 4;
+    const float4 b4 = *reinterpret_cast<const float4*>(bias + col0);
+    const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-    for (int cb = 0; cb < IW_CB; ++cb)
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = rb * 16 + (l & 15);
+      bf16x4 v;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = rb * 16 + (l >> 4) * 4 + j;
-        const int col = wave * 16 * IW_CB + cb * 16 + (l & 15);
-        buf[row * LDH + col] = (bf16)gelu_tab(tab, acc[rb][cb][j] + bias[col]);
-      }
+      for (int j = 0; j < 4; ++j) v[j] = (bf16)gelu_tab(tab, acc[rb][cb][j] + bb[j]);
+      *reinterpret_cast<bf16x4*>(buf + row * LDH + col0) = v;
+    }
+  }
 }
 
+// The layer as D^T = W X^T: the weights are the A operand and the tile's
+// rows the B operand, so that lane l receives four consecutive output
+// columns of one row and stores them with one 8-byte write.
 template <int NK>
 __device__ __forceinline__ void resident_hidden(bf16* buf, int ldin, const bf16x8 (&w)[NK][IW_CB],
                                                 const float* __restrict__ bias,
@@ -593,7 +604,7 @@ __device__ __forceinline__ void resident_hidden(bf16* buf, int ldin, const bf16x
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < IW_CB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rb], w[s][cb], acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][cb], av[rb], acc[rb][cb], 0, 0, 0);
   }
   __syncthreads();  // every wave has read the layer's inputs
   resident_hidden_epilogue(buf, acc, bias, tab, wave, l);
