@@ -12,8 +12,10 @@
 // Every GEMM is C = A . Bt^T with A [M][Kd] and Bt [N][Kd] both contiguous
 // along Kd, so each lane fetches its 8-element MFMA fragments with one
 // 16-byte load:  forward  X [B][K] . Wt [N][K]^T;  input gradient
-// dZ [B][N] . W [K][N]^T;  weight gradient dZ^T [N][B] . X^T [K][B]^T, split
-// along the batch into MLP_SPLITK partial sums that the Adam kernel adds.
+// dZ [B][N] . W [K][N]^T;  weight gradient X^T [K][B] . dZ^T [N][B]^T (in the
+// [in][out] order of the master weights, so that the Adam kernel reads it
+// coalesced), split along the batch into MLP_SPLITK partial sums that the
+// Adam kernel adds.
 #include <hip/hip_runtime.h>
 
 #include "me_device.h"
@@ -190,7 +192,7 @@ struct EpiBwdX {  // dz_prev = (dZ . W^T) * gelu'(z_prev)
   }
 };
 
-struct EpiDW {  // partial weight gradient, [split][out][in]
+struct EpiDW {  // partial weight gradient, [split][in][out]
   float* part;
   int64_t split_stride;
   int ldo;
@@ -305,7 +307,7 @@ __global__ void adam_kernel(const AdamArgs a) {
     n = (int)(e - (int64_t)k * a.out_dim[l]);
     g = 0.f;
     for (int s = 0; s < MLP_SPLITK; ++s)
-      g += a.part[l][(int64_t)s * a.split_stride[l] + (int64_t)n * a.in_dim[l] + k];
+      g += a.part[l][(int64_t)s * a.split_stride[l] + e];
     a.grad[i] = g;
   } else {
     g = a.grad[i];  // written by bias_grad_kernel
@@ -1010,10 +1012,10 @@ hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* t
     const int64_t stride = (int64_t)out * in;
     int64_t off = 0;
     for (int q = 0; q < l; ++q) off += (int64_t)L.in_dim[q] * L.out_dim[q] * MLP_SPLITK;
-    // weight gradient: dWt[out][in] = dZ^T[out][B] . X^T[in][B]^T
+    // weight gradient: dW[in][out] = X^T[in][B] . dZ^T[out][B]^T
     const bf16* Xt = l == 0 ? w.X0t : w.Yt[l - 1];
-    EpiDW ed{w.dW + off, stride, in};
-    e = gemm(w.dZt[l], w.cap, Xt, w.cap, out, in, M, MLP_SPLITK, ed, s);
+    EpiDW ed{w.dW + off, stride, out};
+    e = gemm(Xt, w.cap, w.dZt[l], w.cap, in, out, M, MLP_SPLITK, ed, s);
     if (e != hipSuccess) return e;
     bias_grad_kernel<<<out, 256, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
     e = hipGetLastError();
