@@ -260,11 +260,22 @@ __global__ void loss_grad_kernel(const float* __restrict__ Y4, const float* __re
 // column; the batch dimension is contiguous, so each thread reads 8 values
 // per load (M and cap are multiples of 32: 16-byte aligned rows), then a
 // wave reduction and one LDS step combine the 256 partial sums.
-__global__ __launch_bounds__(256) void bias_grad_kernel(const bf16* __restrict__ dZt, int64_t M,
-                                                        int64_t cap, float* grad_b) {
+// All four layers in one launch: block b takes column b - first[l] of the
+// layer l whose columns it falls in.
+struct BiasGradArgs {
+  const bf16* dZt[4];
+  float* grad_b[4];
+  int first[5];  // first block of each layer; first[4] = total columns
+};
+
+__global__ __launch_bounds__(256) void bias_grad_kernel(const BiasGradArgs a, int64_t M,
+                                                        int64_t cap) {
   __shared__ float red[4];
-  const int n = blockIdx.x;
-  const bf16* row = dZt + (int64_t)n * cap;
+  int l = 0;
+  while (l < 3 && (int)blockIdx.x >= a.first[l + 1]) ++l;
+  const int n = (int)blockIdx.x - a.first[l];
+  float* grad_b = a.grad_b[l];
+  const bf16* row = a.dZt[l] + (int64_t)n * cap;
   float s = 0.f;
   for (int64_t m = (int64_t)threadIdx.x * 8; m < M; m += 256 * 8) {
     const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + m);
@@ -1017,16 +1028,24 @@ hipError_t mlp_backward(const MlpDev& net, MlpWork& w, int64_t M, const float* t
     EpiDW ed{w.dW + off, stride, out};
     e = gemm(Xt, w.cap, w.dZt[l], w.cap, in, out, M, MLP_SPLITK, ed, s);
     if (e != hipSuccess) return e;
-    bias_grad_kernel<<<out, 256, 0, s>>>(w.dZt[l], M, w.cap, w.grad + L.ob[l]);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if (l > 0) {  // input gradient through W and the previous GELU
       EpiBwdX eb{w.Z[l - 1], w.dZ[l - 1], w.dZt[l - 1], MLP_H, w.cap};
       e = gemm(w.dZ[l], out, net.Wk[l], out, M, in, out, 1, eb, s);
       if (e != hipSuccess) return e;
     }
   }
-  return hipSuccess;
+  // bias gradients of every layer: column sums of dZ^T, one launch
+  BiasGradArgs bg;
+  int cols = 0;
+  for (int l = 0; l < 4; ++l) {
+    bg.dZt[l] = w.dZt[l];
+    bg.grad_b[l] = w.grad + L.ob[l];
+    bg.first[l] = cols;
+    cols += L.out_dim[l];
+  }
+  bg.first[4] = cols;
+  bias_grad_kernel<<<cols, 256, 0, s>>>(bg, M, w.cap);
+  return hipGetLastError();
 }
 
 hipError_t mlp_adam(const MlpDev& net, const MlpWork& w, float lr, float beta1, float beta2,
