@@ -155,8 +155,9 @@ __device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C,
                                          float& F) {
   const float D = fmaf(u, u, p.denr2);
   const float rD = frcp(D);
+  const float idr = p.denr * rD, idi = u * rD;  // 1/den
   const float Zr = fmaf(-u, u, p.c0) * rD;
-  const float Zi = C.w2L * u * rD;
+  const float Zi = C.w2L * idi;
   const float r = 2.f * Zr;
   const float s = fmaf(Zr, Zr, Zi * Zi);
   // c_k = wc[k + 1]
@@ -170,7 +171,6 @@ __device__ __forceinline__ void faddeeva(float u, const Pix& p, const Consts& C,
   }
   const float pr = fmaf(b1, Zr, fmaf(-s, b2, C.wc[1]));
   const float pi = b1 * Zi;
-  const float idr = p.denr * rD, idi = u * rD;  // 1/den
   const float qr = fmaf(pr, idr, fmaf(-pi, idi, INV_SQRT_PI));
   const float qi = fmaf(pr, idi, pi * idr);
   H = fmaf(idr, qr, -idi * qi);
@@ -282,48 +282,51 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
   const float alb = fmaf(p.twoa, Hb, fmaf(2.f * ub, Fb, m2sp)), beb = fmaf(p.twoa, Fb, -2.f * ub * Hb);
   const float alr = fmaf(p.twoa, Hr, fmaf(2.f * ur, Fr, m2sp)), ber = fmaf(p.twoa, Fr, -2.f * ur * Hr);
 
-  // d Delta / d(eta_I, eta_Q, eta_V, rho_Q, rho_V)
-  const float dDI = 2.f * eI * (T + eI2);
-  const float dDQ = -2.f * NQ, dDV = -2.f * NV;
-  const float dDq = 2.f * fmaf(eI2, rQ, -Pi * eQ);
-  const float dDw = 2.f * fmaf(eI2, rV, -Pi * eV);
+  // the central component's profile tangents times its element factor
+  // eta0 sin^2(gamma) / 2, which every output's sensitivity to Hp and Fp carries
+  const float alpS = p.hs2 * alp, bepS = p.hs2 * bep;
+
+  // d Delta / d(eta_I, eta_Q, eta_V, rho_Q, rho_V), divided by Delta; the
+  // eta_Q and eta_V ones are -2 N_Q and -2 N_V, i.e. 2 Q and 2 V after division
+  const float eIr = eI * rDel, eIr2 = eIr + eIr, rQr = rQ * rDel, rVr = rV * rDel,
+              Pir = Pi * rDel, eI2r = eI2 * rDel;
+  const float DI = eIr2 * (T + eI2);
+  const float DQ = Qh + Qh, DV = Vh + Vh;
+  const float Dq = 2.f * fmaf(eI2, rQr, -Pir * eQ);
+  const float Dw = 2.f * fmaf(eI2, rVr, -Pir * eV);
 
   // element tangents for gamma (per radian) and eta0
   const float gI = p.hsin2g * dHl, gV = -p.hsg * dHv, gq = p.hsin2g * dFl, gw = -p.hsg * dFv;
   const float nI = fmaf(p.s2h, dHl, sH), nQ = p.s2h * dHl, nV = p.cgh * dHv, nq = p.s2h * dFl,
               nw = p.cgh * dFv;
 
-  // G[X][e] = d(output X)/d(element e), X = N_X/Delta with sign
+  // G[X][e] = d(output X)/d(element e), X = N_X/Delta with sign; the
+  // I_mix row carries alpha
   float G[4][5];
   {
-    const float a0 = fmaf(3.f, eI2, R2), a3 = 2.f * eI * rQ, a4 = 2.f * eI * rV;
-    G[0][0] = fmaf(-Im, dDI, a0) * rDel;
-    G[0][1] = -Im * dDQ * rDel;
-    G[0][2] = -Im * dDV * rDel;
-    G[0][3] = fmaf(-Im, dDq, a3) * rDel;
-    G[0][4] = fmaf(-Im, dDw, a4) * rDel;
+    const float ra = rDel * p.alpha, Ima = Im * p.alpha, eIr2a = eIr2 * p.alpha;
+    G[0][0] = fmaf(-Ima, DI, fmaf(3.f, eI2, R2) * ra);
+    G[0][1] = -Ima * DQ;
+    G[0][2] = -Ima * DV;
+    G[0][3] = fmaf(-Ima, Dq, eIr2a * rQ);
+    G[0][4] = fmaf(-Ima, Dw, eIr2a * rV);
   }
-  {
-    G[1][0] = -fmaf(Qh, dDI, 2.f * eI * eQ) * rDel;
-    G[1][1] = -fmaf(Qh, dDQ, fmaf(rQ, rQ, eI2)) * rDel;
-    G[1][2] = -fmaf(Qh, dDV, rQ * rV) * rDel;
-    G[1][3] = -fmaf(Qh, dDq, fmaf(rQ, eQ, Pi)) * rDel;
-    G[1][4] = -fmaf(Qh, dDw, rQ * eV) * rDel;
-  }
-  {
-    G[2][0] = -fmaf(Uh, dDI, fmaf(eQ, rV, -eV * rQ)) * rDel;
-    G[2][1] = -fmaf(Uh, dDQ, eI * rV) * rDel;
-    G[2][2] = -fmaf(Uh, dDV, -eI * rQ) * rDel;
-    G[2][3] = -fmaf(Uh, dDq, -eI * eV) * rDel;
-    G[2][4] = -fmaf(Uh, dDw, eI * eQ) * rDel;
-  }
-  {
-    G[3][0] = -fmaf(Vh, dDI, 2.f * eI * eV) * rDel;
-    G[3][1] = -fmaf(Vh, dDQ, rV * rQ) * rDel;
-    G[3][2] = -fmaf(Vh, dDV, fmaf(rV, rV, eI2)) * rDel;
-    G[3][3] = -fmaf(Vh, dDq, rV * eQ) * rDel;
-    G[3][4] = -fmaf(Vh, dDw, fmaf(rV, eV, Pi)) * rDel;
-  }
+  const float qv = rQr * rV;
+  G[1][0] = -fmaf(Qh, DI, eIr2 * eQ);
+  G[1][1] = -fmaf(Qh, DQ, fmaf(rQr, rQ, eI2r));
+  G[1][2] = -fmaf(Qh, DV, qv);
+  G[1][3] = -fmaf(Qh, Dq, fmaf(rQr, eQ, Pir));
+  G[1][4] = -fmaf(Qh, Dw, rQr * eV);
+  G[2][0] = -fmaf(Uh, DI, fmaf(eQ, rV, -eV * rQ) * rDel);
+  G[2][1] = -fmaf(Uh, DQ, eIr * rV);
+  G[2][2] = -fmaf(Uh, DV, -eIr * rQ);
+  G[2][3] = -fmaf(Uh, Dq, -eIr * eV);
+  G[2][4] = -fmaf(Uh, Dw, eIr * eQ);
+  G[3][0] = -fmaf(Vh, DI, eIr2 * eV);
+  G[3][1] = -fmaf(Vh, DQ, qv);
+  G[3][2] = -fmaf(Vh, DV, fmaf(rVr, rV, eI2r));
+  G[3][3] = -fmaf(Vh, Dq, rVr * eQ);
+  G[3][4] = -fmaf(Vh, Dw, fmaf(rVr, eV, Pir));
   // field-free component: dI0/dHp = -eta0 I0^2, dI0/deta0 = -Hp I0^2
   const float k0 = -p.eta0 * I0 * I0 * p.oma;
   const float d0v = k0 * bep, d0D = k0 * bep * up, d0a = k0 * alp;
@@ -331,25 +334,22 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
 
 #pragma unroll
   for (int X = 0; X < 4; ++X) {
-    const float sc = (X == 0) ? p.alpha : 1.f;  // I_mix carries alpha
-    const float GI = G[X][0] * sc, GQ = G[X][1] * sc, GV = G[X][2] * sc, Gq = G[X][3] * sc,
-                Gw = G[X][4] * sc;
-    // sensitivities to the six profile values
+    const float GI = G[X][0], GQ = G[X][1], GV = G[X][2], Gq = G[X][3], Gw = G[X][4];
+    // sensitivities to the six profile values (central: SH_p = hs2 GIQ,
+    // SF_p = hs2 Gq, the factor hs2 carried by alpS and bepS)
     const float GIQ = GI + GQ;
-    const float SHp = p.hs2 * GIQ;
     const float x1 = fmaf(p.hI, GI, -p.hq * GQ), x2 = p.hc * GV;
     const float SHb = x1 - x2, SHr = x1 + x2;
-    const float SFp = p.hs2 * Gq;
     const float y1 = -p.hq * Gq, y2 = p.hc * Gw;
     const float SFb = y1 - y2, SFr = y1 + y2;
     // u-tangent weights t_c = SH_c beta_c - SF_c alpha_c
-    const float tp = fmaf(SHp, bep, -SFp * alp);
+    const float tp = fmaf(GIQ, bepS, -Gq * alpS);
     const float tb = fmaf(SHb, beb, -SFb * alb);
     const float tr = fmaf(SHr, ber, -SFr * alr);
     float dB = tb - tr;
     float dv = tp + tb + tr;
     float dD = fmaf(up, tp, fmaf(ub, tb, ur * tr));
-    float da = fmaf(SHp, alp, fmaf(SFp, bep, fmaf(SHb, alb, fmaf(SFb, beb, fmaf(SHr, alr, SFr * ber)))));
+    float da = fmaf(GIQ, alpS, fmaf(Gq, bepS, fmaf(SHb, alb, fmaf(SFb, beb, fmaf(SHr, alr, SFr * ber)))));
     const float dg = fmaf(GIQ, gI, fmaf(GV, gV, fmaf(Gq, gq, Gw * gw)));
     float de = fmaf(GI, nI, fmaf(GQ, nQ, fmaf(GV, nV, fmaf(Gq, nq, Gw * nw))));
     if (X == 0) {

@@ -276,22 +276,29 @@ def test_default_start_statistics(ctx, hmi):
     """Plain LM from the default model: GPU and oracle reach statistically
     the same fits (individual trajectories may split on float32 rounding)."""
     spec, inst, oi = hmi
-    n = 1024
+    n = 4096
     P, obs = _observations(oi, spec, n, 1000)
     W = wl.weights(spec.n_obs)
     out = vf.invert(ctx, inst, _dev(ctx, obs), _dev(ctx, W))
     ref = oracle.invert(oi, obs, W)
     gc = out["chi2"].cpu().numpy()
     gi = out["iters"].cpu().numpy()
-    # the chi^2 distribution has a steep tail of failed fits above its 60th
-    # percentile; compare the median, the share of fits at the noise level
-    # and the work
+    # About half of the trajectories split on float32 rounding, and a split
+    # fit ends higher or lower than the oracle's alike (measured 22-24% each
+    # way): no side may end higher more often than the other.  The chi^2
+    # distribution rises steeply between its 45th and 60th percentiles
+    # (1.3 -> 2.2), so the median moves by several percent when a dozen
+    # split fits change sides; 4,096 pixels keep that within the 5% bar.
+    # Also compared: the share of fits at the noise level and the work.
+    rel = (gc - ref["chi2"]) / ref["chi2"]
+    higher, lower = np.mean(rel > 1e-4), np.mean(rel < -1e-4)
+    print("[gpu] split fits: GPU higher %.3f, lower %.3f" % (higher, lower), flush=True)
+    assert abs(higher - lower) < 0.05, (higher, lower)
     a, b = np.median(gc), np.median(ref["chi2"])
     assert abs(a - b) / b < 0.05, (a, b)
     assert abs(np.mean(gc < 2.0) - np.mean(ref["chi2"] < 2.0)) < 0.05
     assert abs(gi.mean() - ref["iters"].mean()) / ref["iters"].mean() < 0.1
-    agree = np.abs(gc - ref["chi2"]) / ref["chi2"] < 1e-4
-    assert agree.mean() > 0.4
+    assert 1.0 - higher - lower > 0.4
 
 
 def test_edge_cases(ctx, hmi):
