@@ -100,7 +100,7 @@ __device__ __forceinline__ T load_uniform(const T* p, int i) {
 
 // Per-pixel quantities of one synthesis pass.
 struct Pix {
-  float vsi, invD, zs, a, twoa, denr, denr2, c0;
+  float vsi, invD, zs, a, denr, denr2, c0;
   float hs2, hc, hI, hq, hsin2g, hsg, s2h, cgh;
   float eta0, alpha, oma;
   int ja;          // Taylor table: damping node of this pixel
@@ -114,7 +114,6 @@ __device__ __forceinline__ void pix_setup(const float* M, const Consts& C, Pix& 
   p.vsi = C.lam_over_c * v * p.invD;
   p.zs = C.cz * B * p.invD;
   p.a = a;
-  p.twoa = 2.f * a;
   p.denr = C.wL + a;
   p.denr2 = p.denr * p.denr;
   p.c0 = C.wL2 - a * a;
@@ -239,7 +238,8 @@ __device__ __forceinline__ void voigt_hf(float u, const Pix& p, const Consts& C,
 //   c[2] Q0, c[3] U0, c[4] V,
 //   c[5 + 4q + X], q in {B, gamma, v, Doppler width, a, eta0},
 //   X in {I_mix, Q0, U0, V}: derivatives up to per-pixel factors
-//   (B: C_Z/DlD, gamma: 1 per radian, v: -(lambda0/c)/DlD, DlD: -1/DlD).
+//   (B: 2 C_Z/DlD, gamma: 1 per radian, v: -2 (lambda0/c)/DlD, DlD: -2/DlD,
+//   a: 2, eta0: 1; the factors 2 of Eqs. 8-9 are left to them).
 template <bool DERIV, int V = 0>
 __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Consts& C,
                                               float* c) {
@@ -251,7 +251,7 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
   voigt_hf<V>(ur, p, C, Hr, Fr);
 
   const float sH = 0.5f * (Hb + Hr), dHl = Hp - sH, dHv = Hr - Hb;
-  const float sF = 0.5f * (Fb + Fr), dFl = Fp - sF, dFv = Fr - Fb;
+  const float dFl = fmaf(-0.5f, Fb + Fr, Fp), dFv = Fr - Fb;
   // absorption-matrix elements, psi = 0 frame
   const float eI = fmaf(p.eta0, sH, fmaf(p.hs2, dHl, 1.f));
   const float eQ = p.hs2 * dHl, eV = p.hc * dHv;
@@ -276,11 +276,17 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
   c[4] = Vh;
   if (!DERIV) return;
 
-  // Eqs. 8-9
-  const float m2sp = -TWO_OVER_SQRT_PI;
-  const float alp = fmaf(p.twoa, Hp, fmaf(2.f * up, Fp, m2sp)), bep = fmaf(p.twoa, Fp, -2.f * up * Hp);
-  const float alb = fmaf(p.twoa, Hb, fmaf(2.f * ub, Fb, m2sp)), beb = fmaf(p.twoa, Fb, -2.f * ub * Hb);
-  const float alr = fmaf(p.twoa, Hr, fmaf(2.f * ur, Fr, m2sp)), ber = fmaf(p.twoa, Fr, -2.f * ur * Hr);
+  // Eqs. 8-9, halved: al = a H + u F - 1/sqrt(pi) = (dH/da) / 2,
+  // be = a F - u H = (dF/da) / 2, and dH/du = -dF/da, dF/du = dH/da.  Every
+  // tangent below that carries them (B, v, Doppler width, damping) is half
+  // its value; the factor 2 is applied with the per-parameter factors after
+  // filtering (row_factors, assemble_sample).
+  const float alp = fmaf(p.a, Hp, fmaf(up, Fp, -INV_SQRT_PI)), bep = fmaf(p.a, Fp, -up * Hp);
+  const float alb = fmaf(p.a, Hb, fmaf(ub, Fb, -INV_SQRT_PI)), beb = fmaf(p.a, Fb, -ub * Hb);
+  const float alr = fmaf(p.a, Hr, fmaf(ur, Fr, -INV_SQRT_PI)), ber = fmaf(p.a, Fr, -ur * Hr);
+  // the sigma components enter through their sums and differences (below)
+  const float Sbe = beb + ber, Dbe = beb - ber, Sal = alb + alr, Dal = alb - alr;
+  const float cSbe = p.hc * Sbe, cDbe = p.hc * Dbe, cSal = p.hc * Sal, cDal = p.hc * Dal;
 
   // the central component's profile tangents times its element factor
   // eta0 sin^2(gamma) / 2, which every output's sensitivity to Hp and Fp carries
@@ -328,36 +334,36 @@ __device__ __forceinline__ void point_contrib(float dl, const Pix& p, const Cons
   G[3][3] = -fmaf(Vh, Dq, rVr * eQ);
   G[3][4] = -fmaf(Vh, Dw, fmaf(rVr, eV, Pir));
   // field-free component: dI0/dHp = -eta0 I0^2, dI0/deta0 = -Hp I0^2
-  const float k0 = -p.eta0 * I0 * I0 * p.oma;
-  const float d0v = k0 * bep, d0D = k0 * bep * up, d0a = k0 * alp;
-  const float d0e = -Hp * I0 * I0 * p.oma;
+  const float I02o = I0 * I0 * p.oma, k0 = -p.eta0 * I02o;
+  const float d0v = k0 * bep, d0a = k0 * alp;
+  const float d0e = -Hp * I02o;
 
 #pragma unroll
   for (int X = 0; X < 4; ++X) {
     const float GI = G[X][0], GQ = G[X][1], GV = G[X][2], Gq = G[X][3], Gw = G[X][4];
-    // sensitivities to the six profile values (central: SH_p = hs2 GIQ,
-    // SF_p = hs2 Gq, the factor hs2 carried by alpS and bepS)
+    // sensitivities to the six profile values: SH_p = hs2 GIQ, SF_p = hs2 Gq
+    // (hs2 carried by alpS and bepS), SH_b,r = x1 -/+ hc GV,
+    // SF_b,r = y1 -/+ hc Gw (hc carried by the c* sums and differences)
     const float GIQ = GI + GQ;
-    const float x1 = fmaf(p.hI, GI, -p.hq * GQ), x2 = p.hc * GV;
-    const float SHb = x1 - x2, SHr = x1 + x2;
-    const float y1 = -p.hq * Gq, y2 = p.hc * Gw;
-    const float SFb = y1 - y2, SFr = y1 + y2;
-    // u-tangent weights t_c = SH_c beta_c - SF_c alpha_c
+    const float x1 = fmaf(p.hI, GI, -p.hq * GQ);
+    const float y1 = -p.hq * Gq;
+    // u-tangent weights t_c = SH_c be_c - SF_c al_c: the central one, and
+    // the sum and difference of the sigma ones
     const float tp = fmaf(GIQ, bepS, -Gq * alpS);
-    const float tb = fmaf(SHb, beb, -SFb * alb);
-    const float tr = fmaf(SHr, ber, -SFr * alr);
-    float dB = tb - tr;
-    float dv = tp + tb + tr;
-    float dD = fmaf(up, tp, fmaf(ub, tb, ur * tr));
-    float da = fmaf(GIQ, alpS, fmaf(Gq, bepS, fmaf(SHb, alb, fmaf(SFb, beb, fmaf(SHr, alr, SFr * ber)))));
+    const float tbr = fmaf(x1, Sbe, fmaf(-GV, cDbe, fmaf(-y1, Sal, Gw * cDal)));
+    const float dB = fmaf(x1, Dbe, fmaf(-GV, cSbe, fmaf(-y1, Dal, Gw * cSal)));
+    float dv = tp + tbr;
+    // damping: sum over components of SH_c al_c + SF_c be_c
+    float da = fmaf(GIQ, alpS, fmaf(Gq, bepS, fmaf(x1, Sal, fmaf(-GV, cDal, fmaf(y1, Sbe, -Gw * cDbe)))));
     const float dg = fmaf(GIQ, gI, fmaf(GV, gV, fmaf(Gq, gq, Gw * gw)));
     float de = fmaf(GI, nI, fmaf(GQ, nQ, fmaf(GV, nV, fmaf(Gq, nq, Gw * nw))));
     if (X == 0) {
       dv += d0v;
-      dD += d0D;
       da += d0a;
       de += d0e;
     }
+    // Doppler width: sum over components of u_c t_c, with u_b,r = u_p +/- zs
+    const float dD = fmaf(up, dv, p.zs * dB);
     c[5 + 0 + X] = dB;
     c[5 + 4 + X] = dg;
     c[5 + 8 + X] = dv;
@@ -625,10 +631,12 @@ __device__ __forceinline__ void row_factors(const float* M, const Pix& p, const 
   f.alpha = M[9];
   f.S1a = f.S1 * f.alpha;
   sincosf(2.f * M[2] * DEG, &f.s2p, &f.c2p);
-  f.fB = C.cz * p.invD;
+  // B, v and Doppler width: twice the factor, since their accumulated
+  // tangents are half-values (point_contrib)
+  f.fB = 2.f * C.cz * p.invD;
   f.fg = DEG;
-  f.fv = -C.lam_over_c * p.invD;
-  f.fD = -p.invD;
+  f.fv = -2.f * C.lam_over_c * p.invD;
+  f.fD = -2.f * p.invD;
 }
 
 // Stokes values (I, Q, U, V) of observed sample i and, with DERIV, the four
@@ -643,7 +651,7 @@ __device__ __forceinline__ void assemble_sample(const float* acc, float row_sum,
   S[2] = fmaf(f.s2p, Q0, f.c2p * U0);
   S[3] = f.S1a * acc[4];
   if (!DERIV) return;
-  const float qf[6] = {f.fB, f.fg, f.fv, f.fD, 1.f, 1.f};
+  const float qf[6] = {f.fB, f.fg, f.fv, f.fD, 2.f, 1.f};  // damping: half-values too
   const int qidx[6] = {0, 1, 3, 4, 5, 6};
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
